@@ -1,0 +1,344 @@
+"""Pins for the FP64 oracle: each test checks it against something the paper
+or plain mathematics fixes (closed forms, hand-worked geometry, brute force
+on integer data, special cases of the search, an independent library's
+number formats), never against a retyped copy of its own formula."""
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+
+import datagen
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def unit2(deg):
+    r = math.radians(deg)
+    return [math.cos(r), math.sin(r)]
+
+
+# --------------------------------------------------------------------------
+# distance (Def. 1, inner product)
+# --------------------------------------------------------------------------
+def test_dist_integer_exact(oracle_lib):
+    rng = np.random.default_rng(1)
+    for d in (1, 3, 64, 200):
+        a = rng.integers(-50, 50, size=d)
+        b = rng.integers(-50, 50, size=d)
+        exact = -sum(int(x) * int(y) for x, y in zip(a, b))
+        assert oracle_lib.dist(a, b) == float(exact)
+
+
+def test_dist_selects_index(oracle_lib):
+    # a one-hot vector picks exactly coordinate i of the other operand
+    b = np.arange(1, 17, dtype=np.float32)
+    for i in range(16):
+        a = np.zeros(16, np.float32)
+        a[i] = 1
+        assert oracle_lib.dist(a, b) == -(i + 1)
+
+
+def test_dist_self_and_orthogonal(oracle_lib):
+    x = np.array([3, 4], np.float32)
+    assert oracle_lib.dist(x, x) == -25.0
+    assert oracle_lib.dist([1, 0], [0, 7]) == 0.0
+
+
+def test_dist_sums_in_increasing_index_order(oracle_lib):
+    # 2^53 + 1 rounds back to 2^53 in double; summed left to right the 1 is
+    # lost (-> 0), summed right to left it survives (-> -1).
+    a = np.array([2.0 ** 53, 1.0, -(2.0 ** 53)], np.float32)
+    assert oracle_lib.dist(a, np.ones(3, np.float32)) == 0.0
+    assert oracle_lib.dist(a[::-1].copy(), np.ones(3, np.float32)) == -1.0
+
+
+# --------------------------------------------------------------------------
+# exact kNN (Def. 1), ties by id
+# --------------------------------------------------------------------------
+def test_knn_matches_sort_on_integer_data(oracle_lib):
+    rng = np.random.default_rng(2)
+    X = rng.integers(-3, 4, size=(300, 5)).astype(np.float32)
+    Q = rng.integers(-3, 4, size=(40, 5)).astype(np.float32)
+    ids, ds = oracle_lib.knn(X, Q, 17)
+    S = -(Q.astype(np.int64) @ X.astype(np.int64).T)  # exact integer distances
+    for q in range(len(Q)):
+        order = np.lexsort((np.arange(len(X)), S[q]))[:17]  # by distance, then id
+        assert list(ids[q]) == list(order)
+        assert list(ds[q]) == list(S[q][order].astype(float))
+
+
+def test_knn_k_equals_n_and_padding(oracle_lib):
+    X = np.array([[1, 0], [0, 1], [1, 1]], np.float32)
+    ids, ds = oracle_lib.knn(X, np.array([[2, 1]], np.float32), 5)
+    assert list(ids[0][:3]) == [2, 0, 1]
+    assert list(ds[0][:3]) == [-3.0, -2.0, -1.0]
+    assert ids[0][3] == oracle_lib.NONE and math.isinf(ds[0][4])
+
+
+# --------------------------------------------------------------------------
+# medoid reading: nearest (L2) to the mean, lower id on ties
+# --------------------------------------------------------------------------
+def test_medoid(oracle_lib):
+    assert oracle_lib.medoid(np.array([[0], [1], [2], [10]], np.float32)) == 2  # mean 3.25
+    assert oracle_lib.medoid(np.array([[0], [2]], np.float32)) == 0  # tie -> lower id
+    assert oracle_lib.medoid(np.array([[5, 5]], np.float32)) == 0
+
+
+# --------------------------------------------------------------------------
+# AcquireNeighbors (Algorithm 3) on hand geometry
+# --------------------------------------------------------------------------
+def test_acquire_fan_both_sides(oracle_lib):
+    # x at 0 deg; candidates at +30, -35, +40, +100 deg on the unit circle.
+    # Under -IP, c is kept iff angle(x,c) < angle(c,p) for every kept p.
+    X = np.array([unit2(a) for a in (0, 30, -35, 40, 100)], np.float32)
+    C = [4, 3, 2, 1, 1, 0]  # shuffled, with a duplicate and x itself
+    assert list(oracle_lib.acquire(X, 0, C, 4, 0)) == [1, 2]      # 40 occluded by 30, 100 by 30
+    assert list(oracle_lib.acquire(X, 0, C, 3, 1)) == [1, 2, 3]   # fill in rank order
+    assert list(oracle_lib.acquire(X, 0, C, 4, 1)) == [1, 2, 3, 4]
+    assert list(oracle_lib.acquire(X, 0, C, 1, 1)) == [1]
+    assert list(oracle_lib.acquire(X, 0, [], 3, 1)) == []
+
+
+def test_acquire_pivot_xyz_example(oracle_lib):
+    # Sec. 4.2.3: pivot P; X is kept; Y is closer to X than to P and is
+    # skipped; Z is kept; with degree limit 3 the fill brings Y back.
+    P, Xn, Y, Z = unit2(0), unit2(20), unit2(35), unit2(-40)
+    X = np.array([P, Xn, Y, Z], np.float32)
+    assert list(oracle_lib.acquire(X, 0, [1, 2, 3], 3, 0)) == [1, 3]
+    assert list(oracle_lib.acquire(X, 0, [1, 2, 3], 3, 1)) == [1, 3, 2]
+    assert list(oracle_lib.acquire(X, 0, [1, 2, 3], 2, 1)) == [1, 3]
+
+
+def test_acquire_collinear_inner_product(oracle_lib):
+    # 1-D, delta(a,b) = -ab.  x = 1; candidates 3, 2, -1: 3 first; 2 fails
+    # (-2 < -6 false); -1 passes (1 < 3).
+    X = np.array([[1], [3], [2], [-1]], np.float32)
+    assert list(oracle_lib.acquire(X, 0, [2, 3, 1], 5, 0)) == [1, 3]
+
+
+def test_acquire_strict_rule_ties_exclude(oracle_lib):
+    # delta(x,c) == delta(c,p) must exclude c (strict <)
+    X = np.array([[1, 0], [1, 0], [1, 0]], np.float32)  # all identical vectors
+    assert list(oracle_lib.acquire(X, 0, [1, 2], 3, 0)) == [1]
+
+
+# --------------------------------------------------------------------------
+# hand-worked construction
+# --------------------------------------------------------------------------
+def test_build_hand_worked_five_points(oracle_lib):
+    g = json.load(open(os.path.join(GOLDEN, "projection_5pt.json")))
+    X = np.array([unit2(a) for a in g["base_angles_deg"]], np.float32)
+    T = np.array([unit2(a) for a in g["train_angles_deg"]], np.float32)
+    G = oracle_lib.Graph(X, T, g["Nq"], g["M"], g["L"])
+    assert [sorted(r.tolist()) for r in G.rows("pj")] == [sorted(r) for r in g["pj_rows"]]
+    assert [sorted(r.tolist()) for r in G.rows("ce")] == [sorted(r) for r in g["ce_rows"]]
+    assert [r.tolist() for r in G.rows("final")] == g["final_rows"]
+    assert G.entry == g["entry"]
+    assert G.repairs == g["repairs"]
+    assert list(G.pivot) == [0, 3]
+
+
+# --------------------------------------------------------------------------
+# construction invariants on the tiny OOD workload law
+# --------------------------------------------------------------------------
+@pytest.fixture(scope="module")
+def small_graph(oracle_lib):
+    gen = datagen.Generator(1, n=1500, n_train=1500, n_test=200)
+    X, T, Q = gen.base(), gen.train(), gen.test()
+    G = oracle_lib.Graph(X, T, 16, 16, 120)
+    return X, T, Q, G
+
+
+def _bfs(off, idx, start, n):
+    seen = np.zeros(n, bool)
+    seen[start] = True
+    st = [start]
+    while st:
+        v = st.pop()
+        for u in idx[off[v]:off[v + 1]]:
+            if not seen[u]:
+                seen[u] = True
+                st.append(int(u))
+    return seen
+
+
+def test_bipartite_invariants(oracle_lib, small_graph):
+    X, T, Q, G = small_graph
+    ids, _ = oracle_lib.knn(X, T, G.Nq)
+    assert (G.pivot == ids[:, 0]).all()                       # pivot = nearest base row
+    assert (G.nout == ids[:, 1:]).all()                       # N_out minus the pivot
+    assert G.b_offsets[-1] == len(T)                          # sum |B(x)| = |T|
+    for x in range(G.n):
+        ts = G.b_indices[G.b_offsets[x]:G.b_offsets[x + 1]]
+        assert (G.pivot[ts] == x).all() and (np.diff(ts.astype(np.int64)) > 0).all()
+
+
+def test_graph_invariants(oracle_lib, small_graph):
+    X, T, Q, G = small_graph
+    m_pj, m_ce = G.M // 2, (G.M - 1) // 2
+    pj, ce, fin = G.rows("pj"), G.rows("ce"), G.rows("final")
+    for x in range(G.n):
+        assert len(pj[x]) <= m_pj and len(ce[x]) <= m_ce and len(fin[x]) <= G.M
+        for r in (pj[x], ce[x], fin[x]):
+            assert x not in r and len(set(r.tolist())) == len(r)
+        assert set(pj[x].tolist()) <= set(fin[x].tolist())
+        assert (np.diff(fin[x].astype(np.int64)) > 0).all()
+    assert _bfs(G.offsets, G.indices, G.entry, G.n).all()      # every node reachable
+    assert len(pj[G.entry]) > 0
+    # projection leaves nodes without out-edges, enhancement + repair fix them
+    assert sum(len(r) == 0 for r in pj) > 0
+    assert all(len(r) > 0 for r in fin)
+
+
+def test_build_rejects_bad_args(oracle_lib):
+    X = np.zeros((4, 2), np.float32)
+    with pytest.raises(ValueError):
+        oracle_lib.Graph(X, X, 1, 8)   # Nq < 2
+    with pytest.raises(ValueError):
+        oracle_lib.Graph(X, X, 3, 2)   # M < 3
+
+
+# --------------------------------------------------------------------------
+# beam search (Sec. 4.3): special cases
+# --------------------------------------------------------------------------
+def _complete(n):
+    rows = [[j for j in range(n) if j != i] for i in range(n)]
+    off = np.zeros(n + 1, np.int64)
+    off[1:] = np.cumsum([len(r) for r in rows])
+    return off, np.array(sum(rows, []), np.uint32)
+
+
+def test_search_complete_graph_is_exact(oracle_lib):
+    rng = np.random.default_rng(3)
+    X = rng.standard_normal((60, 8)).astype(np.float32)
+    Q = rng.standard_normal((25, 8)).astype(np.float32)
+    off, idx = _complete(60)
+    gt, gd = oracle_lib.knn(X, Q, 10)
+    for L in (10, 11, 30):
+        ids, ds, hops, ev, _ = oracle_lib.search(X, off, idx, 7, Q, 10, L)
+        assert (ids == gt).all() and (ds == gd).all()
+        assert (ev == 60).all()
+
+
+def test_search_L_at_least_n_is_exact_on_reachable_graph(oracle_lib, small_graph):
+    X, T, Q, G = small_graph
+    gt, gd = oracle_lib.knn(X, Q[:30], 10)
+    ids, ds, hops, ev, _ = oracle_lib.search(X, G.offsets, G.indices, G.entry, Q[:30], 10, G.n)
+    assert (ids == gt).all() and (ds == gd).all()
+    assert (ev == G.n).all()
+    assert oracle_lib.recall(ids, gt, 10) == 1.0
+
+
+def test_search_path_graph_by_hand(oracle_lib):
+    # points on a line, delta = -x*q; path 0-1-2-3-4 (both directions)
+    X = np.array([[1], [2], [3], [4], [5]], np.float32)
+    rows = [[1], [0, 2], [1, 3], [2, 4], [3]]
+    off = np.array([0, 1, 3, 5, 7, 8], np.int64)
+    idx = np.array(sum(rows, []), np.uint32)
+    # q = +1 prefers larger x.  L=1 from entry 0: 0 -> 1 -> 2 -> 3 -> 4.
+    ids, ds, hops, ev, gaps = oracle_lib.search(X, off, idx, 0, np.array([[1]], np.float32), 1, 1)
+    assert ids[0, 0] == 4 and ds[0, 0] == -5.0 and hops[0] == 5 and ev[0] == 5
+    # q = -1 prefers smaller x: from entry 2 with L=2: expand 2 (sees 1, 3),
+    # queue [1, 2]; expand 1 (sees 0), queue [0, 1]; expand 0; done.
+    ids, ds, hops, ev, gaps = oracle_lib.search(X, off, idx, 2, np.array([[-1]], np.float32), 2, 2)
+    assert list(ids[0]) == [0, 1] and list(ds[0]) == [1.0, 2.0]
+    assert hops[0] == 3 and ev[0] == 4
+    assert gaps[0] == 1.0
+
+
+def test_search_single_node_and_padding(oracle_lib):
+    X = np.array([[2.0, 0.0]], np.float32)
+    ids, ds, hops, ev, _ = oracle_lib.search(X, np.array([0, 0], np.int64), np.zeros(0, np.uint32), 0,
+                                             np.array([[1.0, 1.0]], np.float32), 3, 2)
+    assert ids[0, 0] == 0 and ds[0, 0] == -2.0
+    assert ids[0, 1] == oracle_lib.NONE and math.isinf(ds[0, 2])
+    assert hops[0] == 1 and ev[0] == 1
+
+
+def test_search_exact_tie_has_zero_gap(oracle_lib):
+    X = np.array([[1, 0], [0, 1], [0, 1]], np.float32)  # nodes 1 and 2 tie for any query
+    off, idx = _complete(3)
+    ids, ds, hops, ev, gaps = oracle_lib.search(X, off, idx, 0, np.array([[0, 1]], np.float32), 1, 1)
+    assert ids[0, 0] == 1 and gaps[0] == 0.0
+
+
+# --------------------------------------------------------------------------
+# recall@k (Sec. 2.1.1)
+# --------------------------------------------------------------------------
+def test_recall_definition(oracle_lib):
+    res = np.array([[1, 2, 3], [4, 5, 6]], np.uint32)
+    gt = np.array([[3, 2, 9, 1], [7, 8, 9, 4]], np.uint32)
+    assert oracle_lib.recall(res, gt, 3) == pytest.approx((2 / 3 + 0) / 2)
+    assert oracle_lib.recall(res, gt, 1) == pytest.approx(0.0)
+
+
+# --------------------------------------------------------------------------
+# number formats of the reduced-precision form, against torch's CPU casts
+# --------------------------------------------------------------------------
+def test_bf16_matches_torch_rounding(oracle_lib):
+    torch = pytest.importorskip("torch")
+    rng = np.random.default_rng(4)
+    x = np.concatenate([
+        rng.standard_normal(20000).astype(np.float32),
+        (rng.standard_normal(2000) * 1e-30).astype(np.float32),
+        np.array([0.0, -0.0, 1.0, 1.00390625, 1.01171875, 3.0e38, -2.5, 65504.0], np.float32),
+    ])
+    # exact ties: low 16 bits == 0x8000
+    b = rng.integers(0, 2 ** 31, size=2000, dtype=np.uint32) & np.uint32(0x7F7F0000) | np.uint32(0x8000)
+    x = np.concatenate([x, b.view(np.float32)])
+    ref = torch.from_numpy(x).to(torch.bfloat16).to(torch.float32).numpy()
+    got = oracle_lib.bf16(x)
+    assert np.array_equal(got.view(np.uint32), ref.view(np.uint32))
+
+
+def test_e4m3_code_values_match_torch(oracle_lib):
+    torch = pytest.importorskip("torch")
+    codes = torch.arange(256, dtype=torch.uint8).view(torch.float8_e4m3fn).to(torch.float64).numpy()
+    for c in range(256):
+        v = oracle_lib.e4m3_value(c)
+        if math.isnan(codes[c]):
+            assert math.isnan(v)
+        else:
+            assert v == codes[c], c
+    assert oracle_lib.e4m3_value(0x7E) == 448.0
+
+
+def test_e4m3_encode_matches_torch(oracle_lib):
+    torch = pytest.importorskip("torch")
+    rng = np.random.default_rng(5)
+    y = np.concatenate([rng.uniform(-448, 448, 4000), rng.standard_normal(4000) * 0.01,
+                        np.array([0.0, 448.0, -448.0, 0.0009765625, 1.0625, 17.0, 0.01953125 / 2])])
+    # midpoints between neighbouring codes (exact ties)
+    vals = np.array([oracle_lib.e4m3_value(c) for c in range(0x7F)])
+    y = np.concatenate([y, (vals[:-1] + vals[1:]) / 2, -(vals[:-1] + vals[1:]) / 2])
+    ref = torch.from_numpy(y.astype(np.float32)).to(torch.float8_e4m3fn).view(torch.uint8).numpy()
+    got = np.array([oracle_lib.e4m3_encode(float(np.float32(v))) for v in y], np.uint8)
+    assert np.array_equal(got, ref)
+
+
+def test_fp8_scale_and_error_bound(oracle_lib):
+    rng = np.random.default_rng(6)
+    X = (rng.standard_normal((50, 64)) * rng.uniform(1e-3, 1e3, size=(50, 1))).astype(np.float32)
+    X[3] = 0
+    codes, scales, deq = oracle_lib.quant_fp8(X)
+    for r in range(50):
+        s = float(scales[r])
+        m, e = math.frexp(s)
+        assert m == 0.5                                      # a power of two
+        amax = float(np.abs(X[r]).max())
+        if amax == 0:
+            assert s == 1.0 and (deq[r] == 0).all()
+            continue
+        assert amax <= 448 * s and amax > 224 * s            # smallest such power
+        err = np.abs(deq[r].astype(np.float64) - X[r])
+        # e4m3: relative 2^-4 for normals, absolute 2^-10 * s below 2^-6 * s
+        assert (err <= np.maximum(np.abs(X[r]) * 2.0 ** -4, 2.0 ** -10 * s) + 0).all()
+
+
+def test_rerank_search_with_exact_storage_equals_plain(oracle_lib, small_graph):
+    X, T, Q, G = small_graph
+    a = oracle_lib.search(X, G.offsets, G.indices, G.entry, Q[:40], 10, 32)
+    b = oracle_lib.search_rerank(X, X, G.offsets, G.indices, G.entry, Q[:40], 10, 32)
+    assert (a[0] == b[0]).all() and (a[1] == b[1]).all() and (a[2] == b[2]).all()
