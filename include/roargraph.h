@@ -1,0 +1,275 @@
+/*
+ * roargraph.h -- C ABI of the MI355X RoarGraph library.
+ *
+ * RoarGraph (Chen et al., PVLDB 17(11), 2024) is a graph index for
+ * cross-modal approximate nearest-neighbour search that is built with the
+ * help of a set of training queries: a query-base bipartite graph (Algorithm 1,
+ * Sec. 4.2.2) is projected onto the base vectors (Algorithm 2 with the
+ * neighbour-selection rule of Algorithm 3, Sec. 4.2.3), then every base
+ * vector is searched on the projected graph to add supplementary edges
+ * (connectivity enhancement, Algorithm 1, Sec. 4.2.4).  Queries run a beam
+ * search from the medoid with a queue of length L (Sec. 4.3).
+ *
+ * Conventions for every call:
+ *   - Return value: RG_OK (0) or a negative RG_E* code; rg_last_error()
+ *     then returns a message for the calling thread.
+ *   - Vectors are float32, row-major, rows of d contiguous floats.
+ *   - "device" pointers are HIP device memory on the current device (e.g.
+ *     torch tensors' data_ptr()); "host" pointers are ordinary memory.
+ *   - stream is a hipStream_t passed as void* (NULL = the null stream);
+ *     calls that return host results synchronise that stream before return.
+ *   - Distance: delta(q, x) = -<q, x> (maximum inner product, Sec. 5.1);
+ *     cosine workloads pass L2-normalised rows.  Smaller delta is closer;
+ *     ties are broken by the smaller id.
+ *   - The caller owns every buffer it passes.  The library owns rg_index and
+ *     rg_server objects (their device copies of the base, the graph and the
+ *     reduced-precision copies) until rg_free / rg_server_destroy.
+ *   - rg_search, rg_knn and rg_index_graph may run concurrently on one const
+ *     index; rg_index_set_storage, rg_save and rg_free may not overlap any
+ *     other call on the same index.
+ */
+#ifndef ROARGRAPH_H
+#define ROARGRAPH_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct rg_index rg_index;
+typedef struct rg_server rg_server;
+
+enum {
+    RG_OK = 0,
+    RG_EINVAL = -1,    /* bad argument (sizes, null pointers, unsupported mode) */
+    RG_ENOMEM = -2,    /* host or device allocation failed */
+    RG_EDEVICE = -3,   /* a HIP call or kernel launch failed */
+    RG_EAGAIN = -4,    /* serving: no slot or memory free right now, retry */
+    RG_ECORRUPT = -5,  /* index file unreadable or its checksum does not match */
+    RG_EINTERNAL = -6  /* an internal invariant failed (reported, never ignored) */
+};
+
+enum { RG_METRIC_IP = 0 };
+
+/* Storage of the base rows that the search scores against (Sec. 4.3 calls
+ * compression orthogonal to the index; Sec. 7 names scalar quantisation with
+ * rescoring).  BF16: round-to-nearest-even.  FP8: OCP E4M3 codes with one
+ * power-of-two scale per row, s = the smallest 2^e with 448*2^e >= max|x_i|.
+ * Either way the final queue is rescored exactly in FP32. */
+enum { RG_STORE_FP32 = 0, RG_STORE_BF16 = 1, RG_STORE_FP8E4M3 = 2 };
+
+/* Build options; pass NULL for the defaults. */
+typedef struct {
+    int32_t L_build;   /* candidate-list length in projection and queue length of the
+                          enhancement searches ("L", Algorithms 1-2); default 500 (Sec. 5.1) */
+    int32_t m_pj;      /* out-degree bound of the projected graph; 0 => ceil((M-1)/2) */
+    int32_t m_ce;      /* out-degree bound of the enhancement lists; 0 => floor((M-1)/2) */
+    int32_t threads;   /* host threads for construction; 0 => all hardware threads */
+    int32_t knn_slack; /* extra GPU kNN candidates per training query before the exact
+                          rerank; 0 => max(16, Nq/4) */
+} rg_build_opts;
+
+/*
+ * rg_build -- build the index (Algorithm 1).
+ *   base   device, n x d float32: the base vectors X.
+ *   train  device, nt x d float32: the training queries T (Sec. 4.2.1).
+ *   Nq     number of nearest base vectors per training query (>= 2, <= n).
+ *   M      bound on every node's final out-degree (>= 3); projection and
+ *          enhancement use m_pj + m_ce <= M - 1 and one slot per node is left
+ *          for the reachability repair.
+ * The Nq-NN lists come from the GPU kNN (rg_knn semantics: FP32 MFMA
+ * candidates, exact FP64 rerank with a certified margin); the graph steps run
+ * on host threads with the canonical FP64 distance (sum of exact products in
+ * increasing coordinate order).  The result is deterministic and independent
+ * of the thread count.  On success *out owns a device copy of the base, the
+ * adjacency, and a host CSR view (rg_index_graph).
+ * Errors: RG_EINVAL (n < 1, n >= 2^31, d < 1, nt < 1, Nq < 2, Nq > n, M < 3,
+ * M > 128, metric != RG_METRIC_IP, null pointers), RG_ENOMEM, RG_EDEVICE,
+ * RG_EINTERNAL.
+ */
+int rg_build(const float *base, int64_t n, int32_t d, const float *train, int64_t nt,
+             int32_t Nq, int32_t M, int32_t metric, const rg_build_opts *opts, void *stream,
+             rg_index **out);
+
+/*
+ * rg_build_from_knn -- the host half of rg_build, for callers that already
+ * hold the preprocessing result (the Nq nearest base rows of each training
+ * query, Algorithm 1 input).
+ *   base_host  host, n x d float32.
+ *   knn_host   host, nt x Nq uint32, each row in (delta, id) order with the
+ *              canonical FP64 distance (as rg_knn returns them).
+ * Runs bipartite graph, projection, enhancement, repair and CSR on host
+ * threads; the index holds only the graph (rg_index_graph, rg_save need
+ * no device data; rg_search returns RG_EINVAL).  No HIP call is made.
+ * Errors: RG_EINVAL (as rg_build, plus ids >= n), RG_EINTERNAL.
+ */
+int rg_build_from_knn(const float *base_host, int64_t n, int32_t d, const uint32_t *knn_host,
+                      int64_t nt, int32_t Nq, int32_t M, const rg_build_opts *opts, rg_index **out);
+
+/*
+ * rg_index_from_csr -- wrap an existing graph as an index.
+ *   base    device, n x d float32 (copied).
+ *   offsets host, n+1 int64, offsets[0] = 0, non-decreasing.
+ *   indices host, offsets[n] uint32 ids < n (copied).
+ *   entry   start node of every search (< n).
+ * Out-degree must be <= 128.  Errors: RG_EINVAL, RG_ENOMEM, RG_EDEVICE.
+ */
+int rg_index_from_csr(const float *base, int64_t n, int32_t d, const int64_t *offsets,
+                      const uint32_t *indices, uint32_t entry, int32_t metric, void *stream,
+                      rg_index **out);
+
+/*
+ * rg_index_graph -- host views of the final graph: CSR with rows sorted by
+ * neighbour id, int64 offsets (n+1), uint32 indices (nnz), and the entry
+ * point.  Views stay valid until rg_free.  Any output pointer may be NULL.
+ */
+int rg_index_graph(const rg_index *idx, const int64_t **offsets, const uint32_t **indices,
+                   int64_t *nnz, uint32_t *entry);
+
+/* rg_index_info -- n, d, the padded row pitch in floats, the ELL row width of
+ * the device adjacency, and device bytes held.  Any output may be NULL. */
+int rg_index_info(const rg_index *idx, int64_t *n, int32_t *d, int32_t *pitch,
+                  int32_t *ell_width, int64_t *device_bytes);
+
+/*
+ * rg_index_set_storage -- choose the storage searched by rg_search
+ * (RG_STORE_*).  BF16 / FP8 copies are made on the device from the index's
+ * FP32 rows; the FP32 rows are kept for the exact rerank.
+ * Errors: RG_EINVAL, RG_ENOMEM, RG_EDEVICE.
+ */
+int rg_index_set_storage(rg_index *idx, int32_t storage, void *stream);
+
+/*
+ * rg_search -- batched beam search (Sec. 4.3), one query per wavefront.
+ *   queries device, nq x d float32.
+ *   k       results per query (1..512); L queue length (1..512); the queue
+ *           actually kept is L_eff = max(L, k).
+ *   ids     device, nq x k uint32; dists device, nq x k float32 holding
+ *           -<q, x_id> in FP32, ascending; when fewer than k nodes are
+ *           reachable the tail is 0xFFFFFFFF / +inf.
+ *   hops    device, nq uint32 or NULL: nodes expanded per query.
+ *   evals   device, nq uint32 or NULL: distances computed per query
+ *           (includes recomputations after the LDS visited table is reset).
+ * The search expands the closest unexpanded queue entry until none is left;
+ * a neighbour enters the queue if the queue is not full or it beats the last
+ * entry.  With reduced-precision storage the final L_eff queue is rescored
+ * against the FP32 rows and the best k are returned.  Asynchronous on stream.
+ * Errors: RG_EINVAL, RG_EDEVICE.
+ */
+int rg_search(const rg_index *idx, const float *queries, int64_t nq, int32_t k, int32_t L,
+              uint32_t *ids, float *dists, uint32_t *hops, uint32_t *evals, void *stream);
+
+/*
+ * rg_knn -- exact k nearest base rows of each query (Def. 1): the
+ * preprocessing step of construction and the ground truth of recall@k.
+ *   queries device nq x d; base device n x d; ids/dists device nq x k.
+ * The GPU computes FP32 scores with MFMA and keeps k + slack candidates per
+ * query; the host rescores them in FP64 and certifies that no other base row
+ * can be closer (the FP32 error bound is smaller than the margin); rows that
+ * fail are recomputed with more candidates.  ids are in (delta, id) order and
+ * dists hold the FP64 delta rounded to float.  Synchronous.
+ * Errors: RG_EINVAL (k < 1, k > n, k > 224, n >= 2^31), RG_ENOMEM,
+ * RG_EDEVICE, RG_EINTERNAL (certification failed with 256 candidates).
+ */
+int rg_knn(const float *queries, int64_t nq, const float *base, int64_t n, int32_t d,
+           int32_t k, uint32_t *ids, float *dists, void *stream);
+
+/*
+ * rg_knn_candidates -- the GPU half of rg_knn alone: for each query the K
+ * best base rows by FP32 score, ordered by (score descending, id ascending).
+ * ids/scores device nq x K.  Asynchronous.  Errors: RG_EINVAL, RG_EDEVICE.
+ */
+int rg_knn_candidates(const float *queries, int64_t nq, const float *base, int64_t n, int32_t d,
+                      int32_t K, uint32_t *ids, float *scores, void *stream);
+
+/*
+ * rg_search_hashbits -- rg_search with the LDS visited table fixed at
+ * 2^hash_bits entries (8..15, and at least twice the ELL row width).  The
+ * table only bounds work (a cleared table makes nodes be scored again), so
+ * results are identical for every size; tests use it to show that.
+ */
+int rg_search_hashbits(const rg_index *idx, const float *queries, int64_t nq, int32_t k, int32_t L,
+                       uint32_t *ids, float *dists, uint32_t *hops, uint32_t *evals, int32_t hash_bits,
+                       void *stream);
+
+/* rg_index_build_stats -- wall seconds of the build's kNN preprocessing
+ * (Sec. 5.6 reports it as the dominant share), projection, enhancement and
+ * total, and the number of repair edges.  Any output may be NULL. */
+int rg_index_build_stats(const rg_index *idx, double *t_knn, double *t_project, double *t_enhance,
+                         double *t_total, int64_t *repairs);
+
+/* rg_index_storage_ptrs -- device pointers of the reduced-precision copies
+ * (NULL until made by rg_index_set_storage): bf16 rows (pitch elements of
+ * 2 bytes), e4m3 rows (pitch8 bytes) and their per-row scales.  The index
+ * keeps ownership. */
+int rg_index_storage_ptrs(const rg_index *idx, const void **bf16, const void **fp8,
+                          const float **scales, int32_t *pitch8);
+
+/* rg_save / rg_load -- index file: header, parameters, entry, CSR, FP32 base
+ * rows, and a 64-bit checksum over everything (rg_save needs an index with
+ * device data).  Errors: RG_EINVAL,
+ * RG_ENOMEM, RG_EDEVICE, RG_ECORRUPT (bad magic, size or checksum). */
+int rg_save(const rg_index *idx, const char *path);
+int rg_load(const char *path, void *stream, rg_index **out);
+
+void rg_free(rg_index *idx);
+const char *rg_last_error(void);
+
+/* ---------------------------------------------------------------------- */
+/* Serving: continuous batching of search requests with mixed k and L.     */
+/* Requests are admitted into device-resident slots as slots and the HBM   */
+/* pool allow; every slot keeps its beam state (queue, visited table) in   */
+/* device memory between scheduler steps, and each step advances every     */
+/* active slot by a bounded number of expansions, so requests that arrive  */
+/* while others run join the next step.  A request's result does not       */
+/* depend on what else is in flight.                                       */
+/* ---------------------------------------------------------------------- */
+typedef struct {
+    int32_t max_slots;        /* concurrent requests on the device (>= 1) */
+    int64_t hbm_pool_bytes;   /* bound on slot state bytes; 0 => no bound beyond max_slots */
+    int32_t hops_per_step;    /* expansions per slot per step; 0 => 32 */
+    int32_t max_L;            /* largest L_eff accepted (<= 512); 0 => 512 */
+} rg_server_limits;
+
+typedef struct {
+    uint64_t tag;
+    int32_t k;
+    int32_t status;           /* RG_OK */
+    uint32_t hops, evals;
+    uint32_t ids[512];
+    float dists[512];
+    double t_submit, t_admit, t_done; /* seconds on the server's monotonic clock */
+} rg_result;
+
+/* rg_server_create -- start a server (and its scheduler thread) on idx.
+ * idx must outlive the server.  Errors: RG_EINVAL, RG_ENOMEM, RG_EDEVICE. */
+int rg_server_create(const rg_index *idx, const rg_server_limits *lim, rg_server **out);
+
+/* rg_server_submit -- queue one request; query_host is d floats (copied).
+ * Returns RG_EAGAIN when the pending queue is full.  Errors: RG_EINVAL. */
+int rg_server_submit(rg_server *s, const float *query_host, int32_t k, int32_t L, uint64_t tag);
+
+/* rg_server_poll -- move up to max finished results into out; *n_out gets
+ * the number written.  Never blocks. */
+int rg_server_poll(rg_server *s, rg_result *out, int32_t max, int32_t *n_out);
+
+/* rg_server_stats -- requests submitted, admitted, completed, steps run. */
+int rg_server_stats(const rg_server *s, uint64_t *submitted, uint64_t *admitted,
+                    uint64_t *completed, uint64_t *steps);
+
+/* rg_server_now -- the server's clock (seconds), for request timestamps. */
+double rg_server_now(const rg_server *s);
+
+/* rg_server_slots -- slots actually allocated: min(max_slots,
+ * hbm_pool_bytes / bytes of one slot's state). */
+int32_t rg_server_slots(const rg_server *s);
+
+/* rg_server_destroy -- finish in-flight work, stop the thread, free all. */
+void rg_server_destroy(rg_server *s);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* ROARGRAPH_H */

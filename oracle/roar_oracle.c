@@ -778,10 +778,13 @@ or_graph *or_build(const float *X, int64_t n, int32_t d, const float *T, int64_t
     adj_free(&ce);
     free(tmp);
 
-    /* Reachability repair: BFS from the entry; each node still unreached,  */
-    /* in ascending id, gets one in-edge from the first node of its          */
-    /* enhancement list with a free slot (else the first reached node in BFS */
-    /* order with a free slot), and the BFS is extended from it.             */
+    /* Reachability repair: BFS from the entry, visiting each node's        */
+    /* neighbours in ascending id; each node still unreached, in ascending   */
+    /* id, gets one in-edge from the first node of its enhancement list with */
+    /* a free slot (else the first reached node in BFS order with a free     */
+    /* slot), and the BFS is extended from it.                               */
+    for (int64_t x = 0; x < n; ++x)
+        qsort(fin.a + x * M, (size_t)fin.deg[x], sizeof(uint32_t), u32_cmp);
     {
         uint8_t *seen = (uint8_t *)calloc((size_t)n, 1);
         uint32_t *order = (uint32_t *)malloc(sizeof(uint32_t) * (size_t)n);

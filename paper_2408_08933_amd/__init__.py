@@ -1,0 +1,314 @@
+"""Python binding of the MI355X RoarGraph library (libroargraph.so).
+
+Argument marshalling only: every step of construction and search runs in
+the library (HIP kernels on gfx950 plus its native host code).  PyTorch
+supplies device memory and the current HIP stream.  Names follow the C ABI
+in include/roargraph.h.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libroargraph.so")
+
+RG_OK, RG_EINVAL, RG_ENOMEM, RG_EDEVICE, RG_EAGAIN, RG_ECORRUPT, RG_EINTERNAL = 0, -1, -2, -3, -4, -5, -6
+RG_METRIC_IP = 0
+RG_STORE_FP32, RG_STORE_BF16, RG_STORE_FP8E4M3 = 0, 1, 2
+NONE = 0xFFFFFFFF
+MAX_L = 512
+
+
+class RGError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"roargraph error {code}: {msg}")
+        self.code = code
+
+
+class rg_build_opts(ctypes.Structure):
+    _fields_ = [("L_build", ctypes.c_int32), ("m_pj", ctypes.c_int32), ("m_ce", ctypes.c_int32),
+                ("threads", ctypes.c_int32), ("knn_slack", ctypes.c_int32)]
+
+
+class rg_server_limits(ctypes.Structure):
+    _fields_ = [("max_slots", ctypes.c_int32), ("hbm_pool_bytes", ctypes.c_int64),
+                ("hops_per_step", ctypes.c_int32), ("max_L", ctypes.c_int32)]
+
+
+class rg_result(ctypes.Structure):
+    _fields_ = [("tag", ctypes.c_uint64), ("k", ctypes.c_int32), ("status", ctypes.c_int32),
+                ("hops", ctypes.c_uint32), ("evals", ctypes.c_uint32),
+                ("ids", ctypes.c_uint32 * MAX_L), ("dists", ctypes.c_float * MAX_L),
+                ("t_submit", ctypes.c_double), ("t_admit", ctypes.c_double), ("t_done", ctypes.c_double)]
+
+
+_lib = None
+P, i64, i32, u32 = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32, ctypes.c_uint32
+PP = ctypes.POINTER(ctypes.c_void_p)
+_SIGS = {
+    "rg_build": (i32, [P, i64, i32, P, i64, i32, i32, i32, ctypes.POINTER(rg_build_opts), P, PP]),
+    "rg_index_from_csr": (i32, [P, i64, i32, P, P, u32, i32, P, PP]),
+    "rg_build_from_knn": (i32, [P, i64, i32, P, i64, i32, i32, ctypes.POINTER(rg_build_opts), PP]),
+    "rg_index_graph": (i32, [P, PP, PP, ctypes.POINTER(i64), ctypes.POINTER(u32)]),
+    "rg_index_info": (i32, [P, ctypes.POINTER(i64), ctypes.POINTER(i32), ctypes.POINTER(i32),
+                            ctypes.POINTER(i32), ctypes.POINTER(i64)]),
+    "rg_index_set_storage": (i32, [P, i32, P]),
+    "rg_search": (i32, [P, P, i64, i32, i32, P, P, P, P, P]),
+    "rg_search_hashbits": (i32, [P, P, i64, i32, i32, P, P, P, P, i32, P]),
+    "rg_knn": (i32, [P, i64, P, i64, i32, i32, P, P, P]),
+    "rg_knn_candidates": (i32, [P, i64, P, i64, i32, i32, P, P, P]),
+    "rg_index_build_stats": (i32, [P] + [ctypes.POINTER(ctypes.c_double)] * 4 + [ctypes.POINTER(i64)]),
+    "rg_index_storage_ptrs": (i32, [P, PP, PP, PP, ctypes.POINTER(i32)]),
+    "rg_save": (i32, [P, ctypes.c_char_p]),
+    "rg_load": (i32, [ctypes.c_char_p, P, PP]),
+    "rg_free": (None, [P]),
+    "rg_last_error": (ctypes.c_char_p, []),
+    "rg_server_create": (i32, [P, ctypes.POINTER(rg_server_limits), PP]),
+    "rg_server_submit": (i32, [P, P, i32, i32, ctypes.c_uint64]),
+    "rg_server_poll": (i32, [P, ctypes.POINTER(rg_result), i32, ctypes.POINTER(i32)]),
+    "rg_server_stats": (i32, [P] + [ctypes.POINTER(ctypes.c_uint64)] * 4),
+    "rg_server_now": (ctypes.c_double, [P]),
+    "rg_server_slots": (i32, [P]),
+    "rg_server_destroy": (None, [P]),
+}
+
+
+def lib():
+    """The loaded library; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with __graft_entry__.build()")
+        h = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in _SIGS.items():
+            f = getattr(h, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = h
+    return _lib
+
+
+def _check(rc):
+    if rc != RG_OK:
+        raise RGError(rc, lib().rg_last_error().decode(errors="replace"))
+
+
+def _stream(stream=None):
+    import torch
+    s = torch.cuda.current_stream() if stream is None else stream
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _dev_f32(t, name):
+    import torch
+    if not (isinstance(t, torch.Tensor) and t.is_cuda and t.dtype == torch.float32 and t.dim() == 2
+            and t.is_contiguous()):
+        raise ValueError(f"{name} must be a contiguous 2-D float32 CUDA tensor")
+    return t
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def as_u32(t) -> np.ndarray:
+    """Device int32 tensor holding uint32 ids -> numpy uint32."""
+    return t.cpu().numpy().view(np.uint32)
+
+
+class Index:
+    """Owns an rg_index handle."""
+
+    def __init__(self, handle, keep=None):
+        self.h = handle
+        self._keep = keep
+
+    def __del__(self):
+        if getattr(self, "h", None):
+            lib().rg_free(self.h)
+            self.h = None
+
+    def graph(self):
+        off, idx = ctypes.c_void_p(), ctypes.c_void_p()
+        nnz, entry = i64(), u32()
+        _check(lib().rg_index_graph(self.h, ctypes.byref(off), ctypes.byref(idx), ctypes.byref(nnz),
+                                    ctypes.byref(entry)))
+        n = self.info()["n"]
+        o = np.ctypeslib.as_array(ctypes.cast(off, ctypes.POINTER(ctypes.c_int64)), (n + 1,)).copy()
+        if nnz.value:
+            x = np.ctypeslib.as_array(ctypes.cast(idx, ctypes.POINTER(ctypes.c_uint32)), (nnz.value,)).copy()
+        else:
+            x = np.zeros(0, np.uint32)
+        return o, x, int(entry.value)
+
+    def info(self):
+        n, d, pitch, ell, b = i64(), i32(), i32(), i32(), i64()
+        _check(lib().rg_index_info(self.h, ctypes.byref(n), ctypes.byref(d), ctypes.byref(pitch),
+                                   ctypes.byref(ell), ctypes.byref(b)))
+        return {"n": n.value, "d": d.value, "pitch": pitch.value, "ell": ell.value, "device_bytes": b.value}
+
+    def build_stats(self):
+        v = [ctypes.c_double() for _ in range(4)]
+        r = i64()
+        _check(lib().rg_index_build_stats(self.h, *[ctypes.byref(x) for x in v], ctypes.byref(r)))
+        return {"t_knn": v[0].value, "t_project": v[1].value, "t_enhance": v[2].value,
+                "t_total": v[3].value, "repairs": r.value}
+
+    def storage_ptrs(self):
+        b, f, s = ctypes.c_void_p(), ctypes.c_void_p(), ctypes.c_void_p()
+        p8 = i32()
+        _check(lib().rg_index_storage_ptrs(self.h, ctypes.byref(b), ctypes.byref(f), ctypes.byref(s),
+                                           ctypes.byref(p8)))
+        return b.value, f.value, s.value, p8.value
+
+
+def rg_build(base, train, Nq, M, L_build=0, m_pj=0, m_ce=0, threads=0, knn_slack=0, stream=None) -> Index:
+    base, train = _dev_f32(base, "base"), _dev_f32(train, "train")
+    o = rg_build_opts(L_build, m_pj, m_ce, threads, knn_slack)
+    h = ctypes.c_void_p()
+    _check(lib().rg_build(_ptr(base), base.shape[0], base.shape[1], _ptr(train), train.shape[0], int(Nq), int(M),
+                          RG_METRIC_IP, ctypes.byref(o), _stream(stream), ctypes.byref(h)))
+    return Index(h)
+
+
+def rg_build_from_knn(base_host, knn_host, Nq, M, L_build=0, m_pj=0, m_ce=0, threads=0) -> Index:
+    """Host-only construction from precomputed kNN lists (numpy inputs)."""
+    X = np.ascontiguousarray(base_host, dtype=np.float32)
+    K = np.ascontiguousarray(knn_host, dtype=np.uint32)
+    if K.ndim != 2 or K.shape[1] != Nq:
+        raise ValueError("knn_host must be nt x Nq")
+    o = rg_build_opts(L_build, m_pj, m_ce, threads, 0)
+    h = ctypes.c_void_p()
+    _check(lib().rg_build_from_knn(X.ctypes.data_as(P), X.shape[0], X.shape[1], K.ctypes.data_as(P), K.shape[0],
+                                   int(Nq), int(M), ctypes.byref(o), ctypes.byref(h)))
+    return Index(h)
+
+
+def rg_index_from_csr(base, offsets, indices, entry, stream=None) -> Index:
+    base = _dev_f32(base, "base")
+    off = np.ascontiguousarray(offsets, dtype=np.int64)
+    idx = np.ascontiguousarray(indices, dtype=np.uint32)
+    if idx.size == 0:
+        idx = np.zeros(1, np.uint32)
+    h = ctypes.c_void_p()
+    _check(lib().rg_index_from_csr(_ptr(base), base.shape[0], base.shape[1], off.ctypes.data_as(P),
+                                   idx.ctypes.data_as(P), int(entry), RG_METRIC_IP, _stream(stream), ctypes.byref(h)))
+    return Index(h)
+
+
+def rg_index_set_storage(index: Index, storage: int, stream=None):
+    _check(lib().rg_index_set_storage(index.h, int(storage), _stream(stream)))
+
+
+def rg_search(index: Index, queries, k, L, stats=False, hash_bits=None, stream=None):
+    """Returns (ids int32-as-uint32, dists float32[, hops, evals]) device tensors."""
+    import torch
+    queries = _dev_f32(queries, "queries")
+    nq = queries.shape[0]
+    dev = queries.device
+    ids = torch.empty((nq, k), dtype=torch.int32, device=dev)
+    ds = torch.empty((nq, k), dtype=torch.float32, device=dev)
+    hops = torch.empty(nq, dtype=torch.int32, device=dev) if stats else None
+    ev = torch.empty(nq, dtype=torch.int32, device=dev) if stats else None
+    hp = _ptr(hops) if stats else None
+    ep = _ptr(ev) if stats else None
+    if hash_bits is None:
+        _check(lib().rg_search(index.h, _ptr(queries), nq, int(k), int(L), _ptr(ids), _ptr(ds), hp, ep,
+                               _stream(stream)))
+    else:
+        _check(lib().rg_search_hashbits(index.h, _ptr(queries), nq, int(k), int(L), _ptr(ids), _ptr(ds), hp, ep,
+                                        int(hash_bits), _stream(stream)))
+    return (ids, ds, hops, ev) if stats else (ids, ds)
+
+
+def rg_search_into(index: Index, queries, k, L, ids, ds, hops=None, ev=None, stream=None):
+    """rg_search writing into preallocated device tensors (no allocation)."""
+    _check(lib().rg_search(index.h, _ptr(queries), queries.shape[0], int(k), int(L), _ptr(ids), _ptr(ds),
+                           _ptr(hops) if hops is not None else None, _ptr(ev) if ev is not None else None,
+                           _stream(stream)))
+
+
+def rg_knn(queries, base, k, stream=None):
+    import torch
+    queries, base = _dev_f32(queries, "queries"), _dev_f32(base, "base")
+    nq = queries.shape[0]
+    ids = torch.empty((nq, k), dtype=torch.int32, device=queries.device)
+    ds = torch.empty((nq, k), dtype=torch.float32, device=queries.device)
+    _check(lib().rg_knn(_ptr(queries), nq, _ptr(base), base.shape[0], base.shape[1], int(k), _ptr(ids), _ptr(ds),
+                        _stream(stream)))
+    return ids, ds
+
+
+def rg_knn_candidates(queries, base, K, stream=None):
+    import torch
+    queries, base = _dev_f32(queries, "queries"), _dev_f32(base, "base")
+    nq = queries.shape[0]
+    ids = torch.empty((nq, K), dtype=torch.int32, device=queries.device)
+    sc = torch.empty((nq, K), dtype=torch.float32, device=queries.device)
+    _check(lib().rg_knn_candidates(_ptr(queries), nq, _ptr(base), base.shape[0], base.shape[1], int(K), _ptr(ids),
+                                   _ptr(sc), _stream(stream)))
+    return ids, sc
+
+
+def rg_save(index: Index, path: str):
+    _check(lib().rg_save(index.h, path.encode()))
+
+
+def rg_load(path: str, stream=None) -> Index:
+    h = ctypes.c_void_p()
+    _check(lib().rg_load(path.encode(), _stream(stream), ctypes.byref(h)))
+    return Index(h)
+
+
+class Server:
+    """Continuous-batching search server over an Index (rg_server_*)."""
+
+    def __init__(self, index: Index, max_slots=1024, hbm_pool_bytes=0, hops_per_step=32, max_L=512):
+        self.index = index
+        lim = rg_server_limits(max_slots, hbm_pool_bytes, hops_per_step, max_L)
+        h = ctypes.c_void_p()
+        _check(lib().rg_server_create(index.h, ctypes.byref(lim), ctypes.byref(h)))
+        self.h = h
+        self._buf = (rg_result * 256)()
+
+    def submit(self, q: np.ndarray, k: int, L: int, tag: int) -> int:
+        q = np.ascontiguousarray(q, dtype=np.float32)
+        rc = lib().rg_server_submit(self.h, q.ctypes.data_as(P), int(k), int(L), int(tag))
+        if rc not in (RG_OK, RG_EAGAIN):
+            _check(rc)
+        return rc
+
+    def poll(self):
+        n = i32()
+        _check(lib().rg_server_poll(self.h, self._buf, len(self._buf), ctypes.byref(n)))
+        out = []
+        for i in range(n.value):
+            r = self._buf[i]
+            k = r.k
+            out.append({"tag": r.tag, "k": k, "status": r.status, "hops": r.hops, "evals": r.evals,
+                        "ids": np.frombuffer(r.ids, dtype=np.uint32, count=k).copy(),
+                        "dists": np.frombuffer(r.dists, dtype=np.float32, count=k).copy(),
+                        "t_submit": r.t_submit, "t_admit": r.t_admit, "t_done": r.t_done})
+        return out
+
+    def now(self) -> float:
+        return lib().rg_server_now(self.h)
+
+    def slots(self) -> int:
+        return lib().rg_server_slots(self.h)
+
+    def stats(self):
+        v = [ctypes.c_uint64() for _ in range(4)]
+        _check(lib().rg_server_stats(self.h, *[ctypes.byref(x) for x in v]))
+        return dict(zip(("submitted", "admitted", "completed", "steps"), (x.value for x in v)))
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().rg_server_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        self.close()

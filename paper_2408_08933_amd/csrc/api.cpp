@@ -1,0 +1,677 @@
+// C ABI: argument checking, device memory of the index, the exact kNN
+// (GPU candidates + certified FP64 rerank), search dispatch, index files.
+#include <algorithm>
+#include <atomic>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <thread>
+
+#include "rg_internal.h"
+
+namespace rg {
+
+static thread_local std::string g_err;
+
+void set_error(const std::string &msg) { g_err = msg; }
+
+namespace {
+
+int32_t round_up(int32_t v, int32_t m) { return (v + m - 1) / m * m; }
+
+template <class F>
+void par_rows(int64_t n, int threads, F &&f) {
+    threads = (int)std::max<int64_t>(1, std::min<int64_t>(threads, n));
+    std::atomic<int64_t> next(0);
+    auto work = [&]() {
+        for (;;) {
+            const int64_t s = next.fetch_add(64);
+            if (s >= n) break;
+            for (int64_t i = s; i < std::min(n, s + 64); ++i) f(i);
+        }
+    };
+    std::vector<std::thread> pool;
+    for (int t = 1; t < threads; ++t) pool.emplace_back(work);
+    work();
+    for (auto &th : pool) th.join();
+}
+
+struct DevBuf {
+    void *p = nullptr;
+    ~DevBuf() {
+        if (p) (void)hipFree(p);
+    }
+    int alloc(size_t bytes) {
+        if (hipMalloc(&p, bytes ? bytes : 1) != hipSuccess) {
+            p = nullptr;
+            set_error("out of device memory (" + std::to_string(bytes) + " bytes)");
+            return RG_ENOMEM;
+        }
+        return RG_OK;
+    }
+    template <class T>
+    T *as() const {
+        return static_cast<T *>(p);
+    }
+};
+
+void free_index_device(rg_index *ix) {
+    if (ix->d_base) (void)hipFree(ix->d_base);
+    if (ix->d_adj) (void)hipFree(ix->d_adj);
+    if (ix->d_bf16) (void)hipFree(ix->d_bf16);
+    if (ix->d_fp8) (void)hipFree(ix->d_fp8);
+    if (ix->d_scale) (void)hipFree(ix->d_scale);
+    ix->d_base = nullptr;
+    ix->d_adj = nullptr;
+    ix->d_bf16 = nullptr;
+    ix->d_fp8 = nullptr;
+    ix->d_scale = nullptr;
+}
+
+// Device copy of the base (rows padded to a 64-byte multiple) and the ELL adjacency.
+int upload_index(rg_index *ix, const float *base_dev, hipStream_t st) {
+    const int64_t n = ix->n;
+    ix->pitch = round_up(ix->d, 16);
+    int64_t maxdeg = 1;
+    for (int64_t x = 0; x < n; ++x) maxdeg = std::max<int64_t>(maxdeg, ix->offsets[x + 1] - ix->offsets[x]);
+    if (maxdeg > kMaxEll) {
+        set_error("index: out-degree " + std::to_string(maxdeg) + " exceeds 128");
+        return RG_EINVAL;
+    }
+    ix->ell = round_up((int32_t)maxdeg, 8);
+    if (hipMalloc(&ix->d_base, sizeof(float) * (size_t)n * ix->pitch) != hipSuccess ||
+        hipMalloc(&ix->d_adj, sizeof(uint32_t) * (size_t)n * ix->ell) != hipSuccess) {
+        free_index_device(ix);
+        set_error("index: out of device memory");
+        return RG_ENOMEM;
+    }
+    int rc = launch_pad_rows(base_dev, n, ix->d, ix->d_base, ix->pitch, st);
+    if (rc) return rc;
+    std::vector<uint32_t> ell((size_t)n * ix->ell, kNone);
+    for (int64_t x = 0; x < n; ++x)
+        std::copy(ix->indices.begin() + ix->offsets[x], ix->indices.begin() + ix->offsets[x + 1],
+                  ell.begin() + x * ix->ell);
+    RG_HIP(hipMemcpyAsync(ix->d_adj, ell.data(), sizeof(uint32_t) * ell.size(), hipMemcpyHostToDevice, st));
+    RG_HIP(hipStreamSynchronize(st));
+    return RG_OK;
+}
+
+int check_csr(int64_t n, const int64_t *off, const uint32_t *idx, uint32_t entry) {
+    if (off[0] != 0) return RG_EINVAL;
+    for (int64_t x = 0; x < n; ++x)
+        if (off[x + 1] < off[x]) return RG_EINVAL;
+    for (int64_t e = 0; e < off[n]; ++e)
+        if (idx[e] >= (uint64_t)n) return RG_EINVAL;
+    if (entry >= (uint64_t)n) return RG_EINVAL;
+    return RG_OK;
+}
+
+int copy_to_host(const float *dev, int64_t count, std::vector<float> &h, hipStream_t st) {
+    h.resize((size_t)count);
+    RG_HIP(hipMemcpyAsync(h.data(), dev, sizeof(float) * (size_t)count, hipMemcpyDeviceToHost, st));
+    RG_HIP(hipStreamSynchronize(st));
+    return RG_OK;
+}
+
+uint64_t fnv1a(uint64_t h, const void *p, size_t n) {
+    const unsigned char *b = static_cast<const unsigned char *>(p);
+    for (size_t i = 0; i < n; ++i) {
+        h ^= b[i];
+        h *= 1099511628211ull;
+    }
+    return h;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// exact kNN
+// ---------------------------------------------------------------------------
+int knn_exact(const float *Qdev, int64_t nq, const float *Xdev, int64_t n, int32_t d, int32_t k, int32_t slack,
+              const float *Qhost, const float *Xhost, int threads, std::vector<uint32_t> *ids_out,
+              std::vector<double> *d_out, hipStream_t st) {
+    threads = hw_threads(threads);
+    if (slack <= 0) slack = std::max(16, k / 4);
+    int32_t K = (int32_t)std::min<int64_t>(n, (int64_t)k + slack);
+    if (K > 256) K = std::max(k, 256);
+    ids_out->assign((size_t)nq * k, kNone);
+    if (d_out) d_out->assign((size_t)nq * k, INFINITY);
+    // FP32 error bound of any summation order of d rounded products, and the
+    // FP64 one of the canonical sum; scaled by |t| * max|x| (Cauchy-Schwarz).
+    const double u32 = std::ldexp(1.0, -24), u64 = std::ldexp(1.0, -53);
+    const double g32 = (d + 1) * u32 / (1.0 - (d + 1) * u32);
+    const double g64 = (d + 1) * u64 / (1.0 - (d + 1) * u64);
+    double xmax = 0.0;
+    for (int64_t i = 0; i < n; ++i) {
+        double s = 0.0;
+        for (int j = 0; j < d; ++j) s += (double)Xhost[i * d + j] * (double)Xhost[i * d + j];
+        xmax = std::max(xmax, std::sqrt(s));
+    }
+    xmax *= 1.0 + 1e-12;
+
+    std::vector<int64_t> rows((size_t)nq);
+    for (int64_t i = 0; i < nq; ++i) rows[i] = i;
+    std::vector<float> qsub;
+    for (;;) {
+        const int64_t m = (int64_t)rows.size();
+        // queries of this round, contiguous on the device
+        const float *qd = Qdev;
+        DevBuf qbuf;
+        if (m != nq) {
+            qsub.resize((size_t)m * d);
+            for (int64_t i = 0; i < m; ++i) std::memcpy(&qsub[i * d], Qhost + rows[i] * d, sizeof(float) * d);
+            int rc = qbuf.alloc(sizeof(float) * qsub.size());
+            if (rc) return rc;
+            RG_HIP(hipMemcpyAsync(qbuf.p, qsub.data(), sizeof(float) * qsub.size(), hipMemcpyHostToDevice, st));
+            qd = qbuf.as<float>();
+        }
+        DevBuf cid, csc;
+        int rc = cid.alloc(sizeof(uint32_t) * (size_t)m * K);
+        if (!rc) rc = csc.alloc(sizeof(float) * (size_t)m * K);
+        if (rc) return rc;
+        rc = launch_knn_candidates(qd, m, d, Xdev, n, d, d, K, cid.as<uint32_t>(), csc.as<float>(), st);
+        if (rc) return rc;
+        std::vector<uint32_t> hid((size_t)m * K);
+        std::vector<float> hsc((size_t)m * K);
+        RG_HIP(hipMemcpyAsync(hid.data(), cid.p, sizeof(uint32_t) * hid.size(), hipMemcpyDeviceToHost, st));
+        RG_HIP(hipMemcpyAsync(hsc.data(), csc.p, sizeof(float) * hsc.size(), hipMemcpyDeviceToHost, st));
+        RG_HIP(hipStreamSynchronize(st));
+        std::vector<uint8_t> ok((size_t)m, 0);
+        par_rows(m, threads, [&](int64_t i) {
+            const int64_t q = rows[i];
+            const float *t = Qhost + q * d;
+            struct C {
+                double d;
+                uint32_t id;
+            };
+            std::vector<C> c;
+            c.reserve((size_t)K);
+            for (int j = 0; j < K; ++j) {
+                const uint32_t id = hid[i * K + j];
+                if (id != kNone) c.push_back(C{canon_dist(t, Xhost + (int64_t)id * d, d), id});
+            }
+            std::sort(c.begin(), c.end(), [](const C &a, const C &b) { return a.d < b.d || (a.d == b.d && a.id < b.id); });
+            bool certified = (int64_t)K >= n;
+            if (!certified && (int)c.size() >= k) {
+                double tn = 0.0;
+                for (int j = 0; j < d; ++j) tn += (double)t[j] * (double)t[j];
+                const double tau = (g32 + g64) * std::sqrt(tn) * (1.0 + 1e-12) * xmax;
+                const double sigma = (double)hsc[i * K + K - 1];
+                const double sk = -c[k - 1].d;
+                certified = sigma + tau < sk;
+            }
+            if (!certified) return;
+            ok[i] = 1;
+            for (int j = 0; j < k && j < (int)c.size(); ++j) {
+                (*ids_out)[q * k + j] = c[j].id;
+                if (d_out) (*d_out)[q * k + j] = c[j].d;
+            }
+        });
+        std::vector<int64_t> fail;
+        for (int64_t i = 0; i < m; ++i)
+            if (!ok[i]) fail.push_back(rows[i]);
+        if (fail.empty()) return RG_OK;
+        if (K >= 256 || K >= n) {
+            set_error("knn: " + std::to_string(fail.size()) + " rows could not be certified with 256 candidates");
+            return RG_EINTERNAL;
+        }
+        K = (int32_t)std::min<int64_t>(std::min<int64_t>(256, n), 2 * (int64_t)K);
+        rows.swap(fail);
+    }
+}
+
+}  // namespace rg
+
+using namespace rg;
+
+extern "C" {
+
+const char *rg_last_error(void) { return g_err.c_str(); }
+
+int rg_knn_candidates(const float *queries, int64_t nq, const float *base, int64_t n, int32_t d, int32_t K,
+                      uint32_t *ids, float *scores, void *stream) {
+    if (!queries || !base || !ids || !scores || nq < 0 || n < 1 || d < 1 || K < 1 || K > n) {
+        set_error("rg_knn_candidates: invalid argument");
+        return RG_EINVAL;
+    }
+    return launch_knn_candidates(queries, nq, d, base, n, d, d, K, ids, scores, (hipStream_t)stream);
+}
+
+int rg_knn(const float *queries, int64_t nq, const float *base, int64_t n, int32_t d, int32_t k, uint32_t *ids,
+           float *dists, void *stream) {
+    if (!queries || !base || !ids || !dists || nq < 0 || n < 1 || d < 1 || k < 1 || k > n || k > 224 ||
+        n >= (1ll << 31)) {
+        set_error("rg_knn: invalid argument (need 1 <= k <= min(n, 224), n < 2^31)");
+        return RG_EINVAL;
+    }
+    if (nq == 0) return RG_OK;
+    hipStream_t st = (hipStream_t)stream;
+    std::vector<float> qh, xh;
+    int rc = copy_to_host(queries, nq * d, qh, st);
+    if (!rc) rc = copy_to_host(base, n * d, xh, st);
+    if (rc) return rc;
+    std::vector<uint32_t> hid;
+    std::vector<double> hd;
+    rc = knn_exact(queries, nq, base, n, d, k, 0, qh.data(), xh.data(), 0, &hid, &hd, st);
+    if (rc) return rc;
+    std::vector<float> hdf(hd.size());
+    for (size_t i = 0; i < hd.size(); ++i) hdf[i] = (float)hd[i];
+    RG_HIP(hipMemcpyAsync(ids, hid.data(), sizeof(uint32_t) * hid.size(), hipMemcpyHostToDevice, st));
+    RG_HIP(hipMemcpyAsync(dists, hdf.data(), sizeof(float) * hdf.size(), hipMemcpyHostToDevice, st));
+    RG_HIP(hipStreamSynchronize(st));
+    return RG_OK;
+}
+
+int rg_build(const float *base, int64_t n, int32_t d, const float *train, int64_t nt, int32_t Nq, int32_t M,
+             int32_t metric, const rg_build_opts *opts, void *stream, rg_index **out) {
+    if (!base || !train || !out || n < 1 || n >= (1ll << 31) || d < 1 || nt < 1 || Nq < 2 || Nq > n || M < 3 ||
+        M > kMaxEll || metric != RG_METRIC_IP || Nq > 224) {
+        set_error("rg_build: invalid argument");
+        return RG_EINVAL;
+    }
+    *out = nullptr;
+    rg_build_opts o{};
+    if (opts) o = *opts;
+    const int32_t L = o.L_build > 0 ? o.L_build : 500;
+    const int32_t m_pj = o.m_pj > 0 ? o.m_pj : M / 2;
+    const int32_t m_ce = o.m_ce > 0 ? o.m_ce : (M - 1) / 2;
+    if (m_pj + m_ce > M - 1) {
+        set_error("rg_build: m_pj + m_ce must be <= M - 1");
+        return RG_EINVAL;
+    }
+    hipStream_t st = (hipStream_t)stream;
+    const int threads = hw_threads(o.threads);
+    const auto t0 = std::chrono::steady_clock::now();
+    std::vector<float> xh, th;
+    int rc = copy_to_host(base, n * d, xh, st);
+    if (!rc) rc = copy_to_host(train, nt * d, th, st);
+    if (rc) return rc;
+    std::vector<uint32_t> knn;
+    rc = knn_exact(train, nt, base, n, d, Nq, o.knn_slack, th.data(), xh.data(), threads, &knn, nullptr, st);
+    if (rc) return rc;
+    th.clear();
+    th.shrink_to_fit();
+    const auto t1 = std::chrono::steady_clock::now();
+    HostGraph g;
+    rc = host_construct(xh.data(), n, d, knn.data(), nt, Nq, M, L, m_pj, m_ce, threads, &g);
+    if (rc) return rc;
+    rg_index *ix = new rg_index();
+    ix->n = n;
+    ix->d = d;
+    ix->metric = metric;
+    ix->entry = g.entry;
+    ix->Nq = Nq;
+    ix->M = M;
+    ix->L_build = L;
+    ix->m_pj = m_pj;
+    ix->m_ce = m_ce;
+    ix->repairs = g.repairs;
+    ix->offsets.swap(g.offsets);
+    ix->indices.swap(g.indices);
+    (void)hipGetDevice(&ix->device);
+    rc = upload_index(ix, base, st);
+    if (rc) {
+        free_index_device(ix);
+        delete ix;
+        return rc;
+    }
+    const auto t2 = std::chrono::steady_clock::now();
+    ix->t_knn = std::chrono::duration<double>(t1 - t0).count();
+    ix->t_project = g.t_project;
+    ix->t_enhance = g.t_enhance;
+    ix->t_total = std::chrono::duration<double>(t2 - t0).count();
+    *out = ix;
+    return RG_OK;
+}
+
+int rg_build_from_knn(const float *base_host, int64_t n, int32_t d, const uint32_t *knn_host, int64_t nt,
+                      int32_t Nq, int32_t M, const rg_build_opts *opts, rg_index **out) {
+    if (!base_host || !knn_host || !out || n < 1 || n >= (1ll << 31) || d < 1 || nt < 1 || Nq < 2 || Nq > n ||
+        M < 3 || M > kMaxEll) {
+        set_error("rg_build_from_knn: invalid argument");
+        return RG_EINVAL;
+    }
+    *out = nullptr;
+    for (int64_t i = 0; i < nt * (int64_t)Nq; ++i)
+        if (knn_host[i] >= (uint64_t)n) {
+            set_error("rg_build_from_knn: kNN id out of range");
+            return RG_EINVAL;
+        }
+    rg_build_opts o{};
+    if (opts) o = *opts;
+    const int32_t L = o.L_build > 0 ? o.L_build : 500;
+    const int32_t m_pj = o.m_pj > 0 ? o.m_pj : M / 2;
+    const int32_t m_ce = o.m_ce > 0 ? o.m_ce : (M - 1) / 2;
+    if (m_pj + m_ce > M - 1) {
+        set_error("rg_build_from_knn: m_pj + m_ce must be <= M - 1");
+        return RG_EINVAL;
+    }
+    HostGraph g;
+    const int rc = host_construct(base_host, n, d, knn_host, nt, Nq, M, L, m_pj, m_ce, hw_threads(o.threads), &g);
+    if (rc) return rc;
+    rg_index *ix = new rg_index();
+    ix->n = n;
+    ix->d = d;
+    ix->entry = g.entry;
+    ix->Nq = Nq;
+    ix->M = M;
+    ix->L_build = L;
+    ix->m_pj = m_pj;
+    ix->m_ce = m_ce;
+    ix->repairs = g.repairs;
+    ix->offsets.swap(g.offsets);
+    ix->indices.swap(g.indices);
+    ix->t_project = g.t_project;
+    ix->t_enhance = g.t_enhance;
+    ix->t_total = g.t_total;
+    *out = ix;
+    return RG_OK;
+}
+
+int rg_index_from_csr(const float *base, int64_t n, int32_t d, const int64_t *offsets, const uint32_t *indices,
+                      uint32_t entry, int32_t metric, void *stream, rg_index **out) {
+    if (!base || !offsets || !out || n < 1 || n >= (1ll << 31) || d < 1 || metric != RG_METRIC_IP ||
+        (offsets[n] > 0 && !indices)) {
+        set_error("rg_index_from_csr: invalid argument");
+        return RG_EINVAL;
+    }
+    *out = nullptr;
+    if (check_csr(n, offsets, indices, entry)) {
+        set_error("rg_index_from_csr: malformed CSR or entry");
+        return RG_EINVAL;
+    }
+    rg_index *ix = new rg_index();
+    ix->n = n;
+    ix->d = d;
+    ix->metric = metric;
+    ix->entry = entry;
+    ix->offsets.assign(offsets, offsets + n + 1);
+    ix->indices.assign(indices, indices + offsets[n]);
+    (void)hipGetDevice(&ix->device);
+    const int rc = upload_index(ix, base, (hipStream_t)stream);
+    if (rc) {
+        free_index_device(ix);
+        delete ix;
+        return rc;
+    }
+    *out = ix;
+    return RG_OK;
+}
+
+int rg_index_graph(const rg_index *ix, const int64_t **offsets, const uint32_t **indices, int64_t *nnz,
+                   uint32_t *entry) {
+    if (!ix) {
+        set_error("rg_index_graph: null index");
+        return RG_EINVAL;
+    }
+    if (offsets) *offsets = ix->offsets.data();
+    if (indices) *indices = ix->indices.data();
+    if (nnz) *nnz = ix->offsets[ix->n];
+    if (entry) *entry = ix->entry;
+    return RG_OK;
+}
+
+int rg_index_info(const rg_index *ix, int64_t *n, int32_t *d, int32_t *pitch, int32_t *ell, int64_t *bytes) {
+    if (!ix) {
+        set_error("rg_index_info: null index");
+        return RG_EINVAL;
+    }
+    if (n) *n = ix->n;
+    if (d) *d = ix->d;
+    if (pitch) *pitch = ix->pitch;
+    if (ell) *ell = ix->ell;
+    if (bytes) {
+        int64_t b = (int64_t)ix->n * ix->pitch * 4 + (int64_t)ix->n * ix->ell * 4;
+        if (ix->d_bf16) b += (int64_t)ix->n * ix->pitch * 2;
+        if (ix->d_fp8) b += (int64_t)ix->n * ix->pitch8 + ix->n * 4;
+        *bytes = b;
+    }
+    return RG_OK;
+}
+
+// build statistics: seconds for kNN, projection, enhancement, total; repairs
+int rg_index_build_stats(const rg_index *ix, double *t_knn, double *t_project, double *t_enhance, double *t_total,
+                         int64_t *repairs) {
+    if (!ix) return RG_EINVAL;
+    if (t_knn) *t_knn = ix->t_knn;
+    if (t_project) *t_project = ix->t_project;
+    if (t_enhance) *t_enhance = ix->t_enhance;
+    if (t_total) *t_total = ix->t_total;
+    if (repairs) *repairs = ix->repairs;
+    return RG_OK;
+}
+
+int rg_index_set_storage(rg_index *ix, int32_t storage, void *stream) {
+    if (!ix || !ix->d_base || storage < RG_STORE_FP32 || storage > RG_STORE_FP8E4M3) {
+        set_error("rg_index_set_storage: invalid argument");
+        return RG_EINVAL;
+    }
+    hipStream_t st = (hipStream_t)stream;
+    if (storage == RG_STORE_BF16 && !ix->d_bf16) {
+        if (hipMalloc(&ix->d_bf16, sizeof(uint16_t) * (size_t)ix->n * ix->pitch) != hipSuccess) {
+            ix->d_bf16 = nullptr;
+            set_error("set_storage: out of device memory");
+            return RG_ENOMEM;
+        }
+        const int rc = launch_quant_bf16(ix->d_base, ix->n, ix->pitch, ix->d_bf16, st);
+        if (rc) return rc;
+    }
+    if (storage == RG_STORE_FP8E4M3 && !ix->d_fp8) {
+        ix->pitch8 = round_up(ix->d, 64);
+        if (hipMalloc(&ix->d_fp8, (size_t)ix->n * ix->pitch8) != hipSuccess ||
+            hipMalloc(&ix->d_scale, sizeof(float) * (size_t)ix->n) != hipSuccess) {
+            if (ix->d_fp8) (void)hipFree(ix->d_fp8);
+            ix->d_fp8 = nullptr;
+            ix->d_scale = nullptr;
+            set_error("set_storage: out of device memory");
+            return RG_ENOMEM;
+        }
+        const int rc = launch_quant_fp8(ix->d_base, ix->n, ix->d, ix->pitch, ix->d_fp8, ix->pitch8, ix->d_scale, st);
+        if (rc) return rc;
+    }
+    RG_HIP(hipStreamSynchronize(st));
+    ix->storage = storage;
+    return RG_OK;
+}
+
+// Device copies of the reduced-precision rows (for tests): codes/scales or bf16 bits.
+int rg_index_storage_ptrs(const rg_index *ix, const void **bf16, const void **fp8, const float **scales,
+                          int32_t *pitch8) {
+    if (!ix) return RG_EINVAL;
+    if (bf16) *bf16 = ix->d_bf16;
+    if (fp8) *fp8 = ix->d_fp8;
+    if (scales) *scales = ix->d_scale;
+    if (pitch8) *pitch8 = ix->pitch8;
+    return RG_OK;
+}
+
+int rg_search(const rg_index *ix, const float *queries, int64_t nq, int32_t k, int32_t L, uint32_t *ids,
+              float *dists, uint32_t *hops, uint32_t *evals, void *stream) {
+    if (!ix || nq < 0 || (nq > 0 && (!queries || !ids || !dists)) || k < 1 || L < 1 || k > kMaxL || L > kMaxL ||
+        nq >= (1ll << 31)) {
+        set_error("rg_search: invalid argument (need 1 <= k, L <= 512)");
+        return RG_EINVAL;
+    }
+    if (!ix->d_base) {
+        set_error("rg_search: index has no device data (built by rg_build_from_knn)");
+        return RG_EINVAL;
+    }
+    SearchArgs a{};
+    a.base = ix->d_base;
+    a.base_bf16 = ix->d_bf16;
+    a.base_fp8 = ix->d_fp8;
+    a.scale_fp8 = ix->d_scale;
+    a.adj = ix->d_adj;
+    a.queries = queries;
+    a.out_ids = ids;
+    a.out_d = dists;
+    a.out_hops = hops;
+    a.out_evals = evals;
+    a.nq = nq;
+    a.d = ix->d;
+    a.pitch = ix->pitch;
+    a.pitch8 = ix->pitch8;
+    a.ell = ix->ell;
+    a.k = k;
+    a.Leff = std::max(k, L);
+    a.hash_bits = default_hash_bits(a.Leff);
+    a.entry = ix->entry;
+    a.storage = ix->storage;
+    return launch_search(a, (hipStream_t)stream);
+}
+
+// Same as rg_search with an explicit visited-table size (2^hash_bits
+// entries, 8..15); used to check that the table size never changes results.
+int rg_search_hashbits(const rg_index *ix, const float *queries, int64_t nq, int32_t k, int32_t L, uint32_t *ids,
+                       float *dists, uint32_t *hops, uint32_t *evals, int32_t hash_bits, void *stream) {
+    if (hash_bits < 8 || hash_bits > 15) {
+        set_error("rg_search_hashbits: hash_bits must be in [8, 15]");
+        return RG_EINVAL;
+    }
+    if (!ix || nq < 0 || (nq > 0 && (!queries || !ids || !dists)) || k < 1 || L < 1 || k > kMaxL || L > kMaxL) {
+        set_error("rg_search_hashbits: invalid argument");
+        return RG_EINVAL;
+    }
+    if (!ix->d_base) {
+        set_error("rg_search_hashbits: index has no device data");
+        return RG_EINVAL;
+    }
+    if ((1 << hash_bits) < 2 * ix->ell + 2) {
+        set_error("rg_search_hashbits: table too small for the row width");
+        return RG_EINVAL;
+    }
+    SearchArgs a{};
+    a.base = ix->d_base;
+    a.base_bf16 = ix->d_bf16;
+    a.base_fp8 = ix->d_fp8;
+    a.scale_fp8 = ix->d_scale;
+    a.adj = ix->d_adj;
+    a.queries = queries;
+    a.out_ids = ids;
+    a.out_d = dists;
+    a.out_hops = hops;
+    a.out_evals = evals;
+    a.nq = nq;
+    a.d = ix->d;
+    a.pitch = ix->pitch;
+    a.pitch8 = ix->pitch8;
+    a.ell = ix->ell;
+    a.k = k;
+    a.Leff = std::max(k, L);
+    a.hash_bits = hash_bits;
+    a.entry = ix->entry;
+    a.storage = ix->storage;
+    return launch_search(a, (hipStream_t)stream);
+}
+
+int rg_save(const rg_index *ix, const char *path) {
+    if (!ix || !path || !ix->d_base) {
+        set_error("rg_save: invalid argument");
+        return RG_EINVAL;
+    }
+    std::vector<float> base((size_t)ix->n * ix->d);
+    RG_HIP(hipMemcpy2D(base.data(), sizeof(float) * ix->d, ix->d_base, sizeof(float) * ix->pitch,
+                       sizeof(float) * ix->d, (size_t)ix->n, hipMemcpyDeviceToHost));
+    FILE *f = std::fopen(path, "wb");
+    if (!f) {
+        set_error(std::string("rg_save: cannot open ") + path);
+        return RG_EINVAL;
+    }
+    uint64_t h = 1469598103934665603ull;
+    auto put = [&](const void *p, size_t nb) {
+        h = fnv1a(h, p, nb);
+        return std::fwrite(p, 1, nb, f) == nb;
+    };
+    const char magic[8] = {'R', 'G', 'I', 'D', 'X', 0, 0, 1};
+    const int64_t nnz = ix->offsets[ix->n];
+    const int32_t hdr[8] = {ix->d, ix->metric, (int32_t)ix->entry, ix->Nq, ix->M, ix->L_build, ix->m_pj, ix->m_ce};
+    bool ok = put(magic, 8) && put(&ix->n, 8) && put(hdr, sizeof(hdr)) && put(&ix->repairs, 8) && put(&nnz, 8) &&
+              put(ix->offsets.data(), sizeof(int64_t) * ix->offsets.size()) &&
+              put(ix->indices.data(), sizeof(uint32_t) * ix->indices.size()) &&
+              put(base.data(), sizeof(float) * base.size());
+    ok = ok && std::fwrite(&h, 1, 8, f) == 8;
+    ok = (std::fclose(f) == 0) && ok;
+    if (!ok) {
+        set_error("rg_save: write failed");
+        return RG_EINVAL;
+    }
+    return RG_OK;
+}
+
+int rg_load(const char *path, void *stream, rg_index **out) {
+    if (!path || !out) {
+        set_error("rg_load: invalid argument");
+        return RG_EINVAL;
+    }
+    *out = nullptr;
+    FILE *f = std::fopen(path, "rb");
+    if (!f) {
+        set_error(std::string("rg_load: cannot open ") + path);
+        return RG_EINVAL;
+    }
+    uint64_t h = 1469598103934665603ull;
+    auto get = [&](void *p, size_t nb) {
+        if (std::fread(p, 1, nb, f) != nb) return false;
+        h = fnv1a(h, p, nb);
+        return true;
+    };
+    char magic[8];
+    int64_t n = 0, repairs = 0, nnz = 0;
+    int32_t hdr[8];
+    const char want[8] = {'R', 'G', 'I', 'D', 'X', 0, 0, 1};
+    bool ok = get(magic, 8) && std::memcmp(magic, want, 8) == 0 && get(&n, 8) && get(hdr, sizeof(hdr)) &&
+              get(&repairs, 8) && get(&nnz, 8) && n >= 1 && n < (1ll << 31) && hdr[0] >= 1 && nnz >= 0 &&
+              nnz <= n * (int64_t)kMaxEll;
+    rg_index *ix = nullptr;
+    std::vector<float> base;
+    if (ok) {
+        ix = new rg_index();
+        ix->n = n;
+        ix->d = hdr[0];
+        ix->metric = hdr[1];
+        ix->entry = (uint32_t)hdr[2];
+        ix->Nq = hdr[3];
+        ix->M = hdr[4];
+        ix->L_build = hdr[5];
+        ix->m_pj = hdr[6];
+        ix->m_ce = hdr[7];
+        ix->repairs = repairs;
+        ix->offsets.resize((size_t)n + 1);
+        ix->indices.resize((size_t)nnz);
+        base.resize((size_t)n * ix->d);
+        ok = get(ix->offsets.data(), sizeof(int64_t) * (size_t)(n + 1)) &&
+             get(ix->indices.data(), sizeof(uint32_t) * (size_t)nnz) && get(base.data(), sizeof(float) * base.size());
+    }
+    uint64_t stored = 0;
+    const uint64_t computed = h;
+    ok = ok && std::fread(&stored, 1, 8, f) == 8 && stored == computed;
+    std::fclose(f);
+    if (!ok || ix->offsets[n] != nnz || check_csr(n, ix->offsets.data(), ix->indices.data(), ix->entry)) {
+        delete ix;
+        set_error("rg_load: corrupt index file");
+        return RG_ECORRUPT;
+    }
+    hipStream_t st = (hipStream_t)stream;
+    DevBuf tmp;
+    int rc = tmp.alloc(sizeof(float) * base.size());
+    if (!rc && hipMemcpyAsync(tmp.p, base.data(), sizeof(float) * base.size(), hipMemcpyHostToDevice, st) != hipSuccess)
+        rc = RG_EDEVICE;
+    (void)hipGetDevice(&ix->device);
+    if (!rc) rc = upload_index(ix, tmp.as<float>(), st);
+    if (rc) {
+        free_index_device(ix);
+        delete ix;
+        return rc;
+    }
+    *out = ix;
+    return RG_OK;
+}
+
+void rg_free(rg_index *ix) {
+    if (!ix) return;
+    free_index_device(ix);
+    delete ix;
+}
+
+}  // extern "C"

@@ -1,0 +1,578 @@
+// Batched beam search over the RoarGraph index (Sec. 4.3), one 64-lane
+// wavefront (= one workgroup) per query on gfx950.
+//
+// Per query, in LDS:
+//   * the queue: the best L_eff (delta, id) pairs seen, sorted ascending, the
+//     id's top bit marking "expanded";
+//   * an open-addressing visited table of node ids.  When it passes half
+//     load it is cleared; a node seen again is then scored again and dropped
+//     at the merge if it is already queued.  Because the queue's last key
+//     only decreases once the queue is full, a forgotten node that was
+//     rejected or evicted is rejected again, so clearing changes only the
+//     work done, never the result;
+//   * the candidate batch of the current expansion.
+// Per expansion: pick the first unexpanded queue entry, read its adjacency
+// row (ELL, one id per lane), filter through the visited table, gather the
+// new neighbours' rows (G lanes per row, float4 loads, coalesced), reduce
+// the FP32 dot products inside each G-lane group with xor shuffles, sort the
+// batch in registers, and merge the entries that beat the queue's last key.
+// The search stops when every queue entry is expanded.
+//
+// Dot products: lane j of a group accumulates, with fused multiply-adds in
+// order, the coordinates 4c..4c+3 of chunks c = j, j+G, j+2G, ...; then the
+// G partial sums are added by a log2(G)-level xor tree.  A distance is
+// therefore a fixed function of (query, row) whichever group computes it.
+#include "rg_internal.h"
+#include "wave_ops.h"
+
+#include <climits>
+
+namespace rg {
+namespace {
+
+constexpr uint32_t kEmpty = 0xFFFFFFFFu;
+constexpr int kCand = 128;  // candidate-batch capacity (>= the largest ELL width)
+
+struct Lds {
+    float *qd;
+    uint32_t *qi;
+    float *cd;
+    uint32_t *ci;
+    float *sd;
+    uint32_t *si;
+    int32_t *slb;
+    uint32_t *htab;
+};
+
+__device__ __forceinline__ Lds carve(unsigned char *p, int Leff) {
+    Lds s;
+    s.qd = reinterpret_cast<float *>(p);
+    s.qi = reinterpret_cast<uint32_t *>(s.qd + Leff);
+    s.cd = reinterpret_cast<float *>(s.qi + Leff);
+    s.ci = reinterpret_cast<uint32_t *>(s.cd + kCand);
+    s.sd = reinterpret_cast<float *>(s.ci + kCand);
+    s.si = reinterpret_cast<uint32_t *>(s.sd + kCand);
+    s.slb = reinterpret_cast<int32_t *>(s.si + kCand);
+    s.htab = reinterpret_cast<uint32_t *>(s.slb + kCand);
+    return s;
+}
+
+__device__ __forceinline__ float e4m3_to_f32(uint32_t b) {
+    const uint32_t sgn = (b & 0x80u) << 24;
+    const uint32_t e = (b >> 3) & 15u, m = b & 7u;
+    const float sub = (float)m * 0.001953125f;  // m * 2^-9
+    const float nrm = __uint_as_float(sgn | ((e + 120u) << 23) | (m << 20));
+    return e == 0 ? (sgn ? -sub : sub) : nrm;
+}
+
+template <int G, int NCH>
+__device__ __forceinline__ void load_query(const float *q, int d, float4 (&qv)[NCH]) {
+    const int j = lane_id() % G;
+#pragma unroll
+    for (int t = 0; t < NCH; ++t) {
+        const int e = 4 * (j + G * t);
+        qv[t].x = e + 0 < d ? q[e + 0] : 0.f;
+        qv[t].y = e + 1 < d ? q[e + 1] : 0.f;
+        qv[t].z = e + 2 < d ? q[e + 2] : 0.f;
+        qv[t].w = e + 3 < d ? q[e + 3] : 0.f;
+    }
+}
+
+// This lane's partial dot product of the query with row u (kNone -> 0).
+template <int G, int NCH, int ST>
+__device__ __forceinline__ float row_partial(const SearchArgs &a, uint32_t u, const float4 (&qv)[NCH],
+                                             int nch) {
+    float acc = 0.f;
+    if (u == kNone) return acc;
+    const int j = lane_id() % G;
+    if constexpr (ST == RG_STORE_FP32) {
+        const float4 *row = reinterpret_cast<const float4 *>(a.base + (size_t)u * a.pitch);
+        float4 x[NCH];
+#pragma unroll
+        for (int t = 0; t < NCH; ++t) {
+            const int c = j + G * t;
+            x[t] = c < nch ? row[c] : make_float4(0.f, 0.f, 0.f, 0.f);
+        }
+#pragma unroll
+        for (int t = 0; t < NCH; ++t) {
+            acc = fmaf(qv[t].x, x[t].x, acc);
+            acc = fmaf(qv[t].y, x[t].y, acc);
+            acc = fmaf(qv[t].z, x[t].z, acc);
+            acc = fmaf(qv[t].w, x[t].w, acc);
+        }
+    } else if constexpr (ST == RG_STORE_BF16) {
+        const uint2 *row = reinterpret_cast<const uint2 *>(a.base_bf16 + (size_t)u * a.pitch);
+        uint2 x[NCH];
+#pragma unroll
+        for (int t = 0; t < NCH; ++t) {
+            const int c = j + G * t;
+            x[t] = c < nch ? row[c] : make_uint2(0u, 0u);
+        }
+#pragma unroll
+        for (int t = 0; t < NCH; ++t) {
+            acc = fmaf(qv[t].x, __uint_as_float(x[t].x << 16), acc);
+            acc = fmaf(qv[t].y, __uint_as_float(x[t].x & 0xFFFF0000u), acc);
+            acc = fmaf(qv[t].z, __uint_as_float(x[t].y << 16), acc);
+            acc = fmaf(qv[t].w, __uint_as_float(x[t].y & 0xFFFF0000u), acc);
+        }
+    } else {
+        const uint32_t *row = reinterpret_cast<const uint32_t *>(a.base_fp8 + (size_t)u * a.pitch8);
+        uint32_t x[NCH];
+#pragma unroll
+        for (int t = 0; t < NCH; ++t) {
+            const int c = j + G * t;
+            x[t] = c < nch ? row[c] : 0u;
+        }
+#pragma unroll
+        for (int t = 0; t < NCH; ++t) {
+            acc = fmaf(qv[t].x, e4m3_to_f32(x[t] & 0xFFu), acc);
+            acc = fmaf(qv[t].y, e4m3_to_f32((x[t] >> 8) & 0xFFu), acc);
+            acc = fmaf(qv[t].z, e4m3_to_f32((x[t] >> 16) & 0xFFu), acc);
+            acc = fmaf(qv[t].w, e4m3_to_f32(x[t] >> 24), acc);
+        }
+    }
+    return acc;
+}
+
+template <int G>
+__device__ __forceinline__ float group_sum(float v) {
+#pragma unroll
+    for (int o = G / 2; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    return v;
+}
+
+// delta of this group's row u (uniform within the group)
+template <int G, int ST>
+__device__ __forceinline__ float finish_delta(const SearchArgs &a, uint32_t u, float sum) {
+    if constexpr (ST == RG_STORE_FP8E4M3) {
+        const float s = u == kNone ? 1.f : a.scale_fp8[u];
+        return -(s * sum);
+    } else {
+        return -sum;
+    }
+}
+
+// Score ids[0..cnt) (LDS) into dout[0..cnt) (LDS); two rows per group in flight.
+template <int G, int NCH, int ST>
+__device__ __forceinline__ void score_batch(const SearchArgs &a, const float4 (&qv)[NCH], int nch,
+                                            const uint32_t *ids, uint32_t idmask, float *dout, int cnt) {
+    constexpr int NG = 64 / G;
+    const int g = lane_id() / G, j = lane_id() % G;
+    for (int p = 0; p < cnt; p += 2 * NG) {
+        const int s0 = p + g, s1 = p + NG + g;
+        const uint32_t u0 = s0 < cnt ? (ids[s0] & idmask) : kNone;
+        const uint32_t u1 = s1 < cnt ? (ids[s1] & idmask) : kNone;
+        float a0 = row_partial<G, NCH, ST>(a, u0, qv, nch);
+        float a1 = row_partial<G, NCH, ST>(a, u1, qv, nch);
+        a0 = group_sum<G>(a0);
+        a1 = group_sum<G>(a1);
+        if (j == 0) {
+            if (s0 < cnt) dout[s0] = finish_delta<G, ST>(a, u0, a0);
+            if (s1 < cnt) dout[s1] = finish_delta<G, ST>(a, u1, a1);
+        }
+    }
+}
+
+__device__ __forceinline__ int lower_bound_q(const float *qd, const uint32_t *qi, int qn, float kd,
+                                             uint32_t kid) {
+    int lo = 0, hi = qn;
+    while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (kless(qd[mid], qi[mid] & ~kExpanded, kd, kid))
+            lo = mid + 1;
+        else
+            hi = mid;
+    }
+    return lo;
+}
+
+// #{t < S : slb[t] <= i}, slb non-decreasing
+__device__ __forceinline__ int count_le(const int32_t *slb, int S, int i) {
+    int lo = 0, hi = S;
+    while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (slb[mid] <= i)
+            lo = mid + 1;
+        else
+            hi = mid;
+    }
+    return lo;
+}
+
+// Merge the candidate batch s.cd/s.ci[0..cnt) into the queue.
+template <int E>
+__device__ __forceinline__ void merge_batch(const Lds &s, int cnt, int Leff, int &qn, int &ptr) {
+    const int lane = lane_id();
+    float k[E];
+    uint32_t id[E];
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+        const int i = lane * E + e;
+        k[e] = i < cnt ? s.cd[i] : __builtin_inff();
+        id[e] = i < cnt ? s.ci[i] : kNone;
+    }
+    wave_sort<E>(k, id);
+    const bool full = qn == Leff;
+    const float lastd = full ? s.qd[Leff - 1] : 0.f;
+    const uint32_t lasti = full ? (s.qi[Leff - 1] & ~kExpanded) : 0u;
+    int lb[E];
+    bool sv[E];
+    int mine = 0;
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+        sv[e] = id[e] != kNone && (!full || kless(k[e], id[e], lastd, lasti));
+        lb[e] = 0;
+        if (sv[e]) {
+            lb[e] = lower_bound_q(s.qd, s.qi, qn, k[e], id[e]);
+            if (lb[e] < qn && (s.qi[lb[e]] & ~kExpanded) == id[e]) sv[e] = false;  // already queued
+        }
+        mine += sv[e] ? 1 : 0;
+    }
+    // order-preserving compaction: exclusive prefix of per-lane counts
+    int incl = mine;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const int t = __shfl_up(incl, o);
+        if (lane >= o) incl += t;
+    }
+    const int total = __shfl(incl, 63);
+    int w = incl - mine;
+    __syncthreads();
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+        if (sv[e]) {
+            s.sd[w] = k[e];
+            s.si[w] = id[e];
+            s.slb[w] = lb[e];
+            ++w;
+        }
+    }
+    __syncthreads();
+    if (total == 0) return;
+    const int lbmin = s.slb[0];
+    // entries of the queue that move, and their new places
+    constexpr int R = kMaxL / 64;
+    float md[R];
+    uint32_t mi[R];
+    int mp[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const int i = lbmin + lane + 64 * r;
+        mp[r] = INT_MAX;
+        if (i < qn) {
+            md[r] = s.qd[i];
+            mi[r] = s.qi[i];
+            mp[r] = i + count_le(s.slb, total, i);
+        }
+    }
+    float pd[2];
+    uint32_t pi[2];
+    int pp[2];
+#pragma unroll
+    for (int r = 0; r < 2; ++r) {
+        const int t = lane + 64 * r;
+        pp[r] = INT_MAX;
+        if (t < total) {
+            pd[r] = s.sd[t];
+            pi[r] = s.si[t];
+            pp[r] = s.slb[t] + t;
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < R; ++r)
+        if (mp[r] < Leff) {
+            s.qd[mp[r]] = md[r];
+            s.qi[mp[r]] = mi[r];
+        }
+#pragma unroll
+    for (int r = 0; r < 2; ++r)
+        if (pp[r] < Leff) {
+            s.qd[pp[r]] = pd[r];
+            s.qi[pp[r]] = pi[r];
+        }
+    qn = min(Leff, qn + total);
+    ptr = min(ptr, lbmin);
+    __syncthreads();
+}
+
+__device__ __forceinline__ uint32_t hslot(uint32_t u, int hb) { return (u * 2654435761u) >> (32 - hb); }
+
+// Expansions until done or `budget` expansions were made.
+template <int G, int NCH, int ST>
+__device__ __forceinline__ void run_search(const SearchArgs &a, const float4 (&qv)[NCH], const Lds &s, int &qn, int &ptr,
+                           int &hcount, uint32_t &hops, uint32_t &evals, int budget, bool &done) {
+    const int lane = lane_id();
+    const int Leff = a.Leff, ell = a.ell, nch = (a.d + 3) >> 2;
+    const int hb = a.hash_bits;
+    const int H = 1 << hb;
+    const uint32_t hmask = (uint32_t)H - 1u;
+    done = false;
+    for (; budget > 0; --budget) {
+        int sel = -1;
+        for (int b = ptr; b < qn; b += 64) {
+            const int i = b + lane;
+            const bool un = i < qn && !(s.qi[i] & kExpanded);
+            const uint64_t m = ballot64(un);
+            if (m) {
+                sel = b + (int)__builtin_ctzll(m);
+                break;
+            }
+        }
+        if (sel < 0) {
+            done = true;
+            break;
+        }
+        ptr = sel;
+        const uint32_t v = s.qi[sel];
+        __syncthreads();
+        if (lane == 0) s.qi[sel] = v | kExpanded;
+        ++hops;
+        if (hcount + ell > (H >> 1)) {
+            for (int i = lane; i < H; i += 64) s.htab[i] = kEmpty;
+            hcount = 0;
+            __syncthreads();
+        }
+        int nnew = 0;
+        for (int b = 0; b < ell; b += 64) {
+            const int e = b + lane;
+            const uint32_t u = e < ell ? a.adj[(size_t)v * ell + e] : kNone;
+            bool fresh = false;
+            if (u != kNone) {
+                uint32_t h = hslot(u, hb);
+                for (int probe = 0; probe < H; ++probe) {
+                    const uint32_t old = atomicCAS(&s.htab[h], kEmpty, u);
+                    if (old == kEmpty) {
+                        fresh = true;
+                        break;
+                    }
+                    if (old == u) break;
+                    h = (h + 1u) & hmask;
+                }
+            }
+            const uint64_t m = ballot64(fresh);
+            if (fresh) s.ci[nnew + lanes_below(m)] = u;
+            nnew += (int)__popcll(m);
+        }
+        hcount += nnew;
+        evals += (uint32_t)nnew;
+        __syncthreads();
+        if (nnew == 0) continue;
+        score_batch<G, NCH, ST>(a, qv, nch, s.ci, 0xFFFFFFFFu, s.cd, nnew);
+        __syncthreads();
+        if (nnew <= 64)
+            merge_batch<1>(s, nnew, Leff, qn, ptr);
+        else
+            merge_batch<2>(s, nnew, Leff, qn, ptr);
+    }
+}
+
+template <int G, int NCH, int ST>
+__device__ __forceinline__ void init_state(const SearchArgs &a, const float4 (&qv)[NCH], const Lds &s, int &qn, int &ptr,
+                           int &hcount, uint32_t &hops, uint32_t &evals) {
+    const int lane = lane_id();
+    const int H = 1 << a.hash_bits;
+    for (int i = lane; i < H; i += 64) s.htab[i] = kEmpty;
+    const uint32_t u = lane < G ? a.entry : kNone;
+    float acc = row_partial<G, NCH, ST>(a, u, qv, (a.d + 3) >> 2);
+    acc = group_sum<G>(acc);
+    __syncthreads();
+    if (lane == 0) {
+        s.qd[0] = finish_delta<G, ST>(a, a.entry, acc);
+        s.qi[0] = a.entry;
+        s.htab[hslot(a.entry, a.hash_bits)] = a.entry;
+    }
+    qn = 1;
+    ptr = 0;
+    hcount = 1;
+    hops = 0;
+    evals = 1;
+    __syncthreads();
+}
+
+// Rescore the final queue against FP32 rows and sort it (reduced-precision storage).
+template <int G, int NCH>
+__device__ __forceinline__ void rerank_queue(const SearchArgs &a, const float4 (&qv)[NCH], const Lds &s, int qn) {
+    score_batch<G, NCH, RG_STORE_FP32>(a, qv, (a.d + 3) >> 2, s.qi, ~kExpanded, s.qd, qn);
+    __syncthreads();
+    constexpr int E = kMaxL / 64;
+    const int lane = lane_id();
+    float k[E];
+    uint32_t id[E];
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+        const int i = lane * E + e;
+        k[e] = i < qn ? s.qd[i] : __builtin_inff();
+        id[e] = i < qn ? (s.qi[i] & ~kExpanded) : kNone;
+    }
+    wave_sort<E>(k, id);
+    __syncthreads();
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+        const int i = lane * E + e;
+        if (i < qn) {
+            s.qd[i] = k[e];
+            s.qi[i] = id[e];
+        }
+    }
+    __syncthreads();
+}
+
+template <int G, int NCH, int ST>
+__global__ __launch_bounds__(64) void k_search(SearchArgs a) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int64_t q = blockIdx.x;
+    const Lds s = carve(smem, a.Leff);
+    float4 qv[NCH];
+    load_query<G, NCH>(a.queries + q * a.d, a.d, qv);
+    int qn, ptr, hcount;
+    uint32_t hops, evals;
+    bool done;
+    init_state<G, NCH, ST>(a, qv, s, qn, ptr, hcount, hops, evals);
+    run_search<G, NCH, ST>(a, qv, s, qn, ptr, hcount, hops, evals, INT_MAX, done);
+    if constexpr (ST != RG_STORE_FP32) rerank_queue<G, NCH>(a, qv, s, qn);
+    const int lane = lane_id();
+    for (int i = lane; i < a.k; i += 64) {
+        a.out_ids[q * a.k + i] = i < qn ? (s.qi[i] & ~kExpanded) : kNone;
+        a.out_d[q * a.k + i] = i < qn ? s.qd[i] : __builtin_inff();
+    }
+    if (lane == 0) {
+        if (a.out_hops) a.out_hops[q] = hops;
+        if (a.out_evals) a.out_evals[q] = evals;
+    }
+}
+
+// One scheduler step of the serving loop: advance each listed slot by up to
+// hops_budget expansions, keeping its whole state in device memory.
+template <int G, int NCH, int ST>
+__global__ __launch_bounds__(64) void k_serve_step(SlotArgs sa) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int slot = sa.active[blockIdx.x];
+    SearchArgs a = sa.s;
+    a.k = sa.slot_k[slot];
+    a.Leff = max(sa.slot_L[slot], a.k);
+    const Lds s = carve(smem, a.Leff);
+    const int lane = lane_id();
+    const int H = 1 << a.hash_bits;
+    float4 qv[NCH];
+    load_query<G, NCH>(sa.slot_q + (size_t)slot * a.d, a.d, qv);
+    int32_t *st = sa.slot_state + (size_t)slot * 8;
+    float *gqd = sa.slot_qd + (size_t)slot * kMaxL;
+    uint32_t *gqi = sa.slot_qi + (size_t)slot * kMaxL;
+    uint32_t *gh = sa.slot_hash + ((size_t)slot << a.hash_bits);
+    int qn, ptr, hcount;
+    uint32_t hops, evals;
+    if (st[0] == 0) {
+        init_state<G, NCH, ST>(a, qv, s, qn, ptr, hcount, hops, evals);
+    } else {
+        qn = st[0];
+        ptr = st[1];
+        hcount = st[2];
+        hops = (uint32_t)st[3];
+        evals = (uint32_t)st[4];
+        for (int i = lane; i < qn; i += 64) {
+            s.qd[i] = gqd[i];
+            s.qi[i] = gqi[i];
+        }
+        for (int i = lane; i < H; i += 64) s.htab[i] = gh[i];
+        __syncthreads();
+    }
+    bool done;
+    run_search<G, NCH, ST>(a, qv, s, qn, ptr, hcount, hops, evals, sa.hops_budget, done);
+    if (done) {
+        if constexpr (ST != RG_STORE_FP32) rerank_queue<G, NCH>(a, qv, s, qn);
+        for (int i = lane; i < a.k; i += 64) {
+            sa.slot_out_ids[(size_t)slot * kMaxL + i] = i < qn ? (s.qi[i] & ~kExpanded) : kNone;
+            sa.slot_out_d[(size_t)slot * kMaxL + i] = i < qn ? s.qd[i] : __builtin_inff();
+        }
+    } else {
+        for (int i = lane; i < qn; i += 64) {
+            gqd[i] = s.qd[i];
+            gqi[i] = s.qi[i];
+        }
+        for (int i = lane; i < H; i += 64) gh[i] = s.htab[i];
+    }
+    if (lane == 0) {
+        st[0] = qn;
+        st[1] = ptr;
+        st[2] = hcount;
+        st[3] = (int32_t)hops;
+        st[4] = (int32_t)evals;
+        if (done) sa.slot_done[slot] = 1;
+    }
+}
+
+template <int G, int NCH, int ST>
+int launch_one(const SearchArgs &a, hipStream_t stream) {
+    const size_t lds = search_lds_bytes(a.Leff, a.ell, a.hash_bits);
+    hipLaunchKernelGGL((k_search<G, NCH, ST>), dim3((unsigned)a.nq), dim3(64), lds, stream, a);
+    RG_HIP(hipGetLastError());
+    return RG_OK;
+}
+
+template <int G, int NCH, int ST>
+int launch_step(const SlotArgs &sa, hipStream_t stream) {
+    const size_t lds = search_lds_bytes(kMaxL, sa.s.ell, sa.s.hash_bits);
+    hipLaunchKernelGGL((k_serve_step<G, NCH, ST>), dim3((unsigned)sa.n_active), dim3(64), lds, stream, sa);
+    RG_HIP(hipGetLastError());
+    return RG_OK;
+}
+
+// (G, NCH) for a dimension: G lanes per row, NCH float4 chunks per lane.
+template <template <int, int, int> class F, int ST, typename Arg>
+int dispatch_dim(int d, const Arg &a, hipStream_t stream) {
+    const int nch = (d + 3) / 4;
+    if (nch <= 16) return F<16, 1, ST>::run(a, stream);
+    if (nch <= 32) return F<16, 2, ST>::run(a, stream);
+    if (nch <= 56) return F<8, 7, ST>::run(a, stream);
+    if (nch <= 64) return F<16, 4, ST>::run(a, stream);
+    if (nch <= 128) return F<16, 8, ST>::run(a, stream);
+    if (nch <= 256) return F<32, 8, ST>::run(a, stream);
+    set_error("search: d > 1024 is not supported");
+    return RG_EINVAL;
+}
+
+template <int G, int NCH, int ST>
+struct SearchLaunch {
+    static int run(const SearchArgs &a, hipStream_t s) { return launch_one<G, NCH, ST>(a, s); }
+};
+template <int G, int NCH, int ST>
+struct StepLaunch {
+    static int run(const SlotArgs &a, hipStream_t s) { return launch_step<G, NCH, ST>(a, s); }
+};
+
+}  // namespace
+
+size_t search_lds_bytes(int Leff, int ell, int hash_bits) {
+    (void)ell;
+    return (size_t)Leff * 8 + (size_t)kCand * 20 + ((size_t)4 << hash_bits);
+}
+
+int default_hash_bits(int Leff) {
+    // table of about 16 entries per queue slot, 2^11 .. 2^13
+    int hb = 11;
+    while (hb < 13 && (1 << hb) < 16 * Leff) ++hb;
+    return hb;
+}
+
+int launch_search(const SearchArgs &a, hipStream_t stream) {
+    if (a.nq == 0) return RG_OK;
+    switch (a.storage) {
+    case RG_STORE_FP32: return dispatch_dim<SearchLaunch, RG_STORE_FP32>(a.d, a, stream);
+    case RG_STORE_BF16: return dispatch_dim<SearchLaunch, RG_STORE_BF16>(a.d, a, stream);
+    case RG_STORE_FP8E4M3: return dispatch_dim<SearchLaunch, RG_STORE_FP8E4M3>(a.d, a, stream);
+    default: set_error("search: unknown storage"); return RG_EINVAL;
+    }
+}
+
+int launch_serve_step(const SlotArgs &sa, hipStream_t stream) {
+    if (sa.n_active == 0) return RG_OK;
+    switch (sa.s.storage) {
+    case RG_STORE_FP32: return dispatch_dim<StepLaunch, RG_STORE_FP32>(sa.s.d, sa, stream);
+    case RG_STORE_BF16: return dispatch_dim<StepLaunch, RG_STORE_BF16>(sa.s.d, sa, stream);
+    case RG_STORE_FP8E4M3: return dispatch_dim<StepLaunch, RG_STORE_FP8E4M3>(sa.s.d, sa, stream);
+    default: set_error("serve: unknown storage"); return RG_EINVAL;
+    }
+}
+
+}  // namespace rg

@@ -1,0 +1,505 @@
+// Host side of index construction: bipartite graph, neighbourhood-aware
+// projection, medoid, connectivity enhancement, merge, reachability repair
+// and CSR (Algorithms 1-3, Sec. 4.2).  Written for many host threads with a
+// result that does not depend on the thread count.
+//
+// Distances are the canonical FP64 value: delta(a, b) = -sum_i a_i b_i with
+// the exact products added in increasing i (a float x float product is exact
+// in double, so contraction cannot change it).  All comparisons use the
+// total order (delta, id).
+//
+// Order of updates.  Both Algorithm 2 and the enhancement loop of
+// Algorithm 1 visit nodes x in ascending order, set x's own list (an
+// assignment) from data that does not change during the loop (the bridges'
+// kNN lists; the searches on the fixed projected graph), and then ask every
+// selected p to reconsider its list with x added.  Node p's list is
+// therefore touched only by (a) its own assignment at step p and (b) those
+// reverse insertions, in ascending step order; the assignment discards what
+// came before it.  So each p's final list is computed independently: start
+// from its own assignment (or empty, for a node that is never a pivot) and
+// replay, in ascending x, the reverse insertions from later steps.  This
+// gives exactly the serial result with every node processed in parallel.
+#include <algorithm>
+#include <atomic>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <thread>
+
+#include "rg_internal.h"
+
+namespace rg {
+namespace {
+
+using Clock = std::chrono::steady_clock;
+double secs(Clock::time_point a, Clock::time_point b) { return std::chrono::duration<double>(b - a).count(); }
+
+template <class F>
+void parallel_for(int64_t n, int threads, int64_t grain, F &&f) {
+    if (n <= 0) return;
+    threads = (int)std::max<int64_t>(1, std::min<int64_t>(threads, (n + grain - 1) / grain));
+    std::atomic<int64_t> next(0);
+    auto work = [&](int tid) {
+        for (;;) {
+            const int64_t s = next.fetch_add(grain);
+            if (s >= n) break;
+            const int64_t e = std::min(n, s + grain);
+            for (int64_t i = s; i < e; ++i) f(i, tid);
+        }
+    };
+    if (threads == 1) {
+        work(0);
+        return;
+    }
+    std::vector<std::thread> pool;
+    pool.reserve(threads);
+    for (int t = 0; t < threads; ++t) pool.emplace_back(work, t);
+    for (auto &th : pool) th.join();
+}
+
+// Eight canonical distances at once; each chain is its own left-to-right sum.
+void dist8(const float *q, const float *const r[8], int d, double out[8]) {
+    double s0 = 0, s1 = 0, s2 = 0, s3 = 0, s4 = 0, s5 = 0, s6 = 0, s7 = 0;
+    for (int i = 0; i < d; ++i) {
+        const double qi = (double)q[i];
+        s0 += qi * (double)r[0][i];
+        s1 += qi * (double)r[1][i];
+        s2 += qi * (double)r[2][i];
+        s3 += qi * (double)r[3][i];
+        s4 += qi * (double)r[4][i];
+        s5 += qi * (double)r[5][i];
+        s6 += qi * (double)r[6][i];
+        s7 += qi * (double)r[7][i];
+    }
+    out[0] = -s0;
+    out[1] = -s1;
+    out[2] = -s2;
+    out[3] = -s3;
+    out[4] = -s4;
+    out[5] = -s5;
+    out[6] = -s6;
+    out[7] = -s7;
+}
+
+// out[j] = delta(q, X[ids[j]]) for j < cnt
+void dist_batch(const float *X, int d, const float *q, const uint32_t *ids, int64_t cnt, double *out) {
+    int64_t j = 0;
+    for (; j + 8 <= cnt; j += 8) {
+        const float *r[8];
+        for (int t = 0; t < 8; ++t) r[t] = X + (int64_t)ids[j + t] * d;
+        dist8(q, r, d, out + j);
+    }
+    for (; j < cnt; ++j) out[j] = canon_dist(q, X + (int64_t)ids[j] * d, d);
+}
+
+struct Cand {
+    double d;
+    uint32_t id;
+};
+inline bool cless(const Cand &a, const Cand &b) { return a.d < b.d || (a.d == b.d && a.id < b.id); }
+
+// AcquireNeighbors (Algorithm 3) on candidates already ranked by (delta(x,c), c),
+// distinct and without x.  Writes the kept candidates (with delta(x,.)) to res.
+int acquire_sorted(const float *X, int d, const Cand *C, int nc, int m, bool fill, Cand *res,
+                   std::vector<uint8_t> &kept) {
+    if (nc <= 0 || m <= 0) return 0;
+    kept.assign((size_t)nc, 0);
+    int nr = 0;
+    res[nr++] = C[0];
+    kept[0] = 1;
+    for (int j = 1; j < nc && nr < m; ++j) {
+        const float *xc = X + (int64_t)C[j].id * d;
+        bool ok = true;
+        for (int r0 = 0; r0 < nr && ok; r0 += 8) {
+            const int cnt = std::min(8, nr - r0);
+            double dcp[8];
+            if (cnt == 8) {
+                const float *rows[8];
+                for (int t = 0; t < 8; ++t) rows[t] = X + (int64_t)res[r0 + t].id * d;
+                dist8(xc, rows, d, dcp);
+            } else {
+                for (int t = 0; t < cnt; ++t) dcp[t] = canon_dist(xc, X + (int64_t)res[r0 + t].id * d, d);
+            }
+            for (int t = 0; t < cnt; ++t)
+                if (!(C[j].d < dcp[t])) {
+                    ok = false;
+                    break;
+                }
+        }
+        if (ok) {
+            res[nr++] = C[j];
+            kept[j] = 1;
+        }
+    }
+    if (fill)
+        for (int j = 0; j < nc && nr < m; ++j)
+            if (!kept[j]) res[nr++] = C[j];
+    return nr;
+}
+
+// Fixed-capacity adjacency lists with their distances to the owner.
+struct Lists {
+    int cap = 0;
+    std::vector<Cand> a;
+    std::vector<int32_t> deg;
+    void init(int64_t n, int c) {
+        cap = c;
+        a.assign((size_t)n * c, Cand{0, 0});
+        deg.assign((size_t)n, 0);
+    }
+    Cand *row(int64_t x) { return a.data() + x * cap; }
+    const Cand *row(int64_t x) const { return a.data() + x * cap; }
+};
+
+// Events: for each target p, the ascending steps x whose selection contains p.
+void build_events(const Lists &sel, int64_t n, std::vector<int64_t> &off, std::vector<uint32_t> &src) {
+    off.assign((size_t)n + 1, 0);
+    for (int64_t x = 0; x < n; ++x)
+        for (int j = 0; j < sel.deg[x]; ++j) off[sel.row(x)[j].id + 1]++;
+    for (int64_t i = 0; i < n; ++i) off[i + 1] += off[i];
+    src.resize((size_t)off[n]);
+    std::vector<int64_t> fillp(off.begin(), off.end() - 1);
+    for (int64_t x = 0; x < n; ++x)  // ascending x => each target's events ascend
+        for (int j = 0; j < sel.deg[x]; ++j) src[fillp[sel.row(x)[j].id]++] = (uint32_t)x;
+}
+
+// Replay reverse insertions into p (see the file comment).
+//   start: p's own assignment (is_assigned) or empty.
+void replay(const float *X, int d, int64_t p, bool is_assigned, const Cand *start, int nstart,
+            const uint32_t *ev, int64_t nev, int m, bool fill, Cand *out, int32_t *outdeg,
+            std::vector<Cand> &cur, std::vector<Cand> &tmp, std::vector<uint8_t> &kept) {
+    cur.assign(start, start + nstart);
+    const float *xp = X + p * d;
+    for (int64_t e = 0; e < nev; ++e) {
+        const uint32_t x = ev[e];
+        if (is_assigned && (int64_t)x < p) continue;  // discarded by p's own assignment
+        bool present = false;
+        for (const Cand &c : cur)
+            if (c.id == x) {
+                present = true;
+                break;
+            }
+        if (!present) cur.push_back(Cand{canon_dist(xp, X + (int64_t)x * d, d), x});
+        if (fill && (int)cur.size() <= m) continue;  // with fill, <= m candidates are all kept
+        std::sort(cur.begin(), cur.end(), cless);
+        tmp.resize(cur.size());
+        const int nr = acquire_sorted(X, d, cur.data(), (int)cur.size(), m, fill, tmp.data(), kept);
+        cur.assign(tmp.begin(), tmp.begin() + nr);
+    }
+    *outdeg = (int32_t)cur.size();
+    std::copy(cur.begin(), cur.end(), out);
+}
+
+// Beam search on a fixed graph with canonical distances (Sec. 4.3 semantics).
+struct Searcher {
+    std::vector<uint32_t> stamp;
+    uint32_t epoch = 0;
+    std::vector<double> qd;
+    std::vector<uint32_t> qi;
+    std::vector<uint8_t> qx;
+    std::vector<uint32_t> nb;
+    std::vector<double> nd;
+    void init(int64_t n, int Leff) {
+        stamp.assign((size_t)n, 0);
+        qd.resize((size_t)Leff + 1);
+        qi.resize((size_t)Leff + 1);
+        qx.resize((size_t)Leff + 1);
+    }
+    // returns the queue length; qd/qi hold the queue in (delta, id) order
+    int run(const float *X, int d, const int64_t *off, const uint32_t *idx, uint32_t entry, const float *q,
+            int Leff) {
+        if (++epoch == 0) {
+            std::fill(stamp.begin(), stamp.end(), 0);
+            epoch = 1;
+        }
+        stamp[entry] = epoch;
+        int qn = 1;
+        qd[0] = canon_dist(q, X + (int64_t)entry * d, d);
+        qi[0] = entry;
+        qx[0] = 0;
+        int ptr = 0;
+        for (;;) {
+            while (ptr < qn && qx[ptr]) ++ptr;
+            if (ptr == qn) break;
+            qx[ptr] = 1;
+            const uint32_t v = qi[ptr];
+            nb.clear();
+            for (int64_t e = off[v]; e < off[v + 1]; ++e) {
+                const uint32_t u = idx[e];
+                if (stamp[u] == epoch) continue;
+                stamp[u] = epoch;
+                nb.push_back(u);
+            }
+            nd.resize(nb.size());
+            dist_batch(X, d, q, nb.data(), (int64_t)nb.size(), nd.data());
+            int first = qn;
+            for (size_t j = 0; j < nb.size(); ++j) {
+                const double du = nd[j];
+                const uint32_t u = nb[j];
+                if (qn == Leff && !(du < qd[Leff - 1] || (du == qd[Leff - 1] && u < qi[Leff - 1]))) continue;
+                // binary search for the insertion point
+                int lo = 0, hi = qn;
+                while (lo < hi) {
+                    const int mid = (lo + hi) >> 1;
+                    if (qd[mid] < du || (qd[mid] == du && qi[mid] < u))
+                        lo = mid + 1;
+                    else
+                        hi = mid;
+                }
+                const int last = qn < Leff ? qn : Leff - 1;
+                for (int t = last; t > lo; --t) {
+                    qd[t] = qd[t - 1];
+                    qi[t] = qi[t - 1];
+                    qx[t] = qx[t - 1];
+                }
+                qd[lo] = du;
+                qi[lo] = u;
+                qx[lo] = 0;
+                if (qn < Leff) ++qn;
+                if (lo < first) first = lo;
+            }
+            if (first < ptr) ptr = first;
+        }
+        return qn;
+    }
+};
+
+void lists_to_csr(const Lists &L, int64_t n, std::vector<int64_t> &off, std::vector<uint32_t> &idx) {
+    off.assign((size_t)n + 1, 0);
+    for (int64_t x = 0; x < n; ++x) off[x + 1] = off[x] + L.deg[x];
+    idx.resize((size_t)off[n]);
+    for (int64_t x = 0; x < n; ++x)
+        for (int j = 0; j < L.deg[x]; ++j) idx[off[x] + j] = L.row(x)[j].id;
+}
+
+}  // namespace
+
+double canon_dist(const float *a, const float *b, int32_t d) {
+    double s = 0.0;
+    for (int32_t i = 0; i < d; ++i) s += (double)a[i] * (double)b[i];
+    return -s;
+}
+
+int hw_threads(int requested) {
+    if (requested > 0) return requested;
+    const unsigned h = std::thread::hardware_concurrency();
+    return h ? (int)h : 1;
+}
+
+int host_construct(const float *X, int64_t n, int32_t d, const uint32_t *knn, int64_t nt, int32_t Nq, int32_t M,
+                   int32_t L, int32_t m_pj, int32_t m_ce, int threads, HostGraph *out) {
+    const auto t0 = Clock::now();
+    threads = hw_threads(threads);
+    const int q1 = Nq - 1;
+
+    // --- bipartite graph (Algorithm 1): pivot of t gets t as a bridge ------
+    std::vector<int64_t> boff((size_t)n + 1, 0);
+    for (int64_t t = 0; t < nt; ++t) boff[knn[t * Nq] + 1]++;
+    for (int64_t i = 0; i < n; ++i) boff[i + 1] += boff[i];
+    std::vector<uint32_t> bidx((size_t)nt);
+    {
+        std::vector<int64_t> fp(boff.begin(), boff.end() - 1);
+        for (int64_t t = 0; t < nt; ++t) bidx[fp[knn[t * Nq]]++] = (uint32_t)t;
+    }
+
+    // --- projection, forward selections F(x) of every pivot ---------------
+    const int capl = std::max(m_pj, m_ce) + 1;
+    Lists F;
+    F.init(n, capl);
+    {
+        std::vector<std::vector<uint32_t>> stamp((size_t)threads);
+        std::vector<std::vector<uint32_t>> cid((size_t)threads);
+        std::vector<std::vector<double>> cdd((size_t)threads);
+        std::vector<std::vector<Cand>> cc((size_t)threads);
+        std::vector<std::vector<uint8_t>> kept((size_t)threads);
+        parallel_for(n, threads, 64, [&](int64_t x, int tid) {
+            if (boff[x] == boff[x + 1]) return;
+            auto &st = stamp[tid];
+            if (st.empty()) st.assign((size_t)n, 0);
+            auto &ids = cid[tid];
+            ids.clear();
+            const uint32_t mark = (uint32_t)x + 1u;
+            for (int64_t b = boff[x]; b < boff[x + 1]; ++b) {
+                if ((int64_t)ids.size() >= L) break;
+                const uint32_t *lst = knn + (int64_t)bidx[b] * Nq + 1;
+                for (int j = 0; j < q1; ++j) {
+                    const uint32_t c = lst[j];
+                    if ((int64_t)c == x || st[c] == mark) continue;
+                    st[c] = mark;
+                    ids.push_back(c);
+                }
+            }
+            auto &dd = cdd[tid];
+            dd.resize(ids.size());
+            dist_batch(X, d, X + x * d, ids.data(), (int64_t)ids.size(), dd.data());
+            auto &c = cc[tid];
+            c.resize(ids.size());
+            for (size_t j = 0; j < ids.size(); ++j) c[j] = Cand{dd[j], ids[j]};
+            std::sort(c.begin(), c.end(), cless);
+            const int nk = (int)std::min<int64_t>((int64_t)c.size(), L);
+            F.deg[x] = acquire_sorted(X, d, c.data(), nk, m_pj, true, F.row(x), kept[tid]);
+        });
+    }
+    // --- projection, reverse insertions replayed per target ---------------
+    Lists PJ;
+    PJ.init(n, capl);
+    {
+        std::vector<int64_t> eoff;
+        std::vector<uint32_t> esrc;
+        build_events(F, n, eoff, esrc);
+        std::vector<std::vector<Cand>> cur((size_t)threads), tmp((size_t)threads);
+        std::vector<std::vector<uint8_t>> kept((size_t)threads);
+        parallel_for(n, threads, 256, [&](int64_t p, int tid) {
+            const bool piv = boff[p] != boff[p + 1];
+            replay(X, d, p, piv, F.row(p), piv ? F.deg[p] : 0, esrc.data() + eoff[p], eoff[p + 1] - eoff[p], m_pj,
+                   true, PJ.row(p), &PJ.deg[p], cur[tid], tmp[tid], kept[tid]);
+        });
+    }
+    std::vector<int64_t> pjoff;
+    std::vector<uint32_t> pjidx;
+    lists_to_csr(PJ, n, pjoff, pjidx);
+    const auto t1 = Clock::now();
+
+    // --- entry: nearest to the mean among nodes with a projected out-edge --
+    uint32_t entry = 0;
+    {
+        std::vector<double> mu((size_t)d, 0.0);
+        for (int64_t i = 0; i < n; ++i)
+            for (int j = 0; j < d; ++j) mu[j] += (double)X[i * d + j];
+        for (int j = 0; j < d; ++j) mu[j] = mu[j] / (double)n;
+        bool any = false;
+        for (int64_t i = 0; i < n && !any; ++i) any = PJ.deg[i] > 0;
+        const int64_t chunk = 4096;
+        const int64_t nchunk = (n + chunk - 1) / chunk;
+        std::vector<double> bestd((size_t)nchunk, INFINITY);
+        std::vector<int64_t> besti((size_t)nchunk, -1);
+        parallel_for(nchunk, threads, 1, [&](int64_t c, int) {
+            for (int64_t i = c * chunk; i < std::min(n, (c + 1) * chunk); ++i) {
+                if (any && PJ.deg[i] == 0) continue;
+                double s = 0.0;
+                for (int j = 0; j < d; ++j) {
+                    const double t = (double)X[i * d + j] - mu[j];
+                    s += t * t;
+                }
+                if (s < bestd[c]) {
+                    bestd[c] = s;
+                    besti[c] = i;
+                }
+            }
+        });
+        double b = INFINITY;
+        for (int64_t c = 0; c < nchunk; ++c)
+            if (besti[c] >= 0 && bestd[c] < b) {
+                b = bestd[c];
+                entry = (uint32_t)besti[c];
+            }
+    }
+
+    // --- enhancement: searches on G_pj and each node's own selection E(x) --
+    Lists E;
+    E.init(n, capl);
+    {
+        std::vector<Searcher> sr((size_t)threads);
+        std::vector<std::vector<Cand>> cc((size_t)threads);
+        std::vector<std::vector<uint8_t>> kept((size_t)threads);
+        parallel_for(n, threads, 16, [&](int64_t x, int tid) {
+            Searcher &s = sr[tid];
+            if (s.stamp.empty()) s.init(n, L);
+            const int qn = s.run(X, d, pjoff.data(), pjidx.data(), entry, X + x * d, L);
+            auto &c = cc[tid];
+            c.clear();
+            for (int j = 0; j < qn; ++j)
+                if ((int64_t)s.qi[j] != x) c.push_back(Cand{s.qd[j], s.qi[j]});
+            E.deg[x] = acquire_sorted(X, d, c.data(), (int)c.size(), m_ce, false, E.row(x), kept[tid]);
+        });
+    }
+    Lists CE;
+    CE.init(n, capl);
+    {
+        std::vector<int64_t> eoff;
+        std::vector<uint32_t> esrc;
+        build_events(E, n, eoff, esrc);
+        std::vector<std::vector<Cand>> cur((size_t)threads), tmp((size_t)threads);
+        std::vector<std::vector<uint8_t>> kept((size_t)threads);
+        parallel_for(n, threads, 256, [&](int64_t p, int tid) {
+            replay(X, d, p, true, E.row(p), E.deg[p], esrc.data() + eoff[p], eoff[p + 1] - eoff[p], m_ce, false,
+                   CE.row(p), &CE.deg[p], cur[tid], tmp[tid], kept[tid]);
+        });
+    }
+    const auto t2 = Clock::now();
+
+    // --- merge: final(x) = G_pj(x) u G'(x) -------------------------------
+    std::vector<std::vector<uint32_t>> fin((size_t)n);
+    parallel_for(n, threads, 1024, [&](int64_t x, int) {
+        auto &r = fin[x];
+        r.reserve((size_t)M);
+        for (int j = 0; j < PJ.deg[x]; ++j) r.push_back(PJ.row(x)[j].id);
+        for (int j = 0; j < CE.deg[x]; ++j) {
+            const uint32_t u = CE.row(x)[j].id;
+            if (std::find(r.begin(), r.end(), u) == r.end()) r.push_back(u);
+        }
+        std::sort(r.begin(), r.end());  // the repair's BFS visits neighbours in ascending id
+    });
+
+    // --- reachability repair ---------------------------------------------
+    int64_t repairs = 0;
+    {
+        std::vector<uint8_t> seen((size_t)n, 0);
+        std::vector<uint32_t> order;
+        order.reserve((size_t)n);
+        size_t head = 0;
+        seen[entry] = 1;
+        order.push_back(entry);
+        auto bfs = [&]() {
+            while (head < order.size()) {
+                const uint32_t v = order[head++];
+                for (uint32_t w : fin[v])
+                    if (!seen[w]) {
+                        seen[w] = 1;
+                        order.push_back(w);
+                    }
+            }
+        };
+        bfs();
+        Searcher s;
+        for (int64_t u = 0; u < n; ++u) {
+            if (seen[u]) continue;
+            if (s.stamp.empty()) s.init(n, L);
+            const int qn = s.run(X, d, pjoff.data(), pjidx.data(), entry, X + u * d, L);
+            int64_t r = -1;
+            for (int j = 0; j < qn && r < 0; ++j) {
+                const uint32_t c = s.qi[j];
+                if ((int64_t)c != u && seen[c] && (int)fin[c].size() < M) r = c;
+            }
+            for (size_t j = 0; j < order.size() && r < 0; ++j)
+                if ((int)fin[order[j]].size() < M) r = order[j];
+            if (r < 0) {
+                set_error("build: reachability repair found no node with a free slot");
+                return RG_EINTERNAL;
+            }
+            fin[r].push_back((uint32_t)u);
+            ++repairs;
+            seen[u] = 1;
+            order.push_back((uint32_t)u);
+            bfs();
+        }
+    }
+
+    // --- CSR, rows sorted by id ------------------------------------------
+    out->offsets.assign((size_t)n + 1, 0);
+    for (int64_t x = 0; x < n; ++x) out->offsets[x + 1] = out->offsets[x] + (int64_t)fin[x].size();
+    out->indices.resize((size_t)out->offsets[n]);
+    parallel_for(n, threads, 4096, [&](int64_t x, int) {
+        std::sort(fin[x].begin(), fin[x].end());
+        std::copy(fin[x].begin(), fin[x].end(), out->indices.begin() + out->offsets[x]);
+    });
+    out->entry = entry;
+    out->repairs = repairs;
+    const auto t3 = Clock::now();
+    out->t_project = secs(t0, t1);
+    out->t_enhance = secs(t1, t2);
+    out->t_total = secs(t0, t3);
+    return RG_OK;
+}
+
+}  // namespace rg

@@ -1,0 +1,332 @@
+// Exact-kNN candidates on gfx950: S = Q X^T with FP32 MFMA
+// (v_mfma_f32_16x16x4_f32), fused with a streaming top-K per query row, so
+// the nq x n score matrix is never written.  This is the preprocessing step
+// of index construction (the training queries' nearest base vectors,
+// Algorithm 1 input) and the ground truth of recall@k (Def. 1).
+//
+// Workgroup = 4 wavefronts, a 128-query x 128-base output tile per step,
+// each wavefront owning a 64 x 64 quarter as 4 x 4 MFMA blocks (64
+// accumulator registers).  Operands are staged through LDS in 32-wide
+// slices of the coordinate axis, stored coordinate-major with a 16-float pad
+// so that the MFMA operand reads are bank-conflict free.
+//
+// Top-K: every query row of the tile keeps, in global memory, a buffer of up
+// to CAP (score, id) pairs and in LDS an admission threshold (the K-th best
+// score after the last compaction; -inf before).  Each score >= threshold is
+// appended; a row whose buffer could overflow on the next tile is compacted
+// by one wavefront (in-register bitonic sort of CAP pairs, keep K).  After a
+// workgroup has swept its share of the base it sorts each row once more and
+// writes the K best by (score desc, id asc).  When the base is split across
+// workgroups, a merge kernel combines the per-split lists the same way.
+#include "rg_internal.h"
+#include "wave_ops.h"
+
+#include <algorithm>
+
+namespace rg {
+namespace {
+
+typedef float fx4 __attribute__((ext_vector_type(4)));
+
+constexpr int BQ = 128, BX = 128, KC = 32, LDS_LD = 128 + 16;
+constexpr int CAP = 512;        // per-row candidate buffer
+constexpr int CE = CAP / 64;    // pairs per lane when sorting a buffer
+
+struct KnnArgs {
+    const float *Q;
+    const float *X;
+    float *buf_sc;
+    uint32_t *buf_id;
+    float *out_sc;
+    uint32_t *out_id;
+    int64_t nq, n;
+    int64_t q_tile0;
+    int64_t xtiles, xtiles_per_split;
+    int32_t ldq, ldx, d, K, splits;
+    int32_t vec_q, vec_x;
+};
+
+__device__ __forceinline__ float4 ld4(const float *M, int64_t rows, int ld, int d, int64_t r, int k, bool vec) {
+    float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+    if (r >= rows) return v;
+    const float *p = M + r * (int64_t)ld + k;
+    if (vec && k + 3 < d) return *reinterpret_cast<const float4 *>(p);
+    if (k + 0 < d) v.x = p[0];
+    if (k + 1 < d) v.y = p[1];
+    if (k + 2 < d) v.z = p[2];
+    if (k + 3 < d) v.w = p[3];
+    return v;
+}
+
+// Sort the row's buffer (count c) by (score desc, id asc) and keep K.
+// Returns the new count; thr receives the K-th best score when c >= K.
+__device__ __forceinline__ int compact_row(float *bsc, uint32_t *bid, int c, int K, float &thr) {
+    const int lane = lane_id();
+    float key[CE];
+    uint32_t id[CE];
+#pragma unroll
+    for (int e = 0; e < CE; ++e) {
+        const int i = lane * CE + e;
+        key[e] = i < c ? -bsc[i] : __builtin_inff();
+        id[e] = i < c ? bid[i] : kNone;
+    }
+    wave_sort<CE>(key, id);
+#pragma unroll
+    for (int e = 0; e < CE; ++e) {
+        const int i = lane * CE + e;
+        if (i < K && i < c) {
+            bsc[i] = -key[e];
+            bid[i] = id[e];
+        }
+    }
+    const int src = (K - 1) / CE, se = (K - 1) % CE;
+    float kth = 0.f;
+#pragma unroll
+    for (int e = 0; e < CE; ++e)
+        if (e == se) kth = key[e];
+    kth = __shfl(kth, src);
+    if (c >= K) thr = -kth;
+    return c < K ? c : K;
+}
+
+__global__ __launch_bounds__(256) void k_knn(KnnArgs a) {
+    __shared__ float As[KC][LDS_LD];
+    __shared__ float Bs[KC][LDS_LD];
+    __shared__ float thr[BQ];
+    __shared__ int cnt[BQ];
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int wr = w >> 1, wc = w & 1;
+    const int64_t qt = a.q_tile0 + blockIdx.x;
+    const int sp = blockIdx.y;
+    const int64_t q0 = qt * BQ;
+    const int64_t slot = (int64_t)blockIdx.x * a.splits + sp;
+    float *bsc = a.buf_sc + slot * BQ * CAP;
+    uint32_t *bid = a.buf_id + slot * BQ * CAP;
+    const bool vq = a.vec_q != 0, vx = a.vec_x != 0;
+
+    if (tid < BQ) {
+        thr[tid] = -__builtin_inff();
+        cnt[tid] = 0;
+    }
+    const int64_t xt0 = (int64_t)sp * a.xtiles_per_split;
+    const int64_t xt1 = min(a.xtiles, xt0 + a.xtiles_per_split);
+    const int lr = tid >> 3, lk = (tid & 7) * 4;
+    for (int64_t xt = xt0; xt < xt1; ++xt) {
+        const int64_t x0 = xt * BX;
+        fx4 acc[4][4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+            for (int j = 0; j < 4; ++j) acc[i][j] = fx4{0.f, 0.f, 0.f, 0.f};
+        for (int k0 = 0; k0 < a.d; k0 += KC) {
+            float4 va[4], vb[4];
+#pragma unroll
+            for (int p = 0; p < 4; ++p) {
+                va[p] = ld4(a.Q, a.nq, a.ldq, a.d, q0 + p * 32 + lr, k0 + lk, vq);
+                vb[p] = ld4(a.X, a.n, a.ldx, a.d, x0 + p * 32 + lr, k0 + lk, vx);
+            }
+            __syncthreads();
+#pragma unroll
+            for (int p = 0; p < 4; ++p) {
+                const int r = p * 32 + lr;
+                As[lk + 0][r] = va[p].x;
+                As[lk + 1][r] = va[p].y;
+                As[lk + 2][r] = va[p].z;
+                As[lk + 3][r] = va[p].w;
+                Bs[lk + 0][r] = vb[p].x;
+                Bs[lk + 1][r] = vb[p].y;
+                Bs[lk + 2][r] = vb[p].z;
+                Bs[lk + 3][r] = vb[p].w;
+            }
+            __syncthreads();
+#pragma unroll
+            for (int ks = 0; ks < KC / 4; ++ks) {
+                const int kk = ks * 4 + (lane >> 4);
+                float af[4], bf[4];
+#pragma unroll
+                for (int i = 0; i < 4; ++i) af[i] = As[kk][wr * 64 + i * 16 + (lane & 15)];
+#pragma unroll
+                for (int j = 0; j < 4; ++j) bf[j] = Bs[kk][wc * 64 + j * 16 + (lane & 15)];
+#pragma unroll
+                for (int i = 0; i < 4; ++i)
+#pragma unroll
+                    for (int j = 0; j < 4; ++j)
+                        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(af[i], bf[j], acc[i][j], 0, 0, 0);
+            }
+        }
+        // filter: accumulator element r of block (i, j) is row 4*(lane/16)+r, column lane%16
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int row = wr * 64 + i * 16 + 4 * (lane >> 4) + r;
+                const float t = thr[row];
+                const bool rok = q0 + row < a.nq;
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    const int64_t gx = x0 + wc * 64 + j * 16 + (lane & 15);
+                    const float s = acc[i][j][r];
+                    if (rok && gx < a.n && s >= t) {
+                        const int pos = atomicAdd(&cnt[row], 1);
+                        bsc[(int64_t)row * CAP + pos] = s;
+                        bid[(int64_t)row * CAP + pos] = (uint32_t)gx;
+                    }
+                }
+            }
+        }
+        __syncthreads();
+        for (int row = w; row < BQ; row += 4) {
+            const int c = cnt[row];
+            if (c > CAP - BX) {
+                float t = thr[row];
+                const int nc = compact_row(bsc + (int64_t)row * CAP, bid + (int64_t)row * CAP, c, a.K, t);
+                if (lane == 0) {
+                    cnt[row] = nc;
+                    thr[row] = t;
+                }
+            }
+        }
+        __syncthreads();
+    }
+    for (int row = w; row < BQ; row += 4) {
+        const int64_t gq = q0 + row;
+        if (gq >= a.nq) continue;
+        float t = thr[row];
+        float *rs = bsc + (int64_t)row * CAP;
+        uint32_t *ri = bid + (int64_t)row * CAP;
+        const int c = compact_row(rs, ri, cnt[row], a.K, t);
+        float *os = a.out_sc + ((int64_t)sp * a.nq + gq) * a.K;
+        uint32_t *oi = a.out_id + ((int64_t)sp * a.nq + gq) * a.K;
+        for (int i = lane; i < a.K; i += 64) {
+            os[i] = i < c ? rs[i] : -__builtin_inff();
+            oi[i] = i < c ? ri[i] : kNone;
+        }
+    }
+}
+
+// Merge per-split top-K lists into one (one wavefront per query row).
+__global__ __launch_bounds__(64) void k_knn_merge(const float *sc, const uint32_t *id, int64_t nq, int K,
+                                                  int splits, float *out_sc, uint32_t *out_id) {
+    const int64_t q = blockIdx.x;
+    const int lane = lane_id();
+    float key[CE];
+    uint32_t v[CE];
+    // running list occupies slots [0, K); the next split's list [K, 2K)
+#pragma unroll
+    for (int e = 0; e < CE; ++e) {
+        const int i = lane * CE + e;
+        key[e] = i < K ? -sc[q * K + i] : __builtin_inff();
+        v[e] = i < K ? id[q * K + i] : kNone;
+    }
+    for (int s = 1; s < splits; ++s) {
+        const float *ss = sc + ((int64_t)s * nq + q) * K;
+        const uint32_t *si = id + ((int64_t)s * nq + q) * K;
+#pragma unroll
+        for (int e = 0; e < CE; ++e) {
+            const int i = lane * CE + e;
+            if (i >= K) {
+                key[e] = i < 2 * K ? -ss[i - K] : __builtin_inff();
+                v[e] = i < 2 * K ? si[i - K] : kNone;
+            }
+        }
+        wave_sort<CE>(key, v);
+    }
+#pragma unroll
+    for (int e = 0; e < CE; ++e) {
+        const int i = lane * CE + e;
+        if (i < K) {
+            out_sc[q * K + i] = -key[e];
+            out_id[q * K + i] = v[e];
+        }
+    }
+}
+
+}  // namespace
+
+int launch_knn_candidates(const float *Q, int64_t nq, int32_t ldq, const float *X, int64_t n, int32_t ldx,
+                          int32_t d, int32_t K, uint32_t *ids, float *scores, hipStream_t stream) {
+    if (K < 1 || K > CAP - BX || K > CAP / 2) {
+        set_error("knn: K must be in [1, 256]");
+        return RG_EINVAL;
+    }
+    if (nq == 0) return RG_OK;
+    const int64_t qtiles = (nq + BQ - 1) / BQ;
+    const int64_t xtiles = (n + BX - 1) / BX;
+    // split the base when there are too few query tiles to fill the chip
+    int splits = (int)std::min<int64_t>(16, std::max<int64_t>(1, 1024 / qtiles));
+    splits = (int)std::min<int64_t>(splits, xtiles);
+    const int64_t per = (xtiles + splits - 1) / splits;
+    splits = (int)((xtiles + per - 1) / per);
+    const int64_t tiles_per_launch = std::max<int64_t>(1, 1024 / splits);
+    const int64_t slots = std::min(qtiles, tiles_per_launch) * splits;
+
+    float *buf_sc = nullptr, *tmp_sc = nullptr;
+    uint32_t *buf_id = nullptr, *tmp_id = nullptr;
+    auto cleanup = [&]() {
+        if (buf_sc) (void)hipFree(buf_sc);
+        if (buf_id) (void)hipFree(buf_id);
+        if (tmp_sc) (void)hipFree(tmp_sc);
+        if (tmp_id) (void)hipFree(tmp_id);
+    };
+    if (hipMalloc(&buf_sc, sizeof(float) * slots * BQ * CAP) != hipSuccess ||
+        hipMalloc(&buf_id, sizeof(uint32_t) * slots * BQ * CAP) != hipSuccess) {
+        cleanup();
+        set_error("knn: out of device memory for candidate buffers");
+        return RG_ENOMEM;
+    }
+    if (splits > 1) {
+        if (hipMalloc(&tmp_sc, sizeof(float) * splits * nq * K) != hipSuccess ||
+            hipMalloc(&tmp_id, sizeof(uint32_t) * splits * nq * K) != hipSuccess) {
+            cleanup();
+            set_error("knn: out of device memory for split lists");
+            return RG_ENOMEM;
+        }
+    }
+    KnnArgs a{};
+    a.Q = Q;
+    a.X = X;
+    a.buf_sc = buf_sc;
+    a.buf_id = buf_id;
+    a.out_sc = splits > 1 ? tmp_sc : scores;
+    a.out_id = splits > 1 ? tmp_id : ids;
+    a.nq = nq;
+    a.n = n;
+    a.xtiles = xtiles;
+    a.xtiles_per_split = per;
+    a.ldq = ldq;
+    a.ldx = ldx;
+    a.d = d;
+    a.K = K;
+    a.splits = splits;
+    a.vec_q = (ldq % 4 == 0) && ((uintptr_t)Q % 16 == 0);
+    a.vec_x = (ldx % 4 == 0) && ((uintptr_t)X % 16 == 0);
+    for (int64_t t0 = 0; t0 < qtiles; t0 += tiles_per_launch) {
+        a.q_tile0 = t0;
+        const int64_t nt = std::min(tiles_per_launch, qtiles - t0);
+        hipLaunchKernelGGL(k_knn, dim3((unsigned)nt, (unsigned)splits), dim3(256), 0, stream, a);
+        if (hipGetLastError() != hipSuccess) {
+            cleanup();
+            set_error("knn: kernel launch failed");
+            return RG_EDEVICE;
+        }
+    }
+    if (splits > 1) {
+        hipLaunchKernelGGL(k_knn_merge, dim3((unsigned)nq), dim3(64), 0, stream, tmp_sc, tmp_id, nq, K, splits,
+                           scores, ids);
+        if (hipGetLastError() != hipSuccess) {
+            cleanup();
+            set_error("knn: merge launch failed");
+            return RG_EDEVICE;
+        }
+    }
+    // buffers are freed only after the kernels that use them have finished
+    if (hipStreamSynchronize(stream) != hipSuccess) {
+        cleanup();
+        set_error("knn: kernel failed");
+        return RG_EDEVICE;
+    }
+    cleanup();
+    return RG_OK;
+}
+
+}  // namespace rg

@@ -1,0 +1,130 @@
+// Internal declarations shared by the library's translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/roargraph.h"
+
+namespace rg {
+
+constexpr uint32_t kNone = 0xFFFFFFFFu;
+constexpr uint32_t kExpanded = 0x80000000u;  // queue-entry flag (ids < 2^31)
+constexpr int kMaxL = 512;                    // largest queue the search kernel holds
+constexpr int kMaxEll = 128;                  // largest out-degree the search kernel reads
+
+void set_error(const std::string &msg);
+
+// status helpers
+#define RG_HIP(call)                                                                  \
+    do {                                                                              \
+        hipError_t e_ = (call);                                                       \
+        if (e_ != hipSuccess) {                                                       \
+            ::rg::set_error(std::string(#call) + ": " + hipGetErrorString(e_));       \
+            return RG_EDEVICE;                                                        \
+        }                                                                             \
+    } while (0)
+
+// Device-side search parameters (one struct, passed by value).
+struct SearchArgs {
+    const float *base;          // fp32 rows, pitch floats
+    const uint16_t *base_bf16;  // bf16 rows (pitch elements) or null
+    const uint8_t *base_fp8;    // e4m3 rows (pitch8 bytes) or null
+    const float *scale_fp8;     // per-row power-of-two scales
+    const uint32_t *adj;        // ELL adjacency, n x ell, kNone padded
+    const float *queries;       // nq x d
+    uint32_t *out_ids;          // nq x k
+    float *out_d;               // nq x k
+    uint32_t *out_hops;         // nq or null
+    uint32_t *out_evals;        // nq or null
+    int64_t nq;
+    int32_t d, pitch, pitch8, ell;
+    int32_t k, Leff;
+    int32_t hash_bits;
+    uint32_t entry;
+    int32_t storage;            // RG_STORE_*
+};
+
+// beam.hip
+int launch_search(const SearchArgs &a, hipStream_t stream);
+size_t search_lds_bytes(int Leff, int ell, int hash_bits);
+int default_hash_bits(int Leff);
+
+// Serving step: same per-query arithmetic as launch_search, resumable.
+struct SlotArgs {
+    SearchArgs s;               // queries/out_* unused; per-slot arrays below
+    const int32_t *active;      // list of slot indices to advance
+    int32_t n_active;
+    float *slot_q;              // slots x d query vectors
+    int32_t *slot_k, *slot_L;
+    float *slot_qd;             // slots x kMaxL queue distances
+    uint32_t *slot_qi;          // slots x kMaxL queue ids (+flag)
+    int32_t *slot_state;        // slots x 4: qn, ptr, hops, evals
+    uint32_t *slot_hash;        // slots x (1 << hash_bits)
+    int32_t *slot_hcount;       // slots
+    uint32_t *slot_out_ids;     // slots x kMaxL
+    float *slot_out_d;          // slots x kMaxL
+    int32_t *slot_done;         // slots: set to 1 when finished
+    int32_t hops_budget;
+};
+int launch_serve_step(const SlotArgs &a, hipStream_t stream);
+
+// knn.hip: top-K candidates by FP32 score (desc), ids asc on ties.
+int launch_knn_candidates(const float *Q, int64_t nq, int32_t ldq, const float *X, int64_t n,
+                          int32_t ldx, int32_t d, int32_t K, uint32_t *ids, float *scores,
+                          hipStream_t stream);
+
+// quant.hip
+int launch_pad_rows(const float *src, int64_t n, int32_t d, float *dst, int32_t pitch,
+                    hipStream_t stream);
+int launch_quant_bf16(const float *src, int64_t n, int32_t pitch, uint16_t *dst,
+                      hipStream_t stream);
+int launch_quant_fp8(const float *src, int64_t n, int32_t d, int32_t pitch, uint8_t *dst,
+                     int32_t pitch8, float *scales, hipStream_t stream);
+
+// host_build.cpp
+struct HostGraph {
+    std::vector<int64_t> offsets;
+    std::vector<uint32_t> indices;
+    uint32_t entry = 0;
+    int64_t repairs = 0;
+    double t_knn = 0, t_project = 0, t_enhance = 0, t_total = 0;
+};
+// knn lists: nt x Nq canonical ids.  X: host n x d.
+int host_construct(const float *X, int64_t n, int32_t d, const uint32_t *knn, int64_t nt,
+                   int32_t Nq, int32_t M, int32_t L, int32_t m_pj, int32_t m_ce, int threads,
+                   HostGraph *out);
+
+// canonical FP64 distance helpers (host)
+double canon_dist(const float *a, const float *b, int32_t d);
+
+// exact kNN = GPU candidates + host certification (api.cpp)
+int knn_exact(const float *Qdev, int64_t nq, const float *Xdev, int64_t n, int32_t d, int32_t k,
+              int32_t slack, const float *Qhost, const float *Xhost, int threads,
+              std::vector<uint32_t> *ids_out, std::vector<double> *d_out, hipStream_t stream);
+
+int hw_threads(int requested);
+
+}  // namespace rg
+
+struct rg_index {
+    int64_t n = 0;
+    int32_t d = 0, pitch = 0, pitch8 = 0, ell = 0;
+    int32_t metric = RG_METRIC_IP;
+    int32_t storage = RG_STORE_FP32;
+    uint32_t entry = 0;
+    int32_t Nq = 0, M = 0, L_build = 0, m_pj = 0, m_ce = 0;
+    int64_t repairs = 0;
+    std::vector<int64_t> offsets;    // host CSR
+    std::vector<uint32_t> indices;
+    float *d_base = nullptr;          // n x pitch fp32
+    uint32_t *d_adj = nullptr;        // n x ell
+    uint16_t *d_bf16 = nullptr;       // n x pitch
+    uint8_t *d_fp8 = nullptr;         // n x pitch8
+    float *d_scale = nullptr;         // n
+    int device = 0;
+    double t_knn = 0, t_project = 0, t_enhance = 0, t_total = 0;
+};

@@ -1,0 +1,311 @@
+// Serving: continuous batching of search requests with mixed (k, L).
+//
+// A scheduler thread owns a table of device-resident slots.  Each slot holds
+// one request's whole beam-search state in device memory: query vector,
+// queue (L_eff <= 512 entries), visited table, counters.  One scheduler step
+// = admit pending requests into free slots (bounded by max_slots and by the
+// HBM pool divided by the per-slot state size), launch one step kernel over
+// all active slots, which advances each by at most hops_per_step expansions
+// and saves its state, then collect the slots that finished.  Requests that
+// arrive while a step runs are admitted at the next step, so new work joins
+// work already on the device instead of waiting for a batch to drain.
+//
+// The step kernel runs the same per-query arithmetic as rg_search (same
+// distance function, same merge), and a slot's state is saved and restored
+// exactly, so a request returns the same ids and distances alone or in any
+// mix.  The device never waits on host memory: every kernel runs to
+// completion and the host polls a done flag after each step.
+#include <chrono>
+#include <condition_variable>
+#include <cstring>
+#include <deque>
+#include <mutex>
+#include <thread>
+
+#include "rg_internal.h"
+
+using namespace rg;
+
+namespace {
+
+struct Pending {
+    std::vector<float> q;
+    int32_t k, L;
+    uint64_t tag;
+    double t_submit;
+};
+
+struct SlotInfo {
+    bool busy = false;
+    bool fresh = false;
+    uint64_t tag = 0;
+    int32_t k = 0, L = 0;
+    double t_submit = 0, t_admit = 0;
+};
+
+constexpr size_t kMaxPending = 1u << 20;
+
+}  // namespace
+
+struct rg_server {
+    const rg_index *ix = nullptr;
+    rg_server_limits lim{};
+    int32_t slots = 0, hash_bits = 12;
+    hipStream_t stream = nullptr;
+    // device slot arrays
+    float *d_q = nullptr, *d_qd = nullptr, *d_outd = nullptr;
+    int32_t *d_k = nullptr, *d_L = nullptr, *d_state = nullptr, *d_hcount = nullptr, *d_done = nullptr,
+            *d_active = nullptr;
+    uint32_t *d_qi = nullptr, *d_hash = nullptr, *d_outi = nullptr;
+    // host side
+    std::mutex mu;
+    std::condition_variable cv;
+    std::deque<Pending> pending;
+    std::vector<SlotInfo> info;
+    std::deque<rg_result> finished;
+    std::thread th;
+    bool stop = false;
+    uint64_t n_sub = 0, n_adm = 0, n_done = 0, n_steps = 0;
+    int err = RG_OK;
+    std::chrono::steady_clock::time_point t0;
+
+    double now() const { return std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count(); }
+    void loop();
+    void release();
+};
+
+void rg_server::release() {
+    void *ps[] = {d_q, d_qd, d_outd, d_k, d_L, d_state, d_hcount, d_done, d_active, d_qi, d_hash, d_outi};
+    for (void *p : ps)
+        if (p) (void)hipFree(p);
+    if (stream) (void)hipStreamDestroy(stream);
+}
+
+void rg_server::loop() {
+    (void)hipSetDevice(ix->device);
+    const int d = ix->d;
+    std::vector<int32_t> active, done((size_t)slots);
+    std::vector<int32_t> zero_state(8, 0);
+    for (;;) {
+        std::vector<int32_t> admitted;
+        {
+            std::unique_lock<std::mutex> lk(mu);
+            bool any_busy = false;
+            for (auto &s : info) any_busy |= s.busy;
+            if (!any_busy && pending.empty()) {
+                if (stop) break;
+                cv.wait_for(lk, std::chrono::milliseconds(1));
+                continue;
+            }
+            // admission: free slots in ascending order, requests in arrival order
+            for (int32_t s = 0; s < slots && !pending.empty() && !stop; ++s) {
+                if (info[s].busy) continue;
+                Pending p = std::move(pending.front());
+                pending.pop_front();
+                info[s] = SlotInfo{true, true, p.tag, p.k, p.L, p.t_submit, now()};
+                ++n_adm;
+                // stage the query and parameters (host -> device, ordered on the stream)
+                if (hipMemcpyAsync(d_q + (size_t)s * d, p.q.data(), sizeof(float) * d, hipMemcpyHostToDevice,
+                                   stream) != hipSuccess ||
+                    hipMemcpyAsync(d_k + s, &info[s].k, 4, hipMemcpyHostToDevice, stream) != hipSuccess ||
+                    hipMemcpyAsync(d_L + s, &info[s].L, 4, hipMemcpyHostToDevice, stream) != hipSuccess ||
+                    hipMemcpyAsync(d_state + (size_t)s * 8, zero_state.data(), 32, hipMemcpyHostToDevice, stream) !=
+                        hipSuccess ||
+                    hipMemcpyAsync(d_done + s, zero_state.data(), 4, hipMemcpyHostToDevice, stream) != hipSuccess) {
+                    err = RG_EDEVICE;
+                }
+                // the copies read p.q and info[s]: wait before they can change
+                (void)hipStreamSynchronize(stream);
+                admitted.push_back(s);
+            }
+            active.clear();
+            for (int32_t s = 0; s < slots; ++s)
+                if (info[s].busy) active.push_back(s);
+        }
+        if (active.empty()) continue;
+        SlotArgs sa{};
+        sa.s.base = ix->d_base;
+        sa.s.base_bf16 = ix->d_bf16;
+        sa.s.base_fp8 = ix->d_fp8;
+        sa.s.scale_fp8 = ix->d_scale;
+        sa.s.adj = ix->d_adj;
+        sa.s.d = d;
+        sa.s.pitch = ix->pitch;
+        sa.s.pitch8 = ix->pitch8;
+        sa.s.ell = ix->ell;
+        sa.s.hash_bits = hash_bits;
+        sa.s.entry = ix->entry;
+        sa.s.storage = ix->storage;
+        sa.active = d_active;
+        sa.n_active = (int32_t)active.size();
+        sa.slot_q = d_q;
+        sa.slot_k = d_k;
+        sa.slot_L = d_L;
+        sa.slot_qd = d_qd;
+        sa.slot_qi = d_qi;
+        sa.slot_state = d_state;
+        sa.slot_hash = d_hash;
+        sa.slot_hcount = d_hcount;
+        sa.slot_out_ids = d_outi;
+        sa.slot_out_d = d_outd;
+        sa.slot_done = d_done;
+        sa.hops_budget = lim.hops_per_step;
+        if (hipMemcpyAsync(d_active, active.data(), sizeof(int32_t) * active.size(), hipMemcpyHostToDevice,
+                           stream) != hipSuccess ||
+            launch_serve_step(sa, stream) != RG_OK ||
+            hipMemcpyAsync(done.data(), d_done, sizeof(int32_t) * slots, hipMemcpyDeviceToHost, stream) !=
+                hipSuccess ||
+            hipStreamSynchronize(stream) != hipSuccess) {
+            std::lock_guard<std::mutex> lk(mu);
+            err = RG_EDEVICE;
+            for (auto &s : info) s.busy = false;
+            pending.clear();
+            continue;
+        }
+        ++n_steps;
+        for (int32_t s : active) {
+            if (!done[s]) continue;
+            rg_result r{};
+            const SlotInfo &si = info[s];
+            r.tag = si.tag;
+            r.k = si.k;
+            r.status = RG_OK;
+            int32_t st[8];
+            if (hipMemcpy(r.ids, d_outi + (size_t)s * kMaxL, sizeof(uint32_t) * si.k, hipMemcpyDeviceToHost) !=
+                    hipSuccess ||
+                hipMemcpy(r.dists, d_outd + (size_t)s * kMaxL, sizeof(float) * si.k, hipMemcpyDeviceToHost) !=
+                    hipSuccess ||
+                hipMemcpy(st, d_state + (size_t)s * 8, sizeof(st), hipMemcpyDeviceToHost) != hipSuccess)
+                r.status = RG_EDEVICE;
+            r.hops = (uint32_t)st[3];
+            r.evals = (uint32_t)st[4];
+            r.t_submit = si.t_submit;
+            r.t_admit = si.t_admit;
+            r.t_done = now();
+            std::lock_guard<std::mutex> lk(mu);
+            finished.push_back(r);
+            info[s].busy = false;
+            ++n_done;
+        }
+    }
+}
+
+extern "C" {
+
+int rg_server_create(const rg_index *ix, const rg_server_limits *lim, rg_server **out) {
+    if (!ix || !out || !ix->d_base) {
+        set_error("rg_server_create: invalid argument");
+        return RG_EINVAL;
+    }
+    *out = nullptr;
+    rg_server_limits l{};
+    if (lim) l = *lim;
+    if (l.max_slots < 1) l.max_slots = 1024;
+    if (l.hops_per_step <= 0) l.hops_per_step = 32;
+    if (l.max_L <= 0 || l.max_L > kMaxL) l.max_L = kMaxL;
+    rg_server *s = new rg_server();
+    s->ix = ix;
+    s->lim = l;
+    s->hash_bits = 12;
+    // device bytes one slot keeps between steps
+    const int64_t per_slot = (int64_t)ix->d * 4 + 8 + (int64_t)kMaxL * 8 + 32 + ((int64_t)4 << s->hash_bits) + 8 +
+                             (int64_t)kMaxL * 8 + 8;
+    int64_t slots = l.max_slots;
+    if (l.hbm_pool_bytes > 0) slots = std::min<int64_t>(slots, l.hbm_pool_bytes / per_slot);
+    if (slots < 1) {
+        delete s;
+        set_error("rg_server_create: HBM pool smaller than one slot");
+        return RG_EINVAL;
+    }
+    s->slots = (int32_t)slots;
+    s->info.resize((size_t)slots);
+    (void)hipSetDevice(ix->device);
+    bool ok = hipStreamCreate(&s->stream) == hipSuccess;
+    auto al = [&](void **p, size_t b) { ok = ok && hipMalloc(p, b) == hipSuccess; };
+    al((void **)&s->d_q, sizeof(float) * slots * ix->d);
+    al((void **)&s->d_k, 4 * slots);
+    al((void **)&s->d_L, 4 * slots);
+    al((void **)&s->d_qd, sizeof(float) * slots * kMaxL);
+    al((void **)&s->d_qi, sizeof(uint32_t) * slots * kMaxL);
+    al((void **)&s->d_state, 32 * slots);
+    al((void **)&s->d_hash, (size_t)slots << (s->hash_bits + 2));
+    al((void **)&s->d_hcount, 4 * slots);
+    al((void **)&s->d_outi, sizeof(uint32_t) * slots * kMaxL);
+    al((void **)&s->d_outd, sizeof(float) * slots * kMaxL);
+    al((void **)&s->d_done, 4 * slots);
+    al((void **)&s->d_active, 4 * slots);
+    if (!ok) {
+        s->release();
+        delete s;
+        set_error("rg_server_create: out of device memory");
+        return RG_ENOMEM;
+    }
+    s->t0 = std::chrono::steady_clock::now();
+    s->th = std::thread([s]() { s->loop(); });
+    *out = s;
+    return RG_OK;
+}
+
+int rg_server_submit(rg_server *s, const float *q, int32_t k, int32_t L, uint64_t tag) {
+    if (!s || !q || k < 1 || L < 1 || k > kMaxL || std::max(k, L) > s->lim.max_L) {
+        set_error("rg_server_submit: invalid argument");
+        return RG_EINVAL;
+    }
+    Pending p{std::vector<float>(q, q + s->ix->d), k, L, tag, s->now()};
+    {
+        std::lock_guard<std::mutex> lk(s->mu);
+        if (s->err) {
+            set_error("rg_server_submit: server stopped after a device error");
+            return s->err;
+        }
+        if (s->pending.size() >= kMaxPending) return RG_EAGAIN;
+        s->pending.push_back(std::move(p));
+        ++s->n_sub;
+    }
+    s->cv.notify_one();
+    return RG_OK;
+}
+
+int rg_server_poll(rg_server *s, rg_result *out, int32_t max, int32_t *n_out) {
+    if (!s || !n_out || (max > 0 && !out)) {
+        set_error("rg_server_poll: invalid argument");
+        return RG_EINVAL;
+    }
+    std::lock_guard<std::mutex> lk(s->mu);
+    int32_t n = 0;
+    while (n < max && !s->finished.empty()) {
+        out[n++] = s->finished.front();
+        s->finished.pop_front();
+    }
+    *n_out = n;
+    return s->err;
+}
+
+int rg_server_stats(const rg_server *s, uint64_t *sub, uint64_t *adm, uint64_t *done, uint64_t *steps) {
+    if (!s) return RG_EINVAL;
+    std::lock_guard<std::mutex> lk(const_cast<rg_server *>(s)->mu);
+    if (sub) *sub = s->n_sub;
+    if (adm) *adm = s->n_adm;
+    if (done) *done = s->n_done;
+    if (steps) *steps = s->n_steps;
+    return RG_OK;
+}
+
+double rg_server_now(const rg_server *s) { return s ? s->now() : 0.0; }
+
+int32_t rg_server_slots(const rg_server *s) { return s ? s->slots : 0; }
+
+void rg_server_destroy(rg_server *s) {
+    if (!s) return;
+    {
+        std::lock_guard<std::mutex> lk(s->mu);
+        s->stop = true;
+        s->pending.clear();
+    }
+    s->cv.notify_one();
+    if (s->th.joinable()) s->th.join();
+    s->release();
+    delete s;
+}
+
+}  // extern "C"

@@ -1,0 +1,82 @@
+"""The library's host construction (rg_build_from_knn) against the oracle,
+and the C ABI surface.  CPU only: no HIP call is made."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import datagen
+import paper_2408_08933_amd as rg
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def test_every_declared_symbol_is_exported():
+    hdr = open(os.path.join(ROOT, "include", "roargraph.h")).read()
+    names = set(re.findall(r"^[a-z_0-9 \*]*\b(rg_[a-z_0-9]+)\s*\(", hdr, flags=re.M))
+    assert len(names) >= 23
+    lib = ctypes.CDLL(rg.LIB_PATH)
+    missing = [n for n in sorted(names) if not hasattr(lib, n)]
+    assert not missing, missing
+
+
+def _compare(X, T, Nq, M, L, oracle_lib, threads=0, m_pj=0, m_ce=0):
+    G = oracle_lib.Graph(X, T, Nq, M, L, m_pj, m_ce)
+    knn, _ = oracle_lib.knn(X, T, Nq)
+    ix = rg.rg_build_from_knn(X, knn, Nq, M, L_build=L, threads=threads, m_pj=m_pj, m_ce=m_ce)
+    off, idx, entry = ix.graph()
+    assert entry == G.entry
+    assert np.array_equal(off, G.offsets)
+    assert np.array_equal(idx, G.indices)
+    assert ix.build_stats()["repairs"] == G.repairs
+    return G, ix
+
+
+def test_hand_worked_five_points(oracle_lib):
+    import json, math
+    g = json.load(open(os.path.join(ROOT, "tests", "golden", "projection_5pt.json")))
+    u = lambda a: [math.cos(math.radians(a)), math.sin(math.radians(a))]
+    X = np.array([u(a) for a in g["base_angles_deg"]], np.float32)
+    T = np.array([u(a) for a in g["train_angles_deg"]], np.float32)
+    knn, _ = oracle_lib.knn(X, T, g["Nq"])
+    ix = rg.rg_build_from_knn(X, knn, g["Nq"], g["M"], L_build=g["L"])
+    off, idx, entry = ix.graph()
+    assert [idx[off[i]:off[i + 1]].tolist() for i in range(5)] == g["final_rows"]
+    assert entry == g["entry"]
+
+
+@pytest.mark.parametrize("cfg,n,Nq,M,L", [(1, 1200, 16, 16, 100), (1, 3000, 32, 32, 200), (2, 1500, 24, 20, 120)])
+def test_library_graph_bit_exact_with_oracle(oracle_lib, cfg, n, Nq, M, L):
+    gen = datagen.Generator(cfg, n=n, n_train=n, n_test=10, d=48 if cfg == 2 else None)
+    _compare(gen.base(), gen.train(), Nq, M, L, oracle_lib)
+
+
+def test_thread_count_does_not_change_graph(oracle_lib):
+    gen = datagen.Generator(1, n=1500, n_train=1500, n_test=10)
+    X, T = gen.base(), gen.train()
+    knn, _ = oracle_lib.knn(X, T, 16)
+    a = rg.rg_build_from_knn(X, knn, 16, 16, L_build=100, threads=1).graph()
+    b = rg.rg_build_from_knn(X, knn, 16, 16, L_build=100, threads=7).graph()
+    assert all(np.array_equal(x, y) for x, y in zip(a[:2], b[:2])) and a[2] == b[2]
+
+
+def test_paper_literal_degree_split(oracle_lib):
+    # both phases at the same bound (the paper uses one M for both, Sec. 5.1)
+    gen = datagen.Generator(1, n=1000, n_train=1000, n_test=10)
+    _compare(gen.base(), gen.train(), 16, 21, 100, oracle_lib, m_pj=10, m_ce=10)
+
+
+def test_training_set_smaller_than_base(oracle_lib):
+    # |T| = 0.1 |X| (the query-set-size study, Sec. 5.5)
+    gen = datagen.Generator(1, n=2000, n_train=200, n_test=10)
+    _compare(gen.base(), gen.train(), 16, 16, 100, oracle_lib)
+
+
+def test_build_from_knn_rejects_bad_input():
+    X = np.zeros((10, 4), np.float32)
+    with pytest.raises(rg.RGError):
+        rg.rg_build_from_knn(X, np.zeros((5, 2), np.uint32), 2, 2)        # M < 3
+    with pytest.raises(rg.RGError):
+        rg.rg_build_from_knn(X, np.full((5, 2), 99, np.uint32), 2, 8)     # ids out of range
