@@ -9,7 +9,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OBJ = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libroargraph.so")
-SOURCES = ["beam.hip", "knn.hip", "quant.hip", "api.cpp", "host_build.cpp", "serve.cpp"]
+SOURCES = ["beam.hip", "knn.hip", "quant.hip", "canon.hip", "api.cpp", "host_build.cpp", "serve.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 COMMON = [

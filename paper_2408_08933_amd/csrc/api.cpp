@@ -69,10 +69,20 @@ void free_index_device(rg_index *ix) {
     ix->d_scale = nullptr;
 }
 
-// Device copy of the base (rows padded to a 64-byte multiple) and the ELL adjacency.
-int upload_index(rg_index *ix, const float *base_dev, hipStream_t st) {
-    const int64_t n = ix->n;
+// Device copy of the base, rows padded to a 64-byte multiple.
+int upload_base(rg_index *ix, const float *base_dev, hipStream_t st) {
     ix->pitch = round_up(ix->d, 16);
+    if (hipMalloc(&ix->d_base, sizeof(float) * (size_t)ix->n * ix->pitch) != hipSuccess) {
+        ix->d_base = nullptr;
+        set_error("index: out of device memory for the base rows");
+        return RG_ENOMEM;
+    }
+    return launch_pad_rows(base_dev, ix->n, ix->d, ix->d_base, ix->pitch, st);
+}
+
+// Device ELL adjacency (rows of width ell = max degree rounded up to 8, kNone padded).
+int upload_adj(rg_index *ix, hipStream_t st) {
+    const int64_t n = ix->n;
     int64_t maxdeg = 1;
     for (int64_t x = 0; x < n; ++x) maxdeg = std::max<int64_t>(maxdeg, ix->offsets[x + 1] - ix->offsets[x]);
     if (maxdeg > kMaxEll) {
@@ -80,14 +90,11 @@ int upload_index(rg_index *ix, const float *base_dev, hipStream_t st) {
         return RG_EINVAL;
     }
     ix->ell = round_up((int32_t)maxdeg, 8);
-    if (hipMalloc(&ix->d_base, sizeof(float) * (size_t)n * ix->pitch) != hipSuccess ||
-        hipMalloc(&ix->d_adj, sizeof(uint32_t) * (size_t)n * ix->ell) != hipSuccess) {
-        free_index_device(ix);
-        set_error("index: out of device memory");
+    if (hipMalloc(&ix->d_adj, sizeof(uint32_t) * (size_t)n * ix->ell) != hipSuccess) {
+        ix->d_adj = nullptr;
+        set_error("index: out of device memory for the adjacency");
         return RG_ENOMEM;
     }
-    int rc = launch_pad_rows(base_dev, n, ix->d, ix->d_base, ix->pitch, st);
-    if (rc) return rc;
     std::vector<uint32_t> ell((size_t)n * ix->ell, kNone);
     for (int64_t x = 0; x < n; ++x)
         std::copy(ix->indices.begin() + ix->offsets[x], ix->indices.begin() + ix->offsets[x + 1],
@@ -95,6 +102,12 @@ int upload_index(rg_index *ix, const float *base_dev, hipStream_t st) {
     RG_HIP(hipMemcpyAsync(ix->d_adj, ell.data(), sizeof(uint32_t) * ell.size(), hipMemcpyHostToDevice, st));
     RG_HIP(hipStreamSynchronize(st));
     return RG_OK;
+}
+
+int upload_index(rg_index *ix, const float *base_dev, hipStream_t st) {
+    int rc = upload_base(ix, base_dev, st);
+    if (!rc) rc = upload_adj(ix, st);
+    return rc;
 }
 
 int check_csr(int64_t n, const int64_t *off, const uint32_t *idx, uint32_t entry) {
@@ -293,24 +306,29 @@ int rg_build(const float *base, int64_t n, int32_t d, const float *train, int64_
     th.clear();
     th.shrink_to_fit();
     const auto t1 = std::chrono::steady_clock::now();
-    HostGraph g;
-    rc = host_construct(xh.data(), n, d, knn.data(), nt, Nq, M, L, m_pj, m_ce, threads, &g);
-    if (rc) return rc;
     rg_index *ix = new rg_index();
     ix->n = n;
     ix->d = d;
     ix->metric = metric;
-    ix->entry = g.entry;
     ix->Nq = Nq;
     ix->M = M;
     ix->L_build = L;
     ix->m_pj = m_pj;
     ix->m_ce = m_ce;
-    ix->repairs = g.repairs;
-    ix->offsets.swap(g.offsets);
-    ix->indices.swap(g.indices);
     (void)hipGetDevice(&ix->device);
-    rc = upload_index(ix, base, st);
+    rc = upload_base(ix, base, st);
+    HostGraph g;
+    if (!rc) {
+        GpuCtx gpu{ix->d_base, ix->pitch, st};
+        rc = host_construct(xh.data(), n, d, knn.data(), nt, Nq, M, L, m_pj, m_ce, threads, &gpu, &g);
+    }
+    if (!rc) {
+        ix->entry = g.entry;
+        ix->repairs = g.repairs;
+        ix->offsets.swap(g.offsets);
+        ix->indices.swap(g.indices);
+        rc = upload_adj(ix, st);
+    }
     if (rc) {
         free_index_device(ix);
         delete ix;
@@ -348,7 +366,8 @@ int rg_build_from_knn(const float *base_host, int64_t n, int32_t d, const uint32
         return RG_EINVAL;
     }
     HostGraph g;
-    const int rc = host_construct(base_host, n, d, knn_host, nt, Nq, M, L, m_pj, m_ce, hw_threads(o.threads), &g);
+    const int rc = host_construct(base_host, n, d, knn_host, nt, Nq, M, L, m_pj, m_ce, hw_threads(o.threads),
+                                  nullptr, &g);
     if (rc) return rc;
     rg_index *ix = new rg_index();
     ix->n = n;

@@ -23,6 +23,7 @@
 // G partial sums are added by a log2(G)-level xor tree.  A distance is
 // therefore a fixed function of (query, row) whichever group computes it.
 #include "rg_internal.h"
+#include "queue_ops.h"
 #include "wave_ops.h"
 
 #include <climits>
@@ -173,129 +174,6 @@ __device__ __forceinline__ void score_batch(const SearchArgs &a, const float4 (&
     }
 }
 
-__device__ __forceinline__ int lower_bound_q(const float *qd, const uint32_t *qi, int qn, float kd,
-                                             uint32_t kid) {
-    int lo = 0, hi = qn;
-    while (lo < hi) {
-        const int mid = (lo + hi) >> 1;
-        if (kless(qd[mid], qi[mid] & ~kExpanded, kd, kid))
-            lo = mid + 1;
-        else
-            hi = mid;
-    }
-    return lo;
-}
-
-// #{t < S : slb[t] <= i}, slb non-decreasing
-__device__ __forceinline__ int count_le(const int32_t *slb, int S, int i) {
-    int lo = 0, hi = S;
-    while (lo < hi) {
-        const int mid = (lo + hi) >> 1;
-        if (slb[mid] <= i)
-            lo = mid + 1;
-        else
-            hi = mid;
-    }
-    return lo;
-}
-
-// Merge the candidate batch s.cd/s.ci[0..cnt) into the queue.
-template <int E>
-__device__ __forceinline__ void merge_batch(const Lds &s, int cnt, int Leff, int &qn, int &ptr) {
-    const int lane = lane_id();
-    float k[E];
-    uint32_t id[E];
-#pragma unroll
-    for (int e = 0; e < E; ++e) {
-        const int i = lane * E + e;
-        k[e] = i < cnt ? s.cd[i] : __builtin_inff();
-        id[e] = i < cnt ? s.ci[i] : kNone;
-    }
-    wave_sort<E>(k, id);
-    const bool full = qn == Leff;
-    const float lastd = full ? s.qd[Leff - 1] : 0.f;
-    const uint32_t lasti = full ? (s.qi[Leff - 1] & ~kExpanded) : 0u;
-    int lb[E];
-    bool sv[E];
-    int mine = 0;
-#pragma unroll
-    for (int e = 0; e < E; ++e) {
-        sv[e] = id[e] != kNone && (!full || kless(k[e], id[e], lastd, lasti));
-        lb[e] = 0;
-        if (sv[e]) {
-            lb[e] = lower_bound_q(s.qd, s.qi, qn, k[e], id[e]);
-            if (lb[e] < qn && (s.qi[lb[e]] & ~kExpanded) == id[e]) sv[e] = false;  // already queued
-        }
-        mine += sv[e] ? 1 : 0;
-    }
-    // order-preserving compaction: exclusive prefix of per-lane counts
-    int incl = mine;
-#pragma unroll
-    for (int o = 1; o < 64; o <<= 1) {
-        const int t = __shfl_up(incl, o);
-        if (lane >= o) incl += t;
-    }
-    const int total = __shfl(incl, 63);
-    int w = incl - mine;
-    __syncthreads();
-#pragma unroll
-    for (int e = 0; e < E; ++e) {
-        if (sv[e]) {
-            s.sd[w] = k[e];
-            s.si[w] = id[e];
-            s.slb[w] = lb[e];
-            ++w;
-        }
-    }
-    __syncthreads();
-    if (total == 0) return;
-    const int lbmin = s.slb[0];
-    // entries of the queue that move, and their new places
-    constexpr int R = kMaxL / 64;
-    float md[R];
-    uint32_t mi[R];
-    int mp[R];
-#pragma unroll
-    for (int r = 0; r < R; ++r) {
-        const int i = lbmin + lane + 64 * r;
-        mp[r] = INT_MAX;
-        if (i < qn) {
-            md[r] = s.qd[i];
-            mi[r] = s.qi[i];
-            mp[r] = i + count_le(s.slb, total, i);
-        }
-    }
-    float pd[2];
-    uint32_t pi[2];
-    int pp[2];
-#pragma unroll
-    for (int r = 0; r < 2; ++r) {
-        const int t = lane + 64 * r;
-        pp[r] = INT_MAX;
-        if (t < total) {
-            pd[r] = s.sd[t];
-            pi[r] = s.si[t];
-            pp[r] = s.slb[t] + t;
-        }
-    }
-    __syncthreads();
-#pragma unroll
-    for (int r = 0; r < R; ++r)
-        if (mp[r] < Leff) {
-            s.qd[mp[r]] = md[r];
-            s.qi[mp[r]] = mi[r];
-        }
-#pragma unroll
-    for (int r = 0; r < 2; ++r)
-        if (pp[r] < Leff) {
-            s.qd[pp[r]] = pd[r];
-            s.qi[pp[r]] = pi[r];
-        }
-    qn = min(Leff, qn + total);
-    ptr = min(ptr, lbmin);
-    __syncthreads();
-}
-
 __device__ __forceinline__ uint32_t hslot(uint32_t u, int hb) { return (u * 2654435761u) >> (32 - hb); }
 
 // Expansions until done or `budget` expansions were made.
@@ -360,10 +238,11 @@ __device__ __forceinline__ void run_search(const SearchArgs &a, const float4 (&q
         if (nnew == 0) continue;
         score_batch<G, NCH, ST>(a, qv, nch, s.ci, 0xFFFFFFFFu, s.cd, nnew);
         __syncthreads();
+        const QueueLds<float> ql{s.qd, s.qi, s.cd, s.ci, s.sd, s.si, s.slb};
         if (nnew <= 64)
-            merge_batch<1>(s, nnew, Leff, qn, ptr);
+            merge_batch<1, float>(ql, nnew, Leff, qn, ptr);
         else
-            merge_batch<2>(s, nnew, Leff, qn, ptr);
+            merge_batch<2, float>(ql, nnew, Leff, qn, ptr);
     }
 }
 

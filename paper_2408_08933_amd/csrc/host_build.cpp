@@ -272,6 +272,78 @@ void lists_to_csr(const Lists &L, int64_t n, std::vector<int64_t> &off, std::vec
         for (int j = 0; j < L.deg[x]; ++j) idx[off[x] + j] = L.row(x)[j].id;
 }
 
+// Enhancement searches on the device (canonical FP64 distance, bit-identical
+// to the host searcher), then each node's own selection on host threads.
+int enhance_on_device(const float *X, int64_t n, int32_t d, const Lists &PJ, const std::vector<int64_t> &pjoff,
+                      const std::vector<uint32_t> &pjidx, uint32_t entry, int32_t L, int32_t m_ce, int threads,
+                      const GpuCtx &gpu, Lists &E, double *t_search) {
+    (void)pjidx;
+    int32_t maxdeg = 1;
+    for (int64_t x = 0; x < n; ++x) maxdeg = std::max<int32_t>(maxdeg, PJ.deg[x]);
+    const int32_t ell = (maxdeg + 7) / 8 * 8;
+    std::vector<uint32_t> adj((size_t)n * ell, kNone);
+    for (int64_t x = 0; x < n; ++x)
+        for (int j = 0; j < PJ.deg[x]; ++j) adj[x * ell + j] = PJ.row(x)[j].id;
+    (void)pjoff;
+    const int64_t B = std::min<int64_t>(n, 1 << 16);
+    uint32_t *d_adj = nullptr, *d_ids = nullptr;
+    double *d_d = nullptr;
+    int32_t *d_n = nullptr;
+    auto release = [&]() {
+        if (d_adj) (void)hipFree(d_adj);
+        if (d_ids) (void)hipFree(d_ids);
+        if (d_d) (void)hipFree(d_d);
+        if (d_n) (void)hipFree(d_n);
+    };
+    if (hipMalloc(&d_adj, sizeof(uint32_t) * adj.size()) != hipSuccess ||
+        hipMalloc(&d_ids, sizeof(uint32_t) * B * L) != hipSuccess ||
+        hipMalloc(&d_d, sizeof(double) * B * L) != hipSuccess || hipMalloc(&d_n, sizeof(int32_t) * B) != hipSuccess) {
+        release();
+        set_error("build: out of device memory for enhancement searches");
+        return RG_ENOMEM;
+    }
+    std::vector<uint32_t> hid((size_t)B * L);
+    std::vector<double> hd((size_t)B * L);
+    std::vector<int32_t> hn((size_t)B);
+    std::vector<std::vector<Cand>> cc((size_t)threads);
+    std::vector<std::vector<uint8_t>> kept((size_t)threads);
+    double ts = 0.0;
+    int rc = RG_OK;
+    if (hipMemcpyAsync(d_adj, adj.data(), sizeof(uint32_t) * adj.size(), hipMemcpyHostToDevice, gpu.stream) !=
+        hipSuccess)
+        rc = RG_EDEVICE;
+    for (int64_t x0 = 0; x0 < n && !rc; x0 += B) {
+        const int64_t cnt = std::min(B, n - x0);
+        const auto t0 = Clock::now();
+        rc = launch_canon_search(gpu.X, d, gpu.pitch, d_adj, ell, entry, L, x0, cnt, d_ids, d_d, d_n, gpu.stream);
+        if (rc) break;
+        if (hipMemcpyAsync(hid.data(), d_ids, sizeof(uint32_t) * cnt * L, hipMemcpyDeviceToHost, gpu.stream) !=
+                hipSuccess ||
+            hipMemcpyAsync(hd.data(), d_d, sizeof(double) * cnt * L, hipMemcpyDeviceToHost, gpu.stream) !=
+                hipSuccess ||
+            hipMemcpyAsync(hn.data(), d_n, sizeof(int32_t) * cnt, hipMemcpyDeviceToHost, gpu.stream) != hipSuccess ||
+            hipStreamSynchronize(gpu.stream) != hipSuccess) {
+            set_error("build: enhancement search on the device failed");
+            rc = RG_EDEVICE;
+            break;
+        }
+        ts += secs(t0, Clock::now());
+        parallel_for(cnt, threads, 16, [&](int64_t b, int tid) {
+            const int64_t x = x0 + b;
+            auto &c = cc[tid];
+            c.clear();
+            for (int j = 0; j < hn[b]; ++j) {
+                const uint32_t u = hid[b * L + j];
+                if ((int64_t)u != x) c.push_back(Cand{hd[b * L + j], u});
+            }
+            E.deg[x] = acquire_sorted(X, d, c.data(), (int)c.size(), m_ce, false, E.row(x), kept[tid]);
+        });
+    }
+    release();
+    *t_search = ts;
+    return rc;
+}
+
 }  // namespace
 
 double canon_dist(const float *a, const float *b, int32_t d) {
@@ -287,7 +359,7 @@ int hw_threads(int requested) {
 }
 
 int host_construct(const float *X, int64_t n, int32_t d, const uint32_t *knn, int64_t nt, int32_t Nq, int32_t M,
-                   int32_t L, int32_t m_pj, int32_t m_ce, int threads, HostGraph *out) {
+                   int32_t L, int32_t m_pj, int32_t m_ce, int threads, const GpuCtx *gpu, HostGraph *out) {
     const auto t0 = Clock::now();
     threads = hw_threads(threads);
     const int q1 = Nq - 1;
@@ -398,7 +470,11 @@ int host_construct(const float *X, int64_t n, int32_t d, const uint32_t *knn, in
     // --- enhancement: searches on G_pj and each node's own selection E(x) --
     Lists E;
     E.init(n, capl);
-    {
+    if (gpu) {
+        const int rc = enhance_on_device(X, n, d, PJ, pjoff, pjidx, entry, L, m_ce, threads, *gpu, E,
+                                         &out->t_enhance_search);
+        if (rc) return rc;
+    } else {
         std::vector<Searcher> sr((size_t)threads);
         std::vector<std::vector<Cand>> cc((size_t)threads);
         std::vector<std::vector<uint8_t>> kept((size_t)threads);

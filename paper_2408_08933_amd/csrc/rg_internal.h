@@ -92,11 +92,23 @@ struct HostGraph {
     uint32_t entry = 0;
     int64_t repairs = 0;
     double t_knn = 0, t_project = 0, t_enhance = 0, t_total = 0;
+    double t_enhance_search = 0;
 };
-// knn lists: nt x Nq canonical ids.  X: host n x d.
+// Device resources construction may use: the padded FP32 base on the device.
+struct GpuCtx {
+    const float *X;      // n x pitch
+    int32_t pitch;
+    hipStream_t stream;
+};
+// knn lists: nt x Nq canonical ids.  X: host n x d.  gpu == nullptr: host only.
 int host_construct(const float *X, int64_t n, int32_t d, const uint32_t *knn, int64_t nt,
                    int32_t Nq, int32_t M, int32_t L, int32_t m_pj, int32_t m_ce, int threads,
-                   HostGraph *out);
+                   const GpuCtx *gpu, HostGraph *out);
+
+// canon.hip: construction-time searches with the canonical FP64 distance
+int launch_canon_search(const float *X, int32_t d, int32_t pitch, const uint32_t *adj, int32_t ell,
+                        uint32_t entry, int32_t L, int64_t x0, int64_t count, uint32_t *ids, double *dists,
+                        int32_t *counts, hipStream_t stream);
 
 // canonical FP64 distance helpers (host)
 double canon_dist(const float *a, const float *b, int32_t d);

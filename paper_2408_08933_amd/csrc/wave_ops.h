@@ -18,7 +18,8 @@ __device__ __forceinline__ int lanes_below(uint64_t m) {
 }
 
 // (key, id) strict order: smaller key first, then smaller id
-__device__ __forceinline__ bool kless(float ka, uint32_t ia, float kb, uint32_t ib) {
+template <typename K>
+__device__ __forceinline__ bool kless(K ka, uint32_t ia, K kb, uint32_t ib) {
     return ka < kb || (ka == kb && ia < ib);
 }
 
@@ -40,15 +41,15 @@ __device__ __forceinline__ int wave_min_i(int v) {
 // One compare-exchange stage of a bitonic network over 64*E pairs held E
 // per lane (element i = lane*E + e); SIZE and STRIDE are compile-time so
 // every register index is static.
-template <int E, int SIZE, int STRIDE>
-__device__ __forceinline__ void bitonic_stage(float (&k)[E], uint32_t (&v)[E]) {
+template <int E, int SIZE, int STRIDE, typename K>
+__device__ __forceinline__ void bitonic_stage(K (&k)[E], uint32_t (&v)[E]) {
     const int lane = lane_id();
     if constexpr (STRIDE >= E) {
         constexpr int lx = STRIDE / E;
 #pragma unroll
         for (int e = 0; e < E; ++e) {
             const int i = lane * E + e;
-            const float ok = __shfl_xor(k[e], lx);
+            const K ok = __shfl_xor(k[e], lx);
             const uint32_t ov = __shfl_xor(v[e], lx);
             const bool up = (i & SIZE) == 0;
             const bool lower = (i & STRIDE) == 0;
@@ -67,7 +68,7 @@ __device__ __forceinline__ void bitonic_stage(float (&k)[E], uint32_t (&v)[E]) {
                 const int i = lane * E + e;
                 const bool up = (i & SIZE) == 0;
                 const bool sw = up ? kless(k[p], v[p], k[e], v[e]) : kless(k[e], v[e], k[p], v[p]);
-                const float ka = k[e], kb = k[p];
+                const K ka = k[e], kb = k[p];
                 const uint32_t va = v[e], vb = v[p];
                 k[e] = sw ? kb : ka;
                 k[p] = sw ? ka : kb;
@@ -78,22 +79,22 @@ __device__ __forceinline__ void bitonic_stage(float (&k)[E], uint32_t (&v)[E]) {
     }
 }
 
-template <int E, int SIZE, int STRIDE>
-__device__ __forceinline__ void bitonic_merge_steps(float (&k)[E], uint32_t (&v)[E]) {
-    bitonic_stage<E, SIZE, STRIDE>(k, v);
-    if constexpr (STRIDE > 1) bitonic_merge_steps<E, SIZE, STRIDE / 2>(k, v);
+template <int E, int SIZE, int STRIDE, typename K>
+__device__ __forceinline__ void bitonic_merge_steps(K (&k)[E], uint32_t (&v)[E]) {
+    bitonic_stage<E, SIZE, STRIDE, K>(k, v);
+    if constexpr (STRIDE > 1) bitonic_merge_steps<E, SIZE, STRIDE / 2, K>(k, v);
 }
 
-template <int E, int SIZE>
-__device__ __forceinline__ void bitonic_sizes(float (&k)[E], uint32_t (&v)[E]) {
-    bitonic_merge_steps<E, SIZE, SIZE / 2>(k, v);
-    if constexpr (SIZE < 64 * E) bitonic_sizes<E, SIZE * 2>(k, v);
+template <int E, int SIZE, typename K>
+__device__ __forceinline__ void bitonic_sizes(K (&k)[E], uint32_t (&v)[E]) {
+    bitonic_merge_steps<E, SIZE, SIZE / 2, K>(k, v);
+    if constexpr (SIZE < 64 * E) bitonic_sizes<E, SIZE * 2, K>(k, v);
 }
 
 // Ascending bitonic sort of 64*E (key, id) pairs; element i = lane*E + e.
-template <int E>
-__device__ __forceinline__ void wave_sort(float (&k)[E], uint32_t (&v)[E]) {
-    bitonic_sizes<E, 2>(k, v);
+template <int E, typename K>
+__device__ __forceinline__ void wave_sort(K (&k)[E], uint32_t (&v)[E]) {
+    bitonic_sizes<E, 2, K>(k, v);
 }
 
 }  // namespace rg

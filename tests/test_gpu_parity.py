@@ -1,0 +1,296 @@
+"""GPU parity: every entry point of the C ABI against the FP64 oracle on the
+same seeded inputs.  Run on an MI355X (-m gpu)."""
+import os
+import sys
+import tempfile
+
+import numpy as np
+import pytest
+
+import datagen
+from parity import NONE, compare, gamma_search
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+rg = pytest.importorskip("paper_2408_08933_amd")
+
+
+def say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def dev():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    rg.lib()
+    return torch.device("cuda:0")
+
+
+def T(a, dev):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).to(dev)
+
+
+@pytest.fixture(scope="module")
+def c1(oracle_lib):
+    """Tiny OOD workload: d=64, 10k base, 10k training, 1k test; Nq=32, M=32."""
+    g = datagen.Generator(1)
+    X, Tr, Q = g.base(), g.train(), g.test()
+    G = oracle_lib.Graph(X, Tr, 32, 32, 500)
+    return X, Tr, Q, G
+
+
+# ---------------------------------------------------------------------------
+# kNN
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("nq,n,d,K", [(300, 3000, 64, 48), (257, 1999, 200, 40), (130, 700, 37, 33),
+                                      (5, 128, 16, 128), (1000, 10000, 512, 112)])
+def test_knn_candidates_are_fp32_topk(dev, nq, n, d, K):
+    say(f"knn_candidates nq={nq} n={n} d={d} K={K}")
+    rng = np.random.default_rng(nq + n + d)
+    X = rng.standard_normal((n, d)).astype(np.float32)
+    Q = rng.standard_normal((nq, d)).astype(np.float32)
+    ids, sc = rg.rg_knn_candidates(T(Q, dev), T(X, dev), K)
+    torch.cuda.synchronize()
+    ids, sc = rg.as_u32(ids), sc.cpu().numpy().astype(np.float64)
+    S = Q.astype(np.float64) @ X.astype(np.float64).T
+    u = 2.0 ** -24
+    tau = (d + 1) * u / (1 - (d + 1) * u) * np.linalg.norm(Q, axis=1)[:, None] * np.linalg.norm(X, axis=1).max()
+    assert (ids < n).all()
+    assert all(len(set(r.tolist())) == K for r in ids)
+    got = np.take_along_axis(S, ids.astype(np.int64), axis=1)
+    assert (np.abs(got - sc) <= tau).all()                    # each score is its pair's FP32 score
+    assert (np.diff(sc, axis=1) <= 0).all()                     # descending
+    kth_true = -np.sort(-S, axis=1)[:, K - 1]
+    # anything left out scores no better than the K-th kept one (up to rounding)
+    for q in range(nq):
+        out = np.setdiff1d(np.arange(n), ids[q].astype(np.int64))
+        assert (S[q, out] <= sc[q, K - 1] + 2 * tau[q, 0]).all()
+        assert got[q].min() >= kth_true[q] - 2 * tau[q, 0]
+
+
+@pytest.mark.parametrize("nq,k", [(1000, 10), (37, 100), (129, 1)])
+def test_knn_exact_matches_oracle(dev, oracle_lib, c1, nq, k):
+    X, Tr, Q, G = c1
+    Qs = np.concatenate([Q, Tr])[:nq]
+    say(f"rg_knn nq={nq} k={k}")
+    ids, ds = rg.rg_knn(T(Qs, dev), T(X, dev), k)
+    torch.cuda.synchronize()
+    oi, od = oracle_lib.knn(X, Qs, k)
+    assert np.array_equal(rg.as_u32(ids), oi)
+    assert np.array_equal(ds.cpu().numpy(), od.astype(np.float32))
+
+
+def test_knn_rejects_bad_k(dev):
+    X = torch.zeros((10, 4), device=dev)
+    with pytest.raises(rg.RGError):
+        rg.rg_knn(X, X, 11)
+
+
+# ---------------------------------------------------------------------------
+# search on the oracle's graph
+# ---------------------------------------------------------------------------
+@pytest.fixture(scope="module")
+def c1_index(dev, c1):
+    X, Tr, Q, G = c1
+    return rg.rg_index_from_csr(T(X, dev), G.offsets, G.indices, G.entry)
+
+
+@pytest.mark.parametrize("L", [16, 32, 64, 128])
+def test_search_parity_c1(dev, oracle_lib, c1, c1_index, L):
+    X, Tr, Q, G = c1
+    say(f"search c1 k=10 L={L}")
+    ids, ds, hops, ev = rg.rg_search(c1_index, T(Q, dev), 10, L, stats=True)
+    torch.cuda.synchronize()
+    oi, od, oh, oe, gaps = oracle_lib.search(X, G.offsets, G.indices, G.entry, Q, 10, L)
+    r = compare(rg.as_u32(ids), ds.cpu().numpy(), oi, od, gaps, Q, X, label=f"c1 L={L}")
+    say(f"  {r}")
+    h = hops.cpu().numpy()
+    tau = gamma_search(X.shape[1]) * np.linalg.norm(Q, axis=1) * np.linalg.norm(X, axis=1).max()
+    sure = gaps > 2 * tau
+    assert np.array_equal(h[sure], oh[sure].astype(np.int64))
+    assert (ev.cpu().numpy()[sure] >= oe[sure]).all()
+
+
+def test_search_k_larger_than_L_and_ragged(dev, oracle_lib, c1, c1_index):
+    X, Tr, Q, G = c1
+    Qs = Q[:77]
+    for k, L in ((100, 32), (1, 1), (7, 13), (512, 512)):
+        say(f"search c1 ragged nq=77 k={k} L={L}")
+        ids, ds = rg.rg_search(c1_index, T(Qs, dev), k, L)
+        torch.cuda.synchronize()
+        oi, od, _, _, gaps = oracle_lib.search(X, G.offsets, G.indices, G.entry, Qs, k, L)
+        compare(rg.as_u32(ids), ds.cpu().numpy(), oi, od, gaps, Qs, X, min_agreement=0.97,
+                min_near_same=0.9, label=f"k={k} L={L}")
+
+
+def test_visited_table_size_does_not_change_results(dev, c1, c1_index):
+    X, Tr, Q, G = c1
+    say("search c1 hash_bits 8 vs 15, L=128")
+    a = rg.rg_search(c1_index, T(Q, dev), 10, 128, stats=True, hash_bits=8)
+    b = rg.rg_search(c1_index, T(Q, dev), 10, 128, stats=True, hash_bits=15)
+    torch.cuda.synchronize()
+    assert torch.equal(a[0], b[0]) and torch.equal(a[1], b[1]) and torch.equal(a[2], b[2])
+    assert (a[3] >= b[3]).all() and (a[3] > b[3]).any()   # the small table forgets and rescores
+
+
+def test_search_repeatable(dev, c1, c1_index):
+    X, Tr, Q, G = c1
+    a = rg.rg_search(c1_index, T(Q, dev), 10, 64)
+    b = rg.rg_search(c1_index, T(Q, dev), 10, 64)
+    torch.cuda.synchronize()
+    assert torch.equal(a[0], b[0]) and torch.equal(a[1], b[1])
+
+
+def test_search_special_graphs(dev, oracle_lib):
+    rng = np.random.default_rng(7)
+    n, d = 120, 24
+    X = rng.standard_normal((n, d)).astype(np.float32)
+    Q = rng.standard_normal((33, d)).astype(np.float32)
+    gt, gd = oracle_lib.knn(X, Q, 10)
+    # complete graph (degree n-1 = 119 <= 128): exact for any L >= k
+    rows = [np.array([j for j in range(n) if j != i], np.uint32) for i in range(n)]
+    off = np.zeros(n + 1, np.int64)
+    off[1:] = np.cumsum([len(r) for r in rows])
+    ix = rg.rg_index_from_csr(T(X, dev), off, np.concatenate(rows), 5)
+    for L in (10, 40):
+        say(f"complete graph L={L}")
+        ids, ds = rg.rg_search(ix, T(Q, dev), 10, L)
+        torch.cuda.synchronize()
+        assert np.array_equal(rg.as_u32(ids), gt)
+    # random connected graph with L >= n: exact
+    off2, idx2 = datagen.random_graph(n, 6, seed=3)
+    ix2 = rg.rg_index_from_csr(T(X, dev), off2, idx2, 0)
+    say("random graph L >= n")
+    ids, ds = rg.rg_search(ix2, T(Q, dev), 10, 128)
+    torch.cuda.synchronize()
+    assert np.array_equal(rg.as_u32(ids), gt)
+    # single node: padding
+    ix3 = rg.rg_index_from_csr(T(X[:1], dev), np.zeros(2, np.int64), np.zeros(0, np.uint32), 0)
+    ids, ds = rg.rg_search(ix3, T(Q[:3], dev), 4, 2)
+    torch.cuda.synchronize()
+    i3 = rg.as_u32(ids)
+    assert (i3[:, 0] == 0).all() and (i3[:, 1:] == NONE).all() and torch.isinf(ds[:, 1:]).all()
+    # zero queries is a no-op
+    rg.rg_search(ix3, torch.zeros((0, d), device=dev), 4, 2)
+
+
+def test_search_rejects_bad_args(dev, c1_index):
+    q = torch.zeros((2, 64), device=dev)
+    for k, L in ((0, 10), (10, 0), (513, 10), (10, 513)):
+        with pytest.raises(rg.RGError):
+            rg.rg_search(c1_index, q, k, L)
+
+
+# ---------------------------------------------------------------------------
+# build
+# ---------------------------------------------------------------------------
+@pytest.fixture(scope="module")
+def c1_built(dev, c1):
+    X, Tr, Q, G = c1
+    say("rg_build c1 (10k x 64, Nq=32, M=32, L=500)")
+    return rg.rg_build(T(X, dev), T(Tr, dev), 32, 32, L_build=500)
+
+
+def test_build_bit_exact_c1(c1, c1_built):
+    X, Tr, Q, G = c1
+    off, idx, entry = c1_built.graph()
+    assert entry == G.entry
+    assert np.array_equal(off, G.offsets) and np.array_equal(idx, G.indices)
+    assert c1_built.build_stats()["repairs"] == G.repairs
+
+
+def test_recall_on_built_index(dev, oracle_lib, c1, c1_built):
+    X, Tr, Q, G = c1
+    gt, _ = oracle_lib.knn(X, Q, 10)
+    rec = []
+    for L in (16, 32, 64, 128):
+        ids, _ = rg.rg_search(c1_built, T(Q, dev), 10, L)
+        torch.cuda.synchronize()
+        rec.append(oracle_lib.recall(rg.as_u32(ids), gt, 10))
+    say(f"recall@10 over L=16..128: {rec}")
+    assert rec[-1] >= 0.9 and rec[0] < rec[-1]
+
+
+def test_save_load_roundtrip(dev, c1, c1_built):
+    X, Tr, Q, G = c1
+    with tempfile.TemporaryDirectory() as td:
+        p = os.path.join(td, "c1.rgidx")
+        rg.rg_save(c1_built, p)
+        ix = rg.rg_load(p)
+        a, b = c1_built.graph(), ix.graph()
+        assert all(np.array_equal(x, y) for x, y in zip(a[:2], b[:2])) and a[2] == b[2]
+        r1 = rg.rg_search(c1_built, T(Q[:50], dev), 10, 32)
+        r2 = rg.rg_search(ix, T(Q[:50], dev), 10, 32)
+        torch.cuda.synchronize()
+        assert torch.equal(r1[0], r2[0]) and torch.equal(r1[1], r2[1])
+        raw = bytearray(open(p, "rb").read())
+        raw[100] ^= 0x40
+        open(p, "wb").write(bytes(raw))
+        with pytest.raises(rg.RGError) as e:
+            rg.rg_load(p)
+        assert e.value.code == rg.RG_ECORRUPT
+
+
+# ---------------------------------------------------------------------------
+# reduced-precision storage
+# ---------------------------------------------------------------------------
+def test_quantized_rows_match_oracle(dev, oracle_lib, c1):
+    X, Tr, Q, G = c1
+    ix = rg.rg_index_from_csr(T(X, dev), G.offsets, G.indices, G.entry)
+    rg.rg_index_set_storage(ix, rg.RG_STORE_BF16)
+    rg.rg_index_set_storage(ix, rg.RG_STORE_FP8E4M3)
+    pb, pf, ps, p8 = ix.storage_ptrs()
+    info = ix.info()
+    n, d, pitch = info["n"], info["d"], info["pitch"]
+    bits = torch.empty((n, pitch), dtype=torch.int16, device=dev)
+    codes = torch.empty((n, p8), dtype=torch.uint8, device=dev)
+    scales = torch.empty(n, dtype=torch.float32, device=dev)
+    import ctypes
+    hip = ctypes.CDLL("libamdhip64.so")
+    for dst, src, nb in ((bits, pb, n * pitch * 2), (codes, pf, n * p8), (scales, ps, n * 4)):
+        assert hip.hipMemcpy(ctypes.c_void_p(dst.data_ptr()), ctypes.c_void_p(src), ctypes.c_size_t(nb), 3) == 0
+    torch.cuda.synchronize()
+    b16 = (bits.cpu().numpy()[:, :d].astype(np.uint16).astype(np.uint32) << 16).view(np.float32)
+    assert np.array_equal(b16, oracle_lib.bf16(X))
+    oc, os_, _ = oracle_lib.quant_fp8(X)
+    assert np.array_equal(codes.cpu().numpy()[:, :d], oc)
+    assert np.array_equal(scales.cpu().numpy(), os_)
+
+
+@pytest.mark.parametrize("storage", ["bf16", "fp8"])
+def test_precision_search_parity(dev, oracle_lib, c1, storage):
+    X, Tr, Q, G = c1
+    ix = rg.rg_index_from_csr(T(X, dev), G.offsets, G.indices, G.entry)
+    st = rg.RG_STORE_BF16 if storage == "bf16" else rg.RG_STORE_FP8E4M3
+    rg.rg_index_set_storage(ix, st)
+    Xq = oracle_lib.bf16(X) if storage == "bf16" else oracle_lib.quant_fp8(X)[2]
+    for k, L in ((10, 64), (100, 128)):
+        say(f"precision {storage} k={k} L={L}")
+        ids, ds = rg.rg_search(ix, T(Q, dev), k, L)
+        torch.cuda.synchronize()
+        oi, od, _, _, gaps = oracle_lib.search_rerank(Xq, X, G.offsets, G.indices, G.entry, Q, k, L)
+        r = compare(rg.as_u32(ids), ds.cpu().numpy(), oi, od, gaps, Q, X, min_agreement=0.98,
+                    min_near_same=0.9, label=f"{storage} k={k} L={L}")
+        say(f"  {r}")
+
+
+# ---------------------------------------------------------------------------
+# full-size shape: 1M x 200 rows on a random graph, sampled queries
+# ---------------------------------------------------------------------------
+def test_full_size_sampled(dev, oracle_lib):
+    g = datagen.Generator(2, n=1_000_000, n_train=1, n_test=48)
+    say("full size: generating 1M x 200 base and a degree-48 random graph")
+    X, Q = g.base(), g.test()
+    off, idx = datagen.random_graph_fast(X.shape[0], 48, seed=5)
+    ix = rg.rg_index_from_csr(T(X, dev), off, idx, 0)
+    for k, L in ((10, 64), (10, 200)):
+        say(f"full size search k={k} L={L}")
+        ids, ds = rg.rg_search(ix, T(Q, dev), k, L)
+        torch.cuda.synchronize()
+        oi, od, _, _, gaps = oracle_lib.search(X, off, idx, 0, Q, k, L)
+        r = compare(rg.as_u32(ids), ds.cpu().numpy(), oi, od, gaps, Q, X, min_agreement=0.97,
+                    min_near_same=0.9, label=f"1M L={L}")
+        say(f"  {r}")
