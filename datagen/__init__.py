@@ -11,14 +11,25 @@ the generators below stand in for them with Gaussian mixtures whose query
 distribution is shifted by a fixed "modality gap" vector, so queries sit far
 from the base and their true neighbours are spread apart (Sec. 3).
 
-Recipe (per config, all draws from numpy PCG64):
+Two laws (all draws from numpy PCG64):
+
+Isotropic mixture (the tiny d=64 config, whose spread is given as sigma):
   * centres c_j ~ N(0, I_d), normalised to unit norm; base and query
     mixtures use independent centre sets;
   * point = c_z + sigma * g, z ~ U{0..K-1}, g ~ N(0, I_d) (each component is
-    N(c_z, sigma^2 I), sigma = 0.3);
-  * query = s (.) (c'_z + noise) + G * u, u a fixed random unit vector,
-    s a per-dimension scale (all ones unless the config says otherwise);
-  * rows are L2-normalised when the config is a cosine workload.
+    N(c_z, sigma^2 I), sigma = 0.3).
+
+Low-rank mixture (the d=200 / d=512 configs, whose spread is not given).
+Real text and image embeddings have an intrinsic dimension far below d;
+both modalities live in one shared semantic subspace:
+  * U = a random orthonormal d x r basis (r = 32), shared by both sets;
+  * latent centres c_j ~ N(0, I_r), independent sets for base and queries;
+  * h = c_z + 0.5 g_r, point = (U h + 0.6 g_d) / sqrt(r), g ~ N(0, I).
+
+For both laws a query is s (.) point' + G u, with point' from the query
+mixture, u a fixed random unit vector (the "modality gap", norm G) and s a
+per-dimension scale (all ones unless the config says otherwise); rows are
+L2-normalised when the config is a cosine workload.
 Seeds: 240808933 + 1000 * config + stream, one stream per role.
 """
 from __future__ import annotations
@@ -29,7 +40,7 @@ import numpy as np
 SEED_BASE = 240808933
 
 # stream ids, one per independent role
-S_BASE_CENTRES, S_BASE_POINTS, S_QUERY_CENTRES, S_GAP, S_SCALE, S_TRAIN, S_TEST, S_REQ, S_GRAPH = range(9)
+S_BASE_CENTRES, S_BASE_POINTS, S_QUERY_CENTRES, S_GAP, S_SCALE, S_TRAIN, S_TEST, S_REQ, S_GRAPH, S_BASIS = range(10)
 
 
 @dataclasses.dataclass(frozen=True)
@@ -48,15 +59,22 @@ class Workload:
     Nq: int
     M: int
     sigma: float = 0.3
+    latent: int = 0          # 0: isotropic law; r > 0: low-rank law with an r-dim shared subspace
+    latent_spread: float = 0.5
+    ambient_noise: float = 0.6
 
 
 # The five workloads (d, N, centres, gap, normalisation, build parameters).
 WORKLOADS = {
     1: Workload("tiny-ood-d64", 1, 64, 10_000, 10_000, 1_000, 16, 16, 1.0, True, None, 32, 32),
-    2: Workload("t2i-like-d200", 2, 200, 1_000_000, 1_000_000, 10_000, 256, 256, 1.5, False, (0.5, 1.5), 100, 64),
-    3: Workload("clip-like-d512", 3, 512, 2_000_000, 2_000_000, 10_000, 1024, 1024, 0.8, True, None, 100, 64),
-    4: Workload("serve-d200-10M", 4, 200, 10_000_000, 10_000_000, 10_000, 1024, 1024, 1.5, False, (0.5, 1.5), 100, 64),
-    5: Workload("serve-fp8-d512-8M", 5, 512, 8_000_000, 8_000_000, 10_000, 1024, 1024, 0.8, True, None, 100, 64),
+    2: Workload("t2i-like-d200", 2, 200, 1_000_000, 1_000_000, 10_000, 256, 256, 1.5, False, (0.5, 1.5), 100, 64,
+                latent=32),
+    3: Workload("clip-like-d512", 3, 512, 2_000_000, 2_000_000, 10_000, 1024, 1024, 0.8, True, None, 100, 64,
+                latent=32),
+    4: Workload("serve-d200-10M", 4, 200, 10_000_000, 10_000_000, 10_000, 1024, 1024, 1.5, False, (0.5, 1.5), 100,
+                64, latent=32),
+    5: Workload("serve-fp8-d512-8M", 5, 512, 8_000_000, 8_000_000, 10_000, 1024, 1024, 0.8, True, None, 100, 64,
+                latent=32),
 }
 
 
@@ -86,6 +104,20 @@ def _mixture(rng, n, centres, sigma, chunk=1 << 18):
     return out
 
 
+def _lowrank_mixture(rng, n, basis, centres, spread, noise, chunk=1 << 17):
+    d, r = basis.shape
+    out = np.empty((n, d), dtype=np.float32)
+    inv = np.float32(1.0 / np.sqrt(r))
+    for s in range(0, n, chunk):
+        e = min(n, s + chunk)
+        z = rng.integers(0, centres.shape[0], size=e - s)
+        h = centres[z] + np.float32(spread) * rng.standard_normal((e - s, r), dtype=np.float32)
+        x = h @ basis.T
+        x += np.float32(noise) * rng.standard_normal((e - s, d), dtype=np.float32)
+        out[s:e] = x * inv
+    return out
+
+
 def _normalize_inplace(a: np.ndarray, chunk=1 << 18):
     for s in range(0, a.shape[0], chunk):
         a[s:s + chunk] = _unit_rows(a[s:s + chunk])
@@ -110,8 +142,15 @@ class Generator:
             n_test=w.n_test if n_test is None else n_test,
         )
         cfg, d = self.w.cfg, self.w.d
-        self.base_centres = _centres(rng_for(cfg, S_BASE_CENTRES), self.w.k_base, d)
-        self.query_centres = _centres(rng_for(cfg, S_QUERY_CENTRES), self.w.k_query, d)
+        r = self.w.latent
+        if r:
+            self.basis = np.linalg.qr(rng_for(cfg, S_BASIS).standard_normal((d, r)))[0].astype(np.float32)
+            self.base_centres = rng_for(cfg, S_BASE_CENTRES).standard_normal((self.w.k_base, r), dtype=np.float32)
+            self.query_centres = rng_for(cfg, S_QUERY_CENTRES).standard_normal((self.w.k_query, r), dtype=np.float32)
+        else:
+            self.basis = None
+            self.base_centres = _centres(rng_for(cfg, S_BASE_CENTRES), self.w.k_base, d)
+            self.query_centres = _centres(rng_for(cfg, S_QUERY_CENTRES), self.w.k_query, d)
         u = rng_for(cfg, S_GAP).standard_normal(d)
         self.gap = (self.w.gap * u / np.linalg.norm(u)).astype(np.float32)
         if self.w.query_scale is not None:
@@ -120,15 +159,20 @@ class Generator:
         else:
             self.scale = np.ones(d, dtype=np.float32)
 
+    def _points(self, rng, n, centres):
+        if self.basis is not None:
+            return _lowrank_mixture(rng, n, self.basis, centres, self.w.latent_spread, self.w.ambient_noise)
+        return _mixture(rng, n, centres, self.w.sigma)
+
     def base(self) -> np.ndarray:
-        x = _mixture(rng_for(self.w.cfg, S_BASE_POINTS), self.w.n, self.base_centres, self.w.sigma)
+        x = self._points(rng_for(self.w.cfg, S_BASE_POINTS), self.w.n, self.base_centres)
         if self.w.normalize:
             _normalize_inplace(x)
         return x
 
     def _queries(self, stream, n, rng=None):
         rng = rng_for(self.w.cfg, stream) if rng is None else rng
-        q = _mixture(rng, n, self.query_centres, self.w.sigma)
+        q = self._points(rng, n, self.query_centres)
         q *= self.scale
         q += self.gap
         if self.w.normalize:
@@ -143,7 +187,7 @@ class Generator:
 
     def in_distribution(self, n: int) -> np.ndarray:
         """Fresh draws from the base law (ID queries), for sanity ratios."""
-        x = _mixture(rng_for(self.w.cfg, S_TEST + 100), n, self.base_centres, self.w.sigma)
+        x = self._points(rng_for(self.w.cfg, S_TEST + 100), n, self.base_centres)
         if self.w.normalize:
             _normalize_inplace(x)
         return x

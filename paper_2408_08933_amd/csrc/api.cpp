@@ -5,6 +5,7 @@
 #include <chrono>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <thread>
 
@@ -185,6 +186,7 @@ int knn_exact(const float *Qdev, int64_t nq, const float *Xdev, int64_t n, int32
         if (rc) return rc;
         rc = launch_knn_candidates(qd, m, d, Xdev, n, d, d, K, cid.as<uint32_t>(), csc.as<float>(), st);
         if (rc) return rc;
+        if (std::getenv("RG_LOG")) std::fprintf(stderr, "[rg] knn candidates: %lld rows, K=%d\n", (long long)m, K);
         std::vector<uint32_t> hid((size_t)m * K);
         std::vector<float> hsc((size_t)m * K);
         RG_HIP(hipMemcpyAsync(hid.data(), cid.p, sizeof(uint32_t) * hid.size(), hipMemcpyDeviceToHost, st));
@@ -301,8 +303,12 @@ int rg_build(const float *base, int64_t n, int32_t d, const float *train, int64_
     if (!rc) rc = copy_to_host(train, nt * d, th, st);
     if (rc) return rc;
     std::vector<uint32_t> knn;
+    if (std::getenv("RG_LOG")) std::fprintf(stderr, "[rg] build: n=%lld d=%d nt=%lld Nq=%d M=%d L=%d\n", (long long)n, d, (long long)nt, Nq, M, L);
     rc = knn_exact(train, nt, base, n, d, Nq, o.knn_slack, th.data(), xh.data(), threads, &knn, nullptr, st);
     if (rc) return rc;
+    if (std::getenv("RG_LOG"))
+        std::fprintf(stderr, "[rg] kNN preprocessing done in %.2f s\n",
+                     std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count());
     th.clear();
     th.shrink_to_fit();
     const auto t1 = std::chrono::steady_clock::now();
@@ -516,6 +522,8 @@ int rg_search(const rg_index *ix, const float *queries, int64_t nq, int32_t k, i
         set_error("rg_search: index has no device data (built by rg_build_from_knn)");
         return RG_EINVAL;
     }
+    if (nq == 0) return RG_OK;
+    hipStream_t st = (hipStream_t)stream;
     SearchArgs a{};
     a.base = ix->d_base;
     a.base_bf16 = ix->d_bf16;
@@ -534,10 +542,33 @@ int rg_search(const rg_index *ix, const float *queries, int64_t nq, int32_t k, i
     a.ell = ix->ell;
     a.k = k;
     a.Leff = std::max(k, L);
-    a.hash_bits = default_hash_bits(a.Leff);
+    a.hash_bits = 0;
     a.entry = ix->entry;
     a.storage = ix->storage;
-    return launch_search(a, (hipStream_t)stream);
+    // persistent grid: as many resident workgroups as the chip holds, each
+    // with its own visited bitmap (bounded to 8 GiB in total)
+    int per_cu = 0, cus = 0;
+    int rc = search_occupancy(a, &per_cu);
+    if (rc) return rc;
+    RG_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, ix->device));
+    a.bm_words = ((ix->n + 31) / 32 + 63) / 64 * 64;
+    int64_t grid = (int64_t)std::max(1, per_cu) * std::max(1, cus);
+    grid = std::min<int64_t>(grid, nq);
+    grid = std::min<int64_t>(grid, std::max<int64_t>(1, (8ll << 30) / (a.bm_words * 4)));
+    a.grid = (int32_t)grid;
+    void *ws = nullptr;
+    const size_t bytes = (size_t)grid * a.bm_words * 4 + 256;
+    if (hipMallocAsync(&ws, bytes, st) != hipSuccess) {
+        set_error("rg_search: out of device memory for visited bitmaps");
+        return RG_ENOMEM;
+    }
+    a.work = static_cast<uint32_t *>(ws);
+    a.bitmap = reinterpret_cast<uint32_t *>(static_cast<char *>(ws) + 256);
+    rc = hipMemsetAsync(a.work, 0, 4, st) == hipSuccess ? RG_OK : RG_EDEVICE;
+    if (!rc) rc = launch_search_persistent(a, st);
+    if (hipFreeAsync(ws, st) != hipSuccess && !rc) rc = RG_EDEVICE;
+    if (rc == RG_EDEVICE) set_error("rg_search: device call failed");
+    return rc;
 }
 
 // Same as rg_search with an explicit visited-table size (2^hash_bits

@@ -176,15 +176,65 @@ __device__ __forceinline__ void score_batch(const SearchArgs &a, const float4 (&
 
 __device__ __forceinline__ uint32_t hslot(uint32_t u, int hb) { return (u * 2654435761u) >> (32 - hb); }
 
+// Visited set kept in LDS: open addressing, cleared when it passes half load
+// (clearing only costs re-scoring; see the file comment).
+struct VisitLds {
+    uint32_t *htab;
+    int hb, H, hcount;
+    __device__ __forceinline__ void clear() {
+        for (int i = lane_id(); i < H; i += 64) htab[i] = kEmpty;
+        hcount = 0;
+    }
+    __device__ __forceinline__ void mark_entry(uint32_t u) {  // lane 0, table just cleared
+        htab[hslot(u, hb)] = u;
+    }
+    __device__ __forceinline__ void begin_hop(int ell) {
+        if (hcount + ell > (H >> 1)) {
+            clear();
+            __syncthreads();
+        }
+    }
+    __device__ __forceinline__ bool insert(uint32_t u) {
+        const uint32_t hmask = (uint32_t)H - 1u;
+        uint32_t h = hslot(u, hb);
+        for (int probe = 0; probe < H; ++probe) {
+            const uint32_t old = atomicCAS(&htab[h], kEmpty, u);
+            if (old == kEmpty) return true;
+            if (old == u) return false;
+            h = (h + 1u) & hmask;
+        }
+        return false;
+    }
+    __device__ __forceinline__ void added(int k) { hcount += k; }
+};
+
+// Exact visited set: one bit per base node in device memory, owned by the
+// workgroup for the query it is running; test-and-set with vector atomics.
+struct VisitBitmap {
+    uint32_t *bm;
+    int64_t words;  // multiple of 4
+    __device__ __forceinline__ void clear() {
+        uint4 *b4 = reinterpret_cast<uint4 *>(bm);
+        const uint4 z = make_uint4(0u, 0u, 0u, 0u);
+        for (int64_t i = lane_id(); i < (words >> 2); i += 64) b4[i] = z;
+        __threadfence();
+    }
+    __device__ __forceinline__ void mark_entry(uint32_t u) { atomicOr(&bm[u >> 5], 1u << (u & 31u)); }
+    __device__ __forceinline__ void begin_hop(int) {}
+    __device__ __forceinline__ bool insert(uint32_t u) {
+        const uint32_t bit = 1u << (u & 31u);
+        return (atomicOr(&bm[u >> 5], bit) & bit) == 0u;
+    }
+    __device__ __forceinline__ void added(int) {}
+};
+
 // Expansions until done or `budget` expansions were made.
-template <int G, int NCH, int ST>
-__device__ __forceinline__ void run_search(const SearchArgs &a, const float4 (&qv)[NCH], const Lds &s, int &qn, int &ptr,
-                           int &hcount, uint32_t &hops, uint32_t &evals, int budget, bool &done) {
+template <int G, int NCH, int ST, class VIS>
+__device__ __forceinline__ void run_search(const SearchArgs &a, const float4 (&qv)[NCH], const Lds &s, VIS &vis,
+                                           int &qn, int &ptr, uint32_t &hops, uint32_t &evals, int budget,
+                                           bool &done) {
     const int lane = lane_id();
     const int Leff = a.Leff, ell = a.ell, nch = (a.d + 3) >> 2;
-    const int hb = a.hash_bits;
-    const int H = 1 << hb;
-    const uint32_t hmask = (uint32_t)H - 1u;
     done = false;
     for (; budget > 0; --budget) {
         int sel = -1;
@@ -206,33 +256,17 @@ __device__ __forceinline__ void run_search(const SearchArgs &a, const float4 (&q
         __syncthreads();
         if (lane == 0) s.qi[sel] = v | kExpanded;
         ++hops;
-        if (hcount + ell > (H >> 1)) {
-            for (int i = lane; i < H; i += 64) s.htab[i] = kEmpty;
-            hcount = 0;
-            __syncthreads();
-        }
+        vis.begin_hop(ell);
         int nnew = 0;
         for (int b = 0; b < ell; b += 64) {
             const int e = b + lane;
             const uint32_t u = e < ell ? a.adj[(size_t)v * ell + e] : kNone;
-            bool fresh = false;
-            if (u != kNone) {
-                uint32_t h = hslot(u, hb);
-                for (int probe = 0; probe < H; ++probe) {
-                    const uint32_t old = atomicCAS(&s.htab[h], kEmpty, u);
-                    if (old == kEmpty) {
-                        fresh = true;
-                        break;
-                    }
-                    if (old == u) break;
-                    h = (h + 1u) & hmask;
-                }
-            }
+            const bool fresh = u != kNone && vis.insert(u);
             const uint64_t m = ballot64(fresh);
             if (fresh) s.ci[nnew + lanes_below(m)] = u;
             nnew += (int)__popcll(m);
         }
-        hcount += nnew;
+        vis.added(nnew);
         evals += (uint32_t)nnew;
         __syncthreads();
         if (nnew == 0) continue;
@@ -246,12 +280,12 @@ __device__ __forceinline__ void run_search(const SearchArgs &a, const float4 (&q
     }
 }
 
-template <int G, int NCH, int ST>
-__device__ __forceinline__ void init_state(const SearchArgs &a, const float4 (&qv)[NCH], const Lds &s, int &qn, int &ptr,
-                           int &hcount, uint32_t &hops, uint32_t &evals) {
+// Queue = [entry]; the visited set is cleared and holds the entry.
+template <int G, int NCH, int ST, class VIS>
+__device__ __forceinline__ void init_state(const SearchArgs &a, const float4 (&qv)[NCH], const Lds &s, VIS &vis,
+                                           int &qn, int &ptr, uint32_t &hops, uint32_t &evals) {
     const int lane = lane_id();
-    const int H = 1 << a.hash_bits;
-    for (int i = lane; i < H; i += 64) s.htab[i] = kEmpty;
+    vis.clear();
     const uint32_t u = lane < G ? a.entry : kNone;
     float acc = row_partial<G, NCH, ST>(a, u, qv, (a.d + 3) >> 2);
     acc = group_sum<G>(acc);
@@ -259,11 +293,11 @@ __device__ __forceinline__ void init_state(const SearchArgs &a, const float4 (&q
     if (lane == 0) {
         s.qd[0] = finish_delta<G, ST>(a, a.entry, acc);
         s.qi[0] = a.entry;
-        s.htab[hslot(a.entry, a.hash_bits)] = a.entry;
+        vis.mark_entry(a.entry);
     }
+    vis.added(1);
     qn = 1;
     ptr = 0;
-    hcount = 1;
     hops = 0;
     evals = 1;
     __syncthreads();
@@ -298,18 +332,8 @@ __device__ __forceinline__ void rerank_queue(const SearchArgs &a, const float4 (
 }
 
 template <int G, int NCH, int ST>
-__global__ __launch_bounds__(64) void k_search(SearchArgs a) {
-    extern __shared__ __align__(16) unsigned char smem[];
-    const int64_t q = blockIdx.x;
-    const Lds s = carve(smem, a.Leff);
-    float4 qv[NCH];
-    load_query<G, NCH>(a.queries + q * a.d, a.d, qv);
-    int qn, ptr, hcount;
-    uint32_t hops, evals;
-    bool done;
-    init_state<G, NCH, ST>(a, qv, s, qn, ptr, hcount, hops, evals);
-    run_search<G, NCH, ST>(a, qv, s, qn, ptr, hcount, hops, evals, INT_MAX, done);
-    if constexpr (ST != RG_STORE_FP32) rerank_queue<G, NCH>(a, qv, s, qn);
+__device__ __forceinline__ void write_result(const SearchArgs &a, const Lds &s, int64_t q, int qn, uint32_t hops,
+                                             uint32_t evals) {
     const int lane = lane_id();
     for (int i = lane; i < a.k; i += 64) {
         a.out_ids[q * a.k + i] = i < qn ? (s.qi[i] & ~kExpanded) : kNone;
@@ -318,6 +342,52 @@ __global__ __launch_bounds__(64) void k_search(SearchArgs a) {
     if (lane == 0) {
         if (a.out_hops) a.out_hops[q] = hops;
         if (a.out_evals) a.out_evals[q] = evals;
+    }
+}
+
+// One query per workgroup, visited set in LDS.
+template <int G, int NCH, int ST>
+__global__ __launch_bounds__(64) void k_search(SearchArgs a) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int64_t q = blockIdx.x;
+    const Lds s = carve(smem, a.Leff);
+    VisitLds vis{s.htab, a.hash_bits, 1 << a.hash_bits, 0};
+    float4 qv[NCH];
+    load_query<G, NCH>(a.queries + q * a.d, a.d, qv);
+    int qn, ptr;
+    uint32_t hops, evals;
+    bool done;
+    init_state<G, NCH, ST>(a, qv, s, vis, qn, ptr, hops, evals);
+    run_search<G, NCH, ST>(a, qv, s, vis, qn, ptr, hops, evals, INT_MAX, done);
+    if constexpr (ST != RG_STORE_FP32) rerank_queue<G, NCH>(a, qv, s, qn);
+    write_result<G, NCH, ST>(a, s, q, qn, hops, evals);
+}
+
+// Persistent grid: each workgroup stays resident, takes queries from a
+// device counter until none are left, and keeps an exact visited bitmap
+// (one bit per base node) in device memory, so LDS holds only the queue and
+// the candidate batch and many more queries are in flight per CU.
+template <int G, int NCH, int ST>
+__global__ __launch_bounds__(64) void k_search_persistent(SearchArgs a) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    const Lds s = carve(smem, a.Leff);
+    VisitBitmap vis{a.bitmap + (size_t)blockIdx.x * a.bm_words, a.bm_words};
+    const int lane = lane_id();
+    for (;;) {
+        int q = 0;
+        if (lane == 0) q = (int)atomicAdd(a.work, 1u);
+        q = __shfl(q, 0);
+        if ((int64_t)q >= a.nq) break;
+        float4 qv[NCH];
+        load_query<G, NCH>(a.queries + (int64_t)q * a.d, a.d, qv);
+        int qn, ptr;
+        uint32_t hops, evals;
+        bool done;
+        init_state<G, NCH, ST>(a, qv, s, vis, qn, ptr, hops, evals);
+        run_search<G, NCH, ST>(a, qv, s, vis, qn, ptr, hops, evals, INT_MAX, done);
+        if constexpr (ST != RG_STORE_FP32) rerank_queue<G, NCH>(a, qv, s, qn);
+        write_result<G, NCH, ST>(a, s, q, qn, hops, evals);
+        __syncthreads();
     }
 }
 
@@ -339,14 +409,15 @@ __global__ __launch_bounds__(64) void k_serve_step(SlotArgs sa) {
     float *gqd = sa.slot_qd + (size_t)slot * kMaxL;
     uint32_t *gqi = sa.slot_qi + (size_t)slot * kMaxL;
     uint32_t *gh = sa.slot_hash + ((size_t)slot << a.hash_bits);
-    int qn, ptr, hcount;
+    int qn, ptr;
     uint32_t hops, evals;
+    VisitLds vis{s.htab, a.hash_bits, H, 0};
     if (st[0] == 0) {
-        init_state<G, NCH, ST>(a, qv, s, qn, ptr, hcount, hops, evals);
+        init_state<G, NCH, ST>(a, qv, s, vis, qn, ptr, hops, evals);
     } else {
         qn = st[0];
         ptr = st[1];
-        hcount = st[2];
+        vis.hcount = st[2];
         hops = (uint32_t)st[3];
         evals = (uint32_t)st[4];
         for (int i = lane; i < qn; i += 64) {
@@ -357,7 +428,7 @@ __global__ __launch_bounds__(64) void k_serve_step(SlotArgs sa) {
         __syncthreads();
     }
     bool done;
-    run_search<G, NCH, ST>(a, qv, s, qn, ptr, hcount, hops, evals, sa.hops_budget, done);
+    run_search<G, NCH, ST>(a, qv, s, vis, qn, ptr, hops, evals, sa.hops_budget, done);
     if (done) {
         if constexpr (ST != RG_STORE_FP32) rerank_queue<G, NCH>(a, qv, s, qn);
         for (int i = lane; i < a.k; i += 64) {
@@ -374,7 +445,7 @@ __global__ __launch_bounds__(64) void k_serve_step(SlotArgs sa) {
     if (lane == 0) {
         st[0] = qn;
         st[1] = ptr;
-        st[2] = hcount;
+        st[2] = vis.hcount;
         st[3] = (int32_t)hops;
         st[4] = (int32_t)evals;
         if (done) sa.slot_done[slot] = 1;
@@ -386,6 +457,21 @@ int launch_one(const SearchArgs &a, hipStream_t stream) {
     const size_t lds = search_lds_bytes(a.Leff, a.ell, a.hash_bits);
     hipLaunchKernelGGL((k_search<G, NCH, ST>), dim3((unsigned)a.nq), dim3(64), lds, stream, a);
     RG_HIP(hipGetLastError());
+    return RG_OK;
+}
+
+template <int G, int NCH, int ST>
+int launch_persistent(const SearchArgs &a, hipStream_t stream) {
+    const size_t lds = search_lds_bytes(a.Leff, a.ell, 0);
+    hipLaunchKernelGGL((k_search_persistent<G, NCH, ST>), dim3((unsigned)a.grid), dim3(64), lds, stream, a);
+    RG_HIP(hipGetLastError());
+    return RG_OK;
+}
+
+template <int G, int NCH, int ST>
+int occupancy_of(int Leff, int *blocks_per_cu) {
+    const size_t lds = search_lds_bytes(Leff, 0, 0);
+    RG_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k_search_persistent<G, NCH, ST>, 64, lds));
     return RG_OK;
 }
 
@@ -416,6 +502,14 @@ struct SearchLaunch {
     static int run(const SearchArgs &a, hipStream_t s) { return launch_one<G, NCH, ST>(a, s); }
 };
 template <int G, int NCH, int ST>
+struct PersistentLaunch {
+    static int run(const SearchArgs &a, hipStream_t s) { return launch_persistent<G, NCH, ST>(a, s); }
+};
+template <int G, int NCH, int ST>
+struct OccLaunch {
+    static int run(const SearchArgs &a, hipStream_t) { return occupancy_of<G, NCH, ST>(a.Leff, a.occ_out); }
+};
+template <int G, int NCH, int ST>
 struct StepLaunch {
     static int run(const SlotArgs &a, hipStream_t s) { return launch_step<G, NCH, ST>(a, s); }
 };
@@ -424,7 +518,7 @@ struct StepLaunch {
 
 size_t search_lds_bytes(int Leff, int ell, int hash_bits) {
     (void)ell;
-    return (size_t)Leff * 8 + (size_t)kCand * 20 + ((size_t)4 << hash_bits);
+    return (size_t)Leff * 8 + (size_t)kCand * 20 + (hash_bits > 0 ? ((size_t)4 << hash_bits) : 0);
 }
 
 int default_hash_bits(int Leff) {
@@ -440,6 +534,27 @@ int launch_search(const SearchArgs &a, hipStream_t stream) {
     case RG_STORE_FP32: return dispatch_dim<SearchLaunch, RG_STORE_FP32>(a.d, a, stream);
     case RG_STORE_BF16: return dispatch_dim<SearchLaunch, RG_STORE_BF16>(a.d, a, stream);
     case RG_STORE_FP8E4M3: return dispatch_dim<SearchLaunch, RG_STORE_FP8E4M3>(a.d, a, stream);
+    default: set_error("search: unknown storage"); return RG_EINVAL;
+    }
+}
+
+int launch_search_persistent(const SearchArgs &a, hipStream_t stream) {
+    if (a.nq == 0) return RG_OK;
+    switch (a.storage) {
+    case RG_STORE_FP32: return dispatch_dim<PersistentLaunch, RG_STORE_FP32>(a.d, a, stream);
+    case RG_STORE_BF16: return dispatch_dim<PersistentLaunch, RG_STORE_BF16>(a.d, a, stream);
+    case RG_STORE_FP8E4M3: return dispatch_dim<PersistentLaunch, RG_STORE_FP8E4M3>(a.d, a, stream);
+    default: set_error("search: unknown storage"); return RG_EINVAL;
+    }
+}
+
+int search_occupancy(const SearchArgs &a, int *blocks_per_cu) {
+    SearchArgs b = a;
+    b.occ_out = blocks_per_cu;
+    switch (a.storage) {
+    case RG_STORE_FP32: return dispatch_dim<OccLaunch, RG_STORE_FP32>(a.d, b, nullptr);
+    case RG_STORE_BF16: return dispatch_dim<OccLaunch, RG_STORE_BF16>(a.d, b, nullptr);
+    case RG_STORE_FP8E4M3: return dispatch_dim<OccLaunch, RG_STORE_FP8E4M3>(a.d, b, nullptr);
     default: set_error("search: unknown storage"); return RG_EINVAL;
     }
 }

@@ -23,6 +23,8 @@
 #include <atomic>
 #include <chrono>
 #include <cmath>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <thread>
 
@@ -33,6 +35,8 @@ namespace {
 
 using Clock = std::chrono::steady_clock;
 double secs(Clock::time_point a, Clock::time_point b) { return std::chrono::duration<double>(b - a).count(); }
+
+constexpr int kHead = 16;  // leading enhancement candidates kept per node for the repair
 
 template <class F>
 void parallel_for(int64_t n, int threads, int64_t grain, F &&f) {
@@ -276,7 +280,8 @@ void lists_to_csr(const Lists &L, int64_t n, std::vector<int64_t> &off, std::vec
 // to the host searcher), then each node's own selection on host threads.
 int enhance_on_device(const float *X, int64_t n, int32_t d, const Lists &PJ, const std::vector<int64_t> &pjoff,
                       const std::vector<uint32_t> &pjidx, uint32_t entry, int32_t L, int32_t m_ce, int threads,
-                      const GpuCtx &gpu, Lists &E, double *t_search) {
+                      const GpuCtx &gpu, Lists &E, std::vector<uint32_t> &head, std::vector<int32_t> &head_n,
+                      double *t_search) {
     (void)pjidx;
     int32_t maxdeg = 1;
     for (int64_t x = 0; x < n; ++x) maxdeg = std::max<int32_t>(maxdeg, PJ.deg[x]);
@@ -336,8 +341,12 @@ int enhance_on_device(const float *X, int64_t n, int32_t d, const Lists &PJ, con
                 const uint32_t u = hid[b * L + j];
                 if ((int64_t)u != x) c.push_back(Cand{hd[b * L + j], u});
             }
+            head_n[x] = (int32_t)c.size();
+            for (int j = 0; j < kHead && j < (int)c.size(); ++j) head[x * kHead + j] = c[j].id;
             E.deg[x] = acquire_sorted(X, d, c.data(), (int)c.size(), m_ce, false, E.row(x), kept[tid]);
         });
+        if (std::getenv("RG_LOG"))
+            std::fprintf(stderr, "[rg] enhancement searches %lld / %lld nodes\n", (long long)(x0 + cnt), (long long)n);
     }
     release();
     *t_search = ts;
@@ -431,6 +440,8 @@ int host_construct(const float *X, int64_t n, int32_t d, const uint32_t *knn, in
     std::vector<uint32_t> pjidx;
     lists_to_csr(PJ, n, pjoff, pjidx);
     const auto t1 = Clock::now();
+    const bool log = std::getenv("RG_LOG") != nullptr;
+    if (log) std::fprintf(stderr, "[rg] projection done in %.2f s\n", secs(t0, t1));
 
     // --- entry: nearest to the mean among nodes with a projected out-edge --
     uint32_t entry = 0;
@@ -470,8 +481,10 @@ int host_construct(const float *X, int64_t n, int32_t d, const uint32_t *knn, in
     // --- enhancement: searches on G_pj and each node's own selection E(x) --
     Lists E;
     E.init(n, capl);
+    std::vector<uint32_t> head((size_t)n * kHead, kNone);
+    std::vector<int32_t> head_n((size_t)n, 0);
     if (gpu) {
-        const int rc = enhance_on_device(X, n, d, PJ, pjoff, pjidx, entry, L, m_ce, threads, *gpu, E,
+        const int rc = enhance_on_device(X, n, d, PJ, pjoff, pjidx, entry, L, m_ce, threads, *gpu, E, head, head_n,
                                          &out->t_enhance_search);
         if (rc) return rc;
     } else {
@@ -486,6 +499,8 @@ int host_construct(const float *X, int64_t n, int32_t d, const uint32_t *knn, in
             c.clear();
             for (int j = 0; j < qn; ++j)
                 if ((int64_t)s.qi[j] != x) c.push_back(Cand{s.qd[j], s.qi[j]});
+            head_n[x] = (int32_t)c.size();
+            for (int j = 0; j < kHead && j < (int)c.size(); ++j) head[x * kHead + j] = c[j].id;
             E.deg[x] = acquire_sorted(X, d, c.data(), (int)c.size(), m_ce, false, E.row(x), kept[tid]);
         });
     }
@@ -503,6 +518,7 @@ int host_construct(const float *X, int64_t n, int32_t d, const uint32_t *knn, in
         });
     }
     const auto t2 = Clock::now();
+    if (log) std::fprintf(stderr, "[rg] enhancement done in %.2f s\n", secs(t1, t2));
 
     // --- merge: final(x) = G_pj(x) u G'(x) -------------------------------
     std::vector<std::vector<uint32_t>> fin((size_t)n);
@@ -523,12 +539,12 @@ int host_construct(const float *X, int64_t n, int32_t d, const uint32_t *knn, in
         std::vector<uint8_t> seen((size_t)n, 0);
         std::vector<uint32_t> order;
         order.reserve((size_t)n);
-        size_t head = 0;
+        size_t qhead = 0;
         seen[entry] = 1;
         order.push_back(entry);
         auto bfs = [&]() {
-            while (head < order.size()) {
-                const uint32_t v = order[head++];
+            while (qhead < order.size()) {
+                const uint32_t v = order[qhead++];
                 for (uint32_t w : fin[v])
                     if (!seen[w]) {
                         seen[w] = 1;
@@ -540,12 +556,20 @@ int host_construct(const float *X, int64_t n, int32_t d, const uint32_t *knn, in
         Searcher s;
         for (int64_t u = 0; u < n; ++u) {
             if (seen[u]) continue;
-            if (s.stamp.empty()) s.init(n, L);
-            const int qn = s.run(X, d, pjoff.data(), pjidx.data(), entry, X + u * d, L);
+            // first node of u's enhancement candidates (queue order) with a free
+            // slot; every one of them was reached from the entry through G_pj
             int64_t r = -1;
-            for (int j = 0; j < qn && r < 0; ++j) {
-                const uint32_t c = s.qi[j];
-                if ((int64_t)c != u && seen[c] && (int)fin[c].size() < M) r = c;
+            for (int j = 0; j < kHead && j < head_n[u] && r < 0; ++j) {
+                const uint32_t c = head[u * kHead + j];
+                if (seen[c] && (int)fin[c].size() < M) r = c;
+            }
+            if (r < 0 && head_n[u] > kHead) {  // rare: the stored head is full, search again
+                if (s.stamp.empty()) s.init(n, L);
+                const int qn = s.run(X, d, pjoff.data(), pjidx.data(), entry, X + u * d, L);
+                for (int j = 0; j < qn && r < 0; ++j) {
+                    const uint32_t c = s.qi[j];
+                    if ((int64_t)c != u && seen[c] && (int)fin[c].size() < M) r = c;
+                }
             }
             for (size_t j = 0; j < order.size() && r < 0; ++j)
                 if ((int)fin[order[j]].size() < M) r = order[j];
@@ -572,6 +596,7 @@ int host_construct(const float *X, int64_t n, int32_t d, const uint32_t *knn, in
     out->entry = entry;
     out->repairs = repairs;
     const auto t3 = Clock::now();
+    if (log) std::fprintf(stderr, "[rg] repair (%lld edges) and CSR done in %.2f s\n", (long long)repairs, secs(t2, t3));
     out->t_project = secs(t0, t1);
     out->t_enhance = secs(t1, t2);
     out->t_total = secs(t0, t3);

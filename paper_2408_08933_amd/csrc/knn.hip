@@ -22,6 +22,8 @@
 #include "wave_ops.h"
 
 #include <algorithm>
+#include <cstdio>
+#include <cstdlib>
 
 namespace rg {
 namespace {
@@ -300,6 +302,7 @@ int launch_knn_candidates(const float *Q, int64_t nq, int32_t ldq, const float *
     a.splits = splits;
     a.vec_q = (ldq % 4 == 0) && ((uintptr_t)Q % 16 == 0);
     a.vec_x = (ldx % 4 == 0) && ((uintptr_t)X % 16 == 0);
+    const bool log = std::getenv("RG_LOG") != nullptr && qtiles > tiles_per_launch;
     for (int64_t t0 = 0; t0 < qtiles; t0 += tiles_per_launch) {
         a.q_tile0 = t0;
         const int64_t nt = std::min(tiles_per_launch, qtiles - t0);
@@ -308,6 +311,10 @@ int launch_knn_candidates(const float *Q, int64_t nq, int32_t ldq, const float *
             cleanup();
             set_error("knn: kernel launch failed");
             return RG_EDEVICE;
+        }
+        if (log) {  // progress for long sweeps (waits for this launch)
+            (void)hipStreamSynchronize(stream);
+            std::fprintf(stderr, "[rg] knn tiles %lld / %lld\n", (long long)(t0 + nt), (long long)qtiles);
         }
     }
     if (splits > 1) {

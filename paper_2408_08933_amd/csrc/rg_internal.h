@@ -46,10 +46,18 @@ struct SearchArgs {
     int32_t hash_bits;
     uint32_t entry;
     int32_t storage;            // RG_STORE_*
+    // persistent variant: visited bitmaps (grid x bm_words) and the work counter
+    uint32_t *bitmap;
+    int64_t bm_words;
+    uint32_t *work;
+    int32_t grid;
+    int *occ_out;
 };
 
 // beam.hip
 int launch_search(const SearchArgs &a, hipStream_t stream);
+int launch_search_persistent(const SearchArgs &a, hipStream_t stream);
+int search_occupancy(const SearchArgs &a, int *blocks_per_cu);
 size_t search_lds_bytes(int Leff, int ell, int hash_bits);
 int default_hash_bits(int Leff);
 
