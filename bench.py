@@ -119,21 +119,46 @@ def serve_latency(rg, ix, Qh, n_req, rate, seed=0):
             "steps": st["steps"], "k_mix": [1, 10, 100], "L_mix": [32, 128, 512]}
 
 
+def search_sources_sha() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for f in ("beam.hip", "queue_ops.h", "wave_ops.h", "rg_internal.h"):
+        with open(os.path.join(ROOT, "paper_2408_08933_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(L, k, nq, ms_launch):
+    """HBM bytes per launch from the committed counter passes (FETCH_SIZE +
+    WRITE_SIZE, calibrated with a plain copy), as GB/s over this run's launch
+    time; None when the kernel sources or the operating point changed."""
+    path = os.path.join(ROOT, "profiles", "k_search_persistent_fp32_t2i-like-d200.traffic.txt")
+    if not os.path.exists(path):
+        return None, None
+    kv = dict(line.strip().split("=", 1) for line in open(path) if "=" in line)
+    if kv.get("sources_sha") != search_sources_sha() or int(kv["L"]) != L or int(kv["k"]) != k \
+            or int(kv["nq"]) != nq:
+        return None, None
+    b = float(kv["fetch_bytes_per_launch"]) + float(kv["write_bytes_per_launch"])
+    return b / (ms_launch * 1e-3) / 1e9, b
+
+
 def cpu_baseline(X, off, idx, entry, Qh, k, L, seconds):
     import oracle
     threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
     n_done, t = 0, 0.0
     batch = 64
-    while t < seconds and n_done < len(Qh):
-        q = Qh[n_done:n_done + batch]
+    while t < seconds:
+        s0 = n_done % len(Qh)
+        q = Qh[s0:s0 + batch]
         t0 = time.perf_counter()
         oracle.search(X, off, idx, entry, q, k, L)
         t += time.perf_counter() - t0
         n_done += len(q)
         batch = min(batch * 2, 2048)
     return {"value": n_done / t, "unit": "queries/s", "cores": threads, "kind": "oracle",
-            "sample": f"{n_done} of the {len(Qh)} test queries, same graph, L={L}, k={k}, FP64 oracle search "
-                      f"with OpenMP over queries ({threads} threads), {t:.1f} s"}
+            "sample": f"{n_done} searches over the {len(Qh)} test queries (cycled), same graph, L={L}, k={k}; "
+                      f"FP64 oracle search, OpenMP over queries ({threads} threads), {t:.1f} s"}
 
 
 def main():
@@ -146,6 +171,7 @@ def main():
     ap.add_argument("--no-precision", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--n", type=int, default=None, help="override base/training size (not the headline)")
+    ap.add_argument("--copy-probe", action="store_true", help="run a 1 GiB plain copy kernel (traffic calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: this build runs on exactly one GPU; --gpus N > 1 is not supported", file=sys.stderr)
@@ -183,6 +209,16 @@ def main():
     gt_ids, _ = rg.rg_knn(Q, X, 10)
     gt = rg.as_u32(gt_ids)
     log(f"ground truth (exact kNN, k=10) in {time.time() - t:.1f} s")
+
+    if args.copy_probe:
+        src = torch.empty(1 << 28, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        src.fill_(1.0)
+        torch.cuda.synchronize()
+        rg.rg_device_copy(dst, src)
+        torch.cuda.synchronize()
+        log("copy probe: 1 GiB read + 1 GiB written by k_copy_probe")
+        del src, dst
 
     k = 10
     log("FP32 sweep")
@@ -229,6 +265,7 @@ def main():
         cpu = cpu_baseline(Xh, off, idx, entry, Qh, k, L, args.cpu_seconds)
         log(f"cpu: {cpu}")
 
+    traffic, traffic_bytes = measured_traffic(L, k, int(nq), ms_launch) if n == w.n else (None, None)
     out = {
         "metric": METRIC,
         "value": qps,
@@ -246,8 +283,9 @@ def main():
                    "M": w.M, "L_build": 500, "k": k, "L": L, "recall_at_10": rec,
                    "recall_curve": [[a, b] for a, b in curve], "metric_space": "inner product"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                     "kernel": "k_search<8,7,0> (FP32 beam search, d=200)",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                     "traffic_bytes_per_launch": traffic_bytes,
+                     "kernel": "k_search_persistent<8,7,0> (FP32 beam search, d=200)",
                      "bytes_per_launch": bytes_total, "mean_visits": Vm, "mean_hops": Hm,
                      "avg_degree": avg_deg, "ms_per_launch": ms_launch},
         "cpu_baseline": cpu,

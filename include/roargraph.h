@@ -213,6 +213,13 @@ int rg_index_storage_ptrs(const rg_index *idx, const void **bf16, const void **f
 int rg_save(const rg_index *idx, const char *path);
 int rg_load(const char *path, void *stream, rg_index **out);
 
+/* rg_device_copy -- a plain streaming device-to-device copy kernel (16-byte
+ * vector loads and stores).  Not part of the method: it gives a copy of
+ * known size whose hardware counters calibrate the traffic measured for
+ * the search kernels.  dst, src device, 16-byte aligned; bytes % 16 == 0.
+ * Asynchronous.  Errors: RG_EINVAL, RG_EDEVICE. */
+int rg_device_copy(void *dst, const void *src, int64_t bytes, void *stream);
+
 void rg_free(rg_index *idx);
 const char *rg_last_error(void);
 

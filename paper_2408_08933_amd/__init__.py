@@ -65,6 +65,7 @@ _SIGS = {
     "rg_save": (i32, [P, ctypes.c_char_p]),
     "rg_load": (i32, [ctypes.c_char_p, P, PP]),
     "rg_free": (None, [P]),
+    "rg_device_copy": (i32, [P, P, i64, P]),
     "rg_last_error": (ctypes.c_char_p, []),
     "rg_server_create": (i32, [P, ctypes.POINTER(rg_server_limits), PP]),
     "rg_server_submit": (i32, [P, P, i32, i32, ctypes.c_uint64]),
@@ -251,6 +252,12 @@ def rg_knn_candidates(queries, base, K, stream=None):
     _check(lib().rg_knn_candidates(_ptr(queries), nq, _ptr(base), base.shape[0], base.shape[1], int(K), _ptr(ids),
                                    _ptr(sc), _stream(stream)))
     return ids, sc
+
+
+def rg_device_copy(dst, src, stream=None):
+    """Plain copy kernel of dst.numel()*itemsize bytes (traffic calibration)."""
+    nbytes = src.numel() * src.element_size()
+    _check(lib().rg_device_copy(_ptr(dst), _ptr(src), nbytes, _stream(stream)))
 
 
 def rg_save(index: Index, path: str):

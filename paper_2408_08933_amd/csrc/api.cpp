@@ -718,6 +718,14 @@ int rg_load(const char *path, void *stream, rg_index **out) {
     return RG_OK;
 }
 
+int rg_device_copy(void *dst, const void *src, int64_t bytes, void *stream) {
+    if (!dst || !src || bytes < 0) {
+        set_error("rg_device_copy: invalid argument");
+        return RG_EINVAL;
+    }
+    return launch_copy_probe(dst, src, bytes, (hipStream_t)stream);
+}
+
 void rg_free(rg_index *ix) {
     if (!ix) return;
     free_index_device(ix);

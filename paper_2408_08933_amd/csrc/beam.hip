@@ -58,13 +58,8 @@ __device__ __forceinline__ Lds carve(unsigned char *p, int Leff) {
     return s;
 }
 
-__device__ __forceinline__ float e4m3_to_f32(uint32_t b) {
-    const uint32_t sgn = (b & 0x80u) << 24;
-    const uint32_t e = (b >> 3) & 15u, m = b & 7u;
-    const float sub = (float)m * 0.001953125f;  // m * 2^-9
-    const float nrm = __uint_as_float(sgn | ((e + 120u) << 23) | (m << 20));
-    return e == 0 ? (sgn ? -sub : sub) : nrm;
-}
+typedef float f32x2 __attribute__((ext_vector_type(2)));
+
 
 template <int G, int NCH>
 __device__ __forceinline__ void load_query(const float *q, int d, float4 (&qv)[NCH]) {
@@ -126,10 +121,13 @@ __device__ __forceinline__ float row_partial(const SearchArgs &a, uint32_t u, co
         }
 #pragma unroll
         for (int t = 0; t < NCH; ++t) {
-            acc = fmaf(qv[t].x, e4m3_to_f32(x[t] & 0xFFu), acc);
-            acc = fmaf(qv[t].y, e4m3_to_f32((x[t] >> 8) & 0xFFu), acc);
-            acc = fmaf(qv[t].z, e4m3_to_f32((x[t] >> 16) & 0xFFu), acc);
-            acc = fmaf(qv[t].w, e4m3_to_f32(x[t] >> 24), acc);
+            // gfx950 converts OCP E4M3 pairs exactly (every code is a float)
+            const f32x2 lo = __builtin_amdgcn_cvt_pk_f32_fp8((int)x[t], false);
+            const f32x2 hi = __builtin_amdgcn_cvt_pk_f32_fp8((int)x[t], true);
+            acc = fmaf(qv[t].x, lo[0], acc);
+            acc = fmaf(qv[t].y, lo[1], acc);
+            acc = fmaf(qv[t].z, hi[0], acc);
+            acc = fmaf(qv[t].w, hi[1], acc);
         }
     }
     return acc;
@@ -431,9 +429,20 @@ __global__ __launch_bounds__(64) void k_serve_step(SlotArgs sa) {
     run_search<G, NCH, ST>(a, qv, s, vis, qn, ptr, hops, evals, sa.hops_budget, done);
     if (done) {
         if constexpr (ST != RG_STORE_FP32) rerank_queue<G, NCH>(a, qv, s, qn);
+        int pos = 0;
+        if (lane == 0) pos = (int)atomicAdd(sa.out_count, 1u);
+        pos = __shfl(pos, 0);
+        ServeRecord *r = sa.out_rec + pos;
         for (int i = lane; i < a.k; i += 64) {
-            sa.slot_out_ids[(size_t)slot * kMaxL + i] = i < qn ? (s.qi[i] & ~kExpanded) : kNone;
-            sa.slot_out_d[(size_t)slot * kMaxL + i] = i < qn ? s.qd[i] : __builtin_inff();
+            r->ids[i] = i < qn ? (s.qi[i] & ~kExpanded) : kNone;
+            r->d[i] = i < qn ? s.qd[i] : __builtin_inff();
+        }
+        if (lane == 0) {
+            r->slot = slot;
+            r->qn = qn;
+            r->hops = hops;
+            r->evals = evals;
+            st[0] = 0;
         }
     } else {
         for (int i = lane; i < qn; i += 64) {
@@ -441,14 +450,26 @@ __global__ __launch_bounds__(64) void k_serve_step(SlotArgs sa) {
             gqi[i] = s.qi[i];
         }
         for (int i = lane; i < H; i += 64) gh[i] = s.htab[i];
+        if (lane == 0) {
+            st[0] = qn;
+            st[1] = ptr;
+            st[2] = vis.hcount;
+            st[3] = (int32_t)hops;
+            st[4] = (int32_t)evals;
+        }
     }
-    if (lane == 0) {
-        st[0] = qn;
-        st[1] = ptr;
-        st[2] = vis.hcount;
-        st[3] = (int32_t)hops;
-        st[4] = (int32_t)evals;
-        if (done) sa.slot_done[slot] = 1;
+}
+
+__global__ __launch_bounds__(64) void k_serve_admit(int32_t n, const int32_t *slots, const float *q,
+                                                   const int32_t *k, const int32_t *L, int32_t d, float *slot_q,
+                                                   int32_t *slot_k, int32_t *slot_L, int32_t *slot_state) {
+    const int i = blockIdx.x;
+    const int s = slots[i];
+    for (int j = threadIdx.x; j < d; j += 64) slot_q[(size_t)s * d + j] = q[(size_t)i * d + j];
+    if (threadIdx.x < 8) slot_state[(size_t)s * 8 + threadIdx.x] = 0;
+    if (threadIdx.x == 0) {
+        slot_k[s] = k[i];
+        slot_L[s] = L[i];
     }
 }
 
@@ -557,6 +578,16 @@ int search_occupancy(const SearchArgs &a, int *blocks_per_cu) {
     case RG_STORE_FP8E4M3: return dispatch_dim<OccLaunch, RG_STORE_FP8E4M3>(a.d, b, nullptr);
     default: set_error("search: unknown storage"); return RG_EINVAL;
     }
+}
+
+int launch_serve_admit(int32_t n, const int32_t *slots, const float *q, const int32_t *k, const int32_t *L,
+                       int32_t d, float *slot_q, int32_t *slot_k, int32_t *slot_L, int32_t *slot_state,
+                       hipStream_t stream) {
+    if (n == 0) return RG_OK;
+    hipLaunchKernelGGL(k_serve_admit, dim3((unsigned)n), dim3(64), 0, stream, n, slots, q, k, L, d, slot_q, slot_k,
+                       slot_L, slot_state);
+    RG_HIP(hipGetLastError());
+    return RG_OK;
 }
 
 int launch_serve_step(const SlotArgs &sa, hipStream_t stream) {

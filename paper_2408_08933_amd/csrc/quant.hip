@@ -79,6 +79,12 @@ __global__ __launch_bounds__(64) void k_quant_fp8(const float *src, int64_t n, i
     if (lane == 0) scales[r] = ldexpf(1.f, e);
 }
 
+// plain streaming copy (16 bytes per lane per step)
+__global__ void k_copy_probe(uint4 *dst, const uint4 *src, int64_t n16) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n16; i += (int64_t)gridDim.x * blockDim.x)
+        dst[i] = src[i];
+}
+
 unsigned grid_for(int64_t total, int threads) {
     int64_t g = (total + threads - 1) / threads;
     if (g > 65536) g = 65536;
@@ -109,6 +115,17 @@ int launch_quant_fp8(const float *src, int64_t n, int32_t d, int32_t pitch, uint
     if (n == 0) return RG_OK;
     hipLaunchKernelGGL(k_quant_fp8, dim3((unsigned)n), dim3(64), 0, stream, src, n, d, pitch, dst, pitch8,
                        scales);
+    RG_HIP(hipGetLastError());
+    return RG_OK;
+}
+
+int launch_copy_probe(void *dst, const void *src, int64_t bytes, hipStream_t stream) {
+    if (bytes % 16 != 0 || ((uintptr_t)dst | (uintptr_t)src) % 16 != 0) {
+        set_error("copy probe: bytes and pointers must be 16-byte aligned");
+        return RG_EINVAL;
+    }
+    hipLaunchKernelGGL(k_copy_probe, dim3(4096), dim3(256), 0, stream, static_cast<uint4 *>(dst),
+                       static_cast<const uint4 *>(src), bytes / 16);
     RG_HIP(hipGetLastError());
     return RG_OK;
 }

@@ -73,12 +73,26 @@ struct SlotArgs {
     int32_t *slot_state;        // slots x 4: qn, ptr, hops, evals
     uint32_t *slot_hash;        // slots x (1 << hash_bits)
     int32_t *slot_hcount;       // slots
-    uint32_t *slot_out_ids;     // slots x kMaxL
-    float *slot_out_d;          // slots x kMaxL
-    int32_t *slot_done;         // slots: set to 1 when finished
+    uint32_t *slot_out_ids;     // unused
+    float *slot_out_d;          // unused
+    int32_t *slot_done;         // unused
     int32_t hops_budget;
+    // finished requests are appended here: out_count (atomic) and records
+    uint32_t *out_count;
+    struct ServeRecord *out_rec;
+};
+// One finished request as the step kernel reports it.
+struct ServeRecord {
+    int32_t slot, qn;
+    uint32_t hops, evals;
+    uint32_t ids[kMaxL];
+    float d[kMaxL];
 };
 int launch_serve_step(const SlotArgs &a, hipStream_t stream);
+// Scatter n admitted requests (compact arrays) into their slots and reset their state.
+int launch_serve_admit(int32_t n, const int32_t *slots, const float *q, const int32_t *k, const int32_t *L,
+                       int32_t d, float *slot_q, int32_t *slot_k, int32_t *slot_L, int32_t *slot_state,
+                       hipStream_t stream);
 
 // knn.hip: top-K candidates by FP32 score (desc), ids asc on ties.
 int launch_knn_candidates(const float *Q, int64_t nq, int32_t ldq, const float *X, int64_t n,
@@ -92,6 +106,8 @@ int launch_quant_bf16(const float *src, int64_t n, int32_t pitch, uint16_t *dst,
                       hipStream_t stream);
 int launch_quant_fp8(const float *src, int64_t n, int32_t d, int32_t pitch, uint8_t *dst,
                      int32_t pitch8, float *scales, hipStream_t stream);
+
+int launch_copy_probe(void *dst, const void *src, int64_t bytes, hipStream_t stream);
 
 // host_build.cpp
 struct HostGraph {

@@ -53,10 +53,17 @@ struct rg_server {
     int32_t slots = 0, hash_bits = 12;
     hipStream_t stream = nullptr;
     // device slot arrays
-    float *d_q = nullptr, *d_qd = nullptr, *d_outd = nullptr;
-    int32_t *d_k = nullptr, *d_L = nullptr, *d_state = nullptr, *d_hcount = nullptr, *d_done = nullptr,
-            *d_active = nullptr;
-    uint32_t *d_qi = nullptr, *d_hash = nullptr, *d_outi = nullptr;
+    float *d_q = nullptr, *d_qd = nullptr;
+    int32_t *d_k = nullptr, *d_L = nullptr, *d_state = nullptr, *d_active = nullptr;
+    uint32_t *d_qi = nullptr, *d_hash = nullptr, *d_count = nullptr;
+    ServeRecord *d_rec = nullptr;
+    // admission staging (device) and pinned host mirrors
+    int32_t *d_adm_slot = nullptr, *d_adm_k = nullptr, *d_adm_L = nullptr;
+    float *d_adm_q = nullptr;
+    int32_t *h_adm_slot = nullptr, *h_adm_k = nullptr, *h_adm_L = nullptr, *h_active = nullptr;
+    float *h_adm_q = nullptr;
+    uint32_t *h_count = nullptr;
+    ServeRecord *h_rec = nullptr;
     // host side
     std::mutex mu;
     std::condition_variable cv;
@@ -75,19 +82,21 @@ struct rg_server {
 };
 
 void rg_server::release() {
-    void *ps[] = {d_q, d_qd, d_outd, d_k, d_L, d_state, d_hcount, d_done, d_active, d_qi, d_hash, d_outi};
+    void *ps[] = {d_q, d_qd, d_k, d_L, d_state, d_active, d_qi, d_hash, d_count, d_rec,
+                  d_adm_slot, d_adm_k, d_adm_L, d_adm_q};
     for (void *p : ps)
         if (p) (void)hipFree(p);
+    void *hs[] = {h_adm_slot, h_adm_k, h_adm_L, h_active, h_adm_q, h_count, h_rec};
+    for (void *p : hs)
+        if (p) (void)hipHostFree(p);
     if (stream) (void)hipStreamDestroy(stream);
 }
 
 void rg_server::loop() {
     (void)hipSetDevice(ix->device);
     const int d = ix->d;
-    std::vector<int32_t> active, done((size_t)slots);
-    std::vector<int32_t> zero_state(8, 0);
     for (;;) {
-        std::vector<int32_t> admitted;
+        int32_t n_adm_now = 0, n_active = 0;
         {
             std::unique_lock<std::mutex> lk(mu);
             bool any_busy = false;
@@ -98,31 +107,23 @@ void rg_server::loop() {
                 continue;
             }
             // admission: free slots in ascending order, requests in arrival order
+            const double t_adm = now();
             for (int32_t s = 0; s < slots && !pending.empty() && !stop; ++s) {
                 if (info[s].busy) continue;
-                Pending p = std::move(pending.front());
+                Pending &p = pending.front();
+                info[s] = SlotInfo{true, true, p.tag, p.k, p.L, p.t_submit, t_adm};
+                h_adm_slot[n_adm_now] = s;
+                h_adm_k[n_adm_now] = p.k;
+                h_adm_L[n_adm_now] = p.L;
+                std::memcpy(h_adm_q + (size_t)n_adm_now * d, p.q.data(), sizeof(float) * d);
+                ++n_adm_now;
                 pending.pop_front();
-                info[s] = SlotInfo{true, true, p.tag, p.k, p.L, p.t_submit, now()};
                 ++n_adm;
-                // stage the query and parameters (host -> device, ordered on the stream)
-                if (hipMemcpyAsync(d_q + (size_t)s * d, p.q.data(), sizeof(float) * d, hipMemcpyHostToDevice,
-                                   stream) != hipSuccess ||
-                    hipMemcpyAsync(d_k + s, &info[s].k, 4, hipMemcpyHostToDevice, stream) != hipSuccess ||
-                    hipMemcpyAsync(d_L + s, &info[s].L, 4, hipMemcpyHostToDevice, stream) != hipSuccess ||
-                    hipMemcpyAsync(d_state + (size_t)s * 8, zero_state.data(), 32, hipMemcpyHostToDevice, stream) !=
-                        hipSuccess ||
-                    hipMemcpyAsync(d_done + s, zero_state.data(), 4, hipMemcpyHostToDevice, stream) != hipSuccess) {
-                    err = RG_EDEVICE;
-                }
-                // the copies read p.q and info[s]: wait before they can change
-                (void)hipStreamSynchronize(stream);
-                admitted.push_back(s);
             }
-            active.clear();
             for (int32_t s = 0; s < slots; ++s)
-                if (info[s].busy) active.push_back(s);
+                if (info[s].busy) h_active[n_active++] = s;
         }
-        if (active.empty()) continue;
+        if (n_active == 0) continue;
         SlotArgs sa{};
         sa.s.base = ix->d_base;
         sa.s.base_bf16 = ix->d_bf16;
@@ -137,7 +138,7 @@ void rg_server::loop() {
         sa.s.entry = ix->entry;
         sa.s.storage = ix->storage;
         sa.active = d_active;
-        sa.n_active = (int32_t)active.size();
+        sa.n_active = n_active;
         sa.slot_q = d_q;
         sa.slot_k = d_k;
         sa.slot_L = d_L;
@@ -145,17 +146,30 @@ void rg_server::loop() {
         sa.slot_qi = d_qi;
         sa.slot_state = d_state;
         sa.slot_hash = d_hash;
-        sa.slot_hcount = d_hcount;
-        sa.slot_out_ids = d_outi;
-        sa.slot_out_d = d_outd;
-        sa.slot_done = d_done;
         sa.hops_budget = lim.hops_per_step;
-        if (hipMemcpyAsync(d_active, active.data(), sizeof(int32_t) * active.size(), hipMemcpyHostToDevice,
-                           stream) != hipSuccess ||
-            launch_serve_step(sa, stream) != RG_OK ||
-            hipMemcpyAsync(done.data(), d_done, sizeof(int32_t) * slots, hipMemcpyDeviceToHost, stream) !=
-                hipSuccess ||
-            hipStreamSynchronize(stream) != hipSuccess) {
+        sa.out_count = d_count;
+        sa.out_rec = d_rec;
+        bool ok = true;
+        if (n_adm_now > 0) {
+            ok = hipMemcpyAsync(d_adm_slot, h_adm_slot, 4 * n_adm_now, hipMemcpyHostToDevice, stream) == hipSuccess &&
+                 hipMemcpyAsync(d_adm_k, h_adm_k, 4 * n_adm_now, hipMemcpyHostToDevice, stream) == hipSuccess &&
+                 hipMemcpyAsync(d_adm_L, h_adm_L, 4 * n_adm_now, hipMemcpyHostToDevice, stream) == hipSuccess &&
+                 hipMemcpyAsync(d_adm_q, h_adm_q, sizeof(float) * d * n_adm_now, hipMemcpyHostToDevice, stream) ==
+                     hipSuccess &&
+                 launch_serve_admit(n_adm_now, d_adm_slot, d_adm_q, d_adm_k, d_adm_L, d, d_q, d_k, d_L, d_state,
+                                    stream) == RG_OK;
+        }
+        ok = ok &&
+             hipMemcpyAsync(d_active, h_active, sizeof(int32_t) * n_active, hipMemcpyHostToDevice, stream) ==
+                 hipSuccess &&
+             hipMemsetAsync(d_count, 0, 4, stream) == hipSuccess && launch_serve_step(sa, stream) == RG_OK &&
+             hipMemcpyAsync(h_count, d_count, 4, hipMemcpyDeviceToHost, stream) == hipSuccess &&
+             hipStreamSynchronize(stream) == hipSuccess;
+        const uint32_t nf = ok ? *h_count : 0;
+        if (ok && nf > 0)
+            ok = hipMemcpyAsync(h_rec, d_rec, sizeof(ServeRecord) * nf, hipMemcpyDeviceToHost, stream) == hipSuccess &&
+                 hipStreamSynchronize(stream) == hipSuccess;
+        if (!ok) {
             std::lock_guard<std::mutex> lk(mu);
             err = RG_EDEVICE;
             for (auto &s : info) s.busy = false;
@@ -163,28 +177,24 @@ void rg_server::loop() {
             continue;
         }
         ++n_steps;
-        for (int32_t s : active) {
-            if (!done[s]) continue;
+        const double t_done = now();
+        std::lock_guard<std::mutex> lk(mu);
+        for (uint32_t i = 0; i < nf; ++i) {
+            const ServeRecord &rec = h_rec[i];
+            SlotInfo &si = info[rec.slot];
             rg_result r{};
-            const SlotInfo &si = info[s];
             r.tag = si.tag;
             r.k = si.k;
             r.status = RG_OK;
-            int32_t st[8];
-            if (hipMemcpy(r.ids, d_outi + (size_t)s * kMaxL, sizeof(uint32_t) * si.k, hipMemcpyDeviceToHost) !=
-                    hipSuccess ||
-                hipMemcpy(r.dists, d_outd + (size_t)s * kMaxL, sizeof(float) * si.k, hipMemcpyDeviceToHost) !=
-                    hipSuccess ||
-                hipMemcpy(st, d_state + (size_t)s * 8, sizeof(st), hipMemcpyDeviceToHost) != hipSuccess)
-                r.status = RG_EDEVICE;
-            r.hops = (uint32_t)st[3];
-            r.evals = (uint32_t)st[4];
+            r.hops = rec.hops;
+            r.evals = rec.evals;
+            std::memcpy(r.ids, rec.ids, sizeof(uint32_t) * si.k);
+            std::memcpy(r.dists, rec.d, sizeof(float) * si.k);
             r.t_submit = si.t_submit;
             r.t_admit = si.t_admit;
-            r.t_done = now();
-            std::lock_guard<std::mutex> lk(mu);
+            r.t_done = t_done;
             finished.push_back(r);
-            info[s].busy = false;
+            si.busy = false;
             ++n_done;
         }
     }
@@ -207,9 +217,10 @@ int rg_server_create(const rg_index *ix, const rg_server_limits *lim, rg_server 
     s->ix = ix;
     s->lim = l;
     s->hash_bits = 12;
-    // device bytes one slot keeps between steps
-    const int64_t per_slot = (int64_t)ix->d * 4 + 8 + (int64_t)kMaxL * 8 + 32 + ((int64_t)4 << s->hash_bits) + 8 +
-                             (int64_t)kMaxL * 8 + 8;
+    // device bytes one slot keeps between steps: query, k/L, queue (keys + ids),
+    // state words, visited table, its result record
+    const int64_t per_slot = (int64_t)ix->d * 4 + 8 + (int64_t)kMaxL * 8 + 32 + ((int64_t)4 << s->hash_bits) +
+                             (int64_t)sizeof(ServeRecord);
     int64_t slots = l.max_slots;
     if (l.hbm_pool_bytes > 0) slots = std::min<int64_t>(slots, l.hbm_pool_bytes / per_slot);
     if (slots < 1) {
@@ -222,6 +233,7 @@ int rg_server_create(const rg_index *ix, const rg_server_limits *lim, rg_server 
     (void)hipSetDevice(ix->device);
     bool ok = hipStreamCreate(&s->stream) == hipSuccess;
     auto al = [&](void **p, size_t b) { ok = ok && hipMalloc(p, b) == hipSuccess; };
+    auto ah = [&](void **p, size_t b) { ok = ok && hipHostMalloc(p, b, hipHostMallocDefault) == hipSuccess; };
     al((void **)&s->d_q, sizeof(float) * slots * ix->d);
     al((void **)&s->d_k, 4 * slots);
     al((void **)&s->d_L, 4 * slots);
@@ -229,15 +241,24 @@ int rg_server_create(const rg_index *ix, const rg_server_limits *lim, rg_server 
     al((void **)&s->d_qi, sizeof(uint32_t) * slots * kMaxL);
     al((void **)&s->d_state, 32 * slots);
     al((void **)&s->d_hash, (size_t)slots << (s->hash_bits + 2));
-    al((void **)&s->d_hcount, 4 * slots);
-    al((void **)&s->d_outi, sizeof(uint32_t) * slots * kMaxL);
-    al((void **)&s->d_outd, sizeof(float) * slots * kMaxL);
-    al((void **)&s->d_done, 4 * slots);
     al((void **)&s->d_active, 4 * slots);
+    al((void **)&s->d_count, 4);
+    al((void **)&s->d_rec, sizeof(ServeRecord) * slots);
+    al((void **)&s->d_adm_slot, 4 * slots);
+    al((void **)&s->d_adm_k, 4 * slots);
+    al((void **)&s->d_adm_L, 4 * slots);
+    al((void **)&s->d_adm_q, sizeof(float) * slots * ix->d);
+    ah((void **)&s->h_adm_slot, 4 * slots);
+    ah((void **)&s->h_adm_k, 4 * slots);
+    ah((void **)&s->h_adm_L, 4 * slots);
+    ah((void **)&s->h_active, 4 * slots);
+    ah((void **)&s->h_adm_q, sizeof(float) * slots * ix->d);
+    ah((void **)&s->h_count, 4);
+    ah((void **)&s->h_rec, sizeof(ServeRecord) * slots);
     if (!ok) {
         s->release();
         delete s;
-        set_error("rg_server_create: out of device memory");
+        set_error("rg_server_create: out of memory");
         return RG_ENOMEM;
     }
     s->t0 = std::chrono::steady_clock::now();
