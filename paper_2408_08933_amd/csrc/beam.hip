@@ -12,16 +12,18 @@
 //     work done, never the result;
 //   * the candidate batch of the current expansion.
 // Per expansion: pick the first unexpanded queue entry, read its adjacency
-// row (ELL, one id per lane), filter through the visited table, gather the
-// new neighbours' rows (G lanes per row, float4 loads, coalesced), reduce
-// the FP32 dot products inside each G-lane group with xor shuffles, sort the
-// batch in registers, and merge the entries that beat the queue's last key.
-// The search stops when every queue entry is expanded.
+// row (ELL, one id per lane), filter through the visited set, gather the
+// new neighbours' rows (G lanes per row, 16-byte loads, R rows per group in
+// flight), reduce the FP32 dot products inside each G-lane group with xor
+// shuffles, sort the batch in registers, and merge the entries that beat the
+// queue's last key.  The search stops when every queue entry is expanded.
 //
-// Dot products: lane j of a group accumulates, with fused multiply-adds in
-// order, the coordinates 4c..4c+3 of chunks c = j, j+G, j+2G, ...; then the
-// G partial sums are added by a log2(G)-level xor tree.  A distance is
-// therefore a fixed function of (query, row) whichever group computes it.
+// Rows are read in 16-byte chunks of EPC elements (4 FP32, 8 BF16 or 16
+// E4M3 values).  Lane j of a group accumulates, with fused multiply-adds in
+// order, the elements of chunks c = j, j+G, j+2G, ...; then the G partial
+// sums are added by a log2(G)-level xor tree (times the row's scale for
+// E4M3).  A distance is therefore a fixed function of (query, row)
+// whichever group computes it.
 #include "rg_internal.h"
 #include "queue_ops.h"
 #include "wave_ops.h"
@@ -35,6 +37,7 @@ constexpr uint32_t kEmpty = 0xFFFFFFFFu;
 constexpr int kCand = 128;  // candidate-batch capacity (>= the largest ELL width)
 
 struct Lds {
+    float *qs;      // the query, zero padded to the row pitch
     float *qd;
     uint32_t *qi;
     float *cd;
@@ -45,9 +48,10 @@ struct Lds {
     uint32_t *htab;
 };
 
-__device__ __forceinline__ Lds carve(unsigned char *p, int Leff) {
+__device__ __forceinline__ Lds carve(unsigned char *p, int Leff, int pitch) {
     Lds s;
-    s.qd = reinterpret_cast<float *>(p);
+    s.qs = reinterpret_cast<float *>(p);
+    s.qd = s.qs + pitch;
     s.qi = reinterpret_cast<uint32_t *>(s.qd + Leff);
     s.cd = reinterpret_cast<float *>(s.qi + Leff);
     s.ci = reinterpret_cast<uint32_t *>(s.cd + kCand);
@@ -61,76 +65,109 @@ __device__ __forceinline__ Lds carve(unsigned char *p, int Leff) {
 typedef float f32x2 __attribute__((ext_vector_type(2)));
 
 
-template <int G, int NCH>
-__device__ __forceinline__ void load_query(const float *q, int d, float4 (&qv)[NCH]) {
-    const int j = lane_id() % G;
-#pragma unroll
-    for (int t = 0; t < NCH; ++t) {
-        const int e = 4 * (j + G * t);
-        qv[t].x = e + 0 < d ? q[e + 0] : 0.f;
-        qv[t].y = e + 1 < d ? q[e + 1] : 0.f;
-        qv[t].z = e + 2 < d ? q[e + 2] : 0.f;
-        qv[t].w = e + 3 < d ? q[e + 3] : 0.f;
-    }
+// Storage formats: 16-byte chunks of EPC elements.
+template <int ST>
+struct Fmt {
+    static constexpr int EPC = 4;
+};
+template <>
+struct Fmt<RG_STORE_BF16> {
+    static constexpr int EPC = 8;
+};
+template <>
+struct Fmt<RG_STORE_FP8E4M3> {
+    static constexpr int EPC = 16;
+};
+
+// Lane shape per dimension class (d <= 64, 128, 224, 256, 512, 1024) and
+// storage: G lanes per row and NCH chunks per lane, G * NCH * EPC >= d; R rows
+// per group whose loads are in flight together.
+constexpr int kClassMaxD[6] = {64, 128, 224, 256, 512, 1024};
+constexpr int shape_g(int st, int cls) {
+    constexpr int g32[6] = {16, 16, 8, 16, 16, 32}, g16[6] = {8, 16, 8, 8, 16, 32}, g8[6] = {4, 8, 8, 8, 16, 32};
+    return st == RG_STORE_FP32 ? g32[cls] : st == RG_STORE_BF16 ? g16[cls] : g8[cls];
+}
+constexpr int shape_nch(int st, int cls) {
+    constexpr int n32[6] = {1, 2, 7, 4, 8, 8}, n16[6] = {1, 1, 4, 4, 4, 4}, n8[6] = {1, 1, 2, 2, 2, 2};
+    return st == RG_STORE_FP32 ? n32[cls] : st == RG_STORE_BF16 ? n16[cls] : n8[cls];
+}
+constexpr int shape_r(int st) { return st == RG_STORE_FP32 ? 2 : st == RG_STORE_BF16 ? 3 : 6; }
+
+// Copy the query into LDS, zero padded to the row pitch.
+__device__ __forceinline__ void load_query(const float *q, int d, int pitch, float *qs) {
+    for (int i = lane_id(); i < pitch; i += 64) qs[i] = i < d ? q[i] : 0.f;
+    __syncthreads();
 }
 
-// This lane's partial dot product of the query with row u (kNone -> 0).
-template <int G, int NCH, int ST>
-__device__ __forceinline__ float row_partial(const SearchArgs &a, uint32_t u, const float4 (&qv)[NCH],
-                                             int nch) {
-    float acc = 0.f;
-    if (u == kNone) return acc;
-    const int j = lane_id() % G;
+template <int ST>
+__device__ __forceinline__ const uint4 *row_chunks(const SearchArgs &a, uint32_t u) {
+    if constexpr (ST == RG_STORE_FP32) return reinterpret_cast<const uint4 *>(a.base + (size_t)u * a.pitch);
+    if constexpr (ST == RG_STORE_BF16) return reinterpret_cast<const uint4 *>(a.base_bf16 + (size_t)u * a.pitch);
+    return reinterpret_cast<const uint4 *>(a.base_fp8 + (size_t)u * a.pitch8);
+}
+
+// acc += q . chunk c, in element order; q is read from LDS
+template <int ST>
+__device__ __forceinline__ float fma_chunk(const float *qs, int c, uint4 x, float acc) {
+    constexpr int EPC = Fmt<ST>::EPC;
+    const float4 *q4 = reinterpret_cast<const float4 *>(qs + c * EPC);
+    const uint32_t w[4] = {x.x, x.y, x.z, x.w};
     if constexpr (ST == RG_STORE_FP32) {
-        const float4 *row = reinterpret_cast<const float4 *>(a.base + (size_t)u * a.pitch);
-        float4 x[NCH];
-#pragma unroll
-        for (int t = 0; t < NCH; ++t) {
-            const int c = j + G * t;
-            x[t] = c < nch ? row[c] : make_float4(0.f, 0.f, 0.f, 0.f);
-        }
-#pragma unroll
-        for (int t = 0; t < NCH; ++t) {
-            acc = fmaf(qv[t].x, x[t].x, acc);
-            acc = fmaf(qv[t].y, x[t].y, acc);
-            acc = fmaf(qv[t].z, x[t].z, acc);
-            acc = fmaf(qv[t].w, x[t].w, acc);
-        }
+        const float4 q = q4[0];
+        acc = fmaf(q.x, __uint_as_float(w[0]), acc);
+        acc = fmaf(q.y, __uint_as_float(w[1]), acc);
+        acc = fmaf(q.z, __uint_as_float(w[2]), acc);
+        acc = fmaf(q.w, __uint_as_float(w[3]), acc);
     } else if constexpr (ST == RG_STORE_BF16) {
-        const uint2 *row = reinterpret_cast<const uint2 *>(a.base_bf16 + (size_t)u * a.pitch);
-        uint2 x[NCH];
 #pragma unroll
-        for (int t = 0; t < NCH; ++t) {
-            const int c = j + G * t;
-            x[t] = c < nch ? row[c] : make_uint2(0u, 0u);
-        }
-#pragma unroll
-        for (int t = 0; t < NCH; ++t) {
-            acc = fmaf(qv[t].x, __uint_as_float(x[t].x << 16), acc);
-            acc = fmaf(qv[t].y, __uint_as_float(x[t].x & 0xFFFF0000u), acc);
-            acc = fmaf(qv[t].z, __uint_as_float(x[t].y << 16), acc);
-            acc = fmaf(qv[t].w, __uint_as_float(x[t].y & 0xFFFF0000u), acc);
+        for (int i = 0; i < 2; ++i) {
+            const float4 q = q4[i];
+            acc = fmaf(q.x, __uint_as_float(w[2 * i] << 16), acc);
+            acc = fmaf(q.y, __uint_as_float(w[2 * i] & 0xFFFF0000u), acc);
+            acc = fmaf(q.z, __uint_as_float(w[2 * i + 1] << 16), acc);
+            acc = fmaf(q.w, __uint_as_float(w[2 * i + 1] & 0xFFFF0000u), acc);
         }
     } else {
-        const uint32_t *row = reinterpret_cast<const uint32_t *>(a.base_fp8 + (size_t)u * a.pitch8);
-        uint32_t x[NCH];
 #pragma unroll
-        for (int t = 0; t < NCH; ++t) {
-            const int c = j + G * t;
-            x[t] = c < nch ? row[c] : 0u;
-        }
-#pragma unroll
-        for (int t = 0; t < NCH; ++t) {
+        for (int i = 0; i < 4; ++i) {
             // gfx950 converts OCP E4M3 pairs exactly (every code is a float)
-            const f32x2 lo = __builtin_amdgcn_cvt_pk_f32_fp8((int)x[t], false);
-            const f32x2 hi = __builtin_amdgcn_cvt_pk_f32_fp8((int)x[t], true);
-            acc = fmaf(qv[t].x, lo[0], acc);
-            acc = fmaf(qv[t].y, lo[1], acc);
-            acc = fmaf(qv[t].z, hi[0], acc);
-            acc = fmaf(qv[t].w, hi[1], acc);
+            const float4 q = q4[i];
+            const f32x2 lo = __builtin_amdgcn_cvt_pk_f32_fp8((int)w[i], false);
+            const f32x2 hi = __builtin_amdgcn_cvt_pk_f32_fp8((int)w[i], true);
+            acc = fmaf(q.x, lo[0], acc);
+            acc = fmaf(q.y, lo[1], acc);
+            acc = fmaf(q.z, hi[0], acc);
+            acc = fmaf(q.w, hi[1], acc);
         }
     }
     return acc;
+}
+
+// This lane's partial dot products with rows u[0..R) (kNone -> 0); all loads
+// are issued before the first multiply.
+template <int ST, int G, int NCH, int R>
+__device__ __forceinline__ void dot_rows(const SearchArgs &a, const uint32_t (&u)[R], const float *qs, int nch,
+                                         float (&acc)[R]) {
+    const int j = lane_id() % G;
+    uint4 raw[R][NCH];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const uint4 *row = row_chunks<ST>(a, u[r] != kNone ? u[r] : 0u);
+#pragma unroll
+        for (int t = 0; t < NCH; ++t) {
+            const int c = j + G * t;
+            raw[r][t] = (u[r] != kNone && c < nch) ? row[c] : make_uint4(0u, 0u, 0u, 0u);
+        }
+    }
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        acc[r] = 0.f;
+#pragma unroll
+        for (int t = 0; t < NCH; ++t) {
+            const int c = j + G * t;
+            if (c < nch) acc[r] = fma_chunk<ST>(qs, c, raw[r][t], acc[r]);
+        }
+    }
 }
 
 template <int G>
@@ -141,7 +178,7 @@ __device__ __forceinline__ float group_sum(float v) {
 }
 
 // delta of this group's row u (uniform within the group)
-template <int G, int ST>
+template <int ST>
 __device__ __forceinline__ float finish_delta(const SearchArgs &a, uint32_t u, float sum) {
     if constexpr (ST == RG_STORE_FP8E4M3) {
         const float s = u == kNone ? 1.f : a.scale_fp8[u];
@@ -151,23 +188,29 @@ __device__ __forceinline__ float finish_delta(const SearchArgs &a, uint32_t u, f
     }
 }
 
-// Score ids[0..cnt) (LDS) into dout[0..cnt) (LDS); two rows per group in flight.
-template <int G, int NCH, int ST>
-__device__ __forceinline__ void score_batch(const SearchArgs &a, const float4 (&qv)[NCH], int nch,
-                                            const uint32_t *ids, uint32_t idmask, float *dout, int cnt) {
+// Score ids[0..cnt) (LDS) into dout[0..cnt) (LDS); R rows per group in flight.
+template <int ST, int G, int NCH, int R>
+__device__ __forceinline__ void score_batch(const SearchArgs &a, const float *qs, int nch, const uint32_t *ids,
+                                            uint32_t idmask, float *dout, int cnt) {
     constexpr int NG = 64 / G;
     const int g = lane_id() / G, j = lane_id() % G;
-    for (int p = 0; p < cnt; p += 2 * NG) {
-        const int s0 = p + g, s1 = p + NG + g;
-        const uint32_t u0 = s0 < cnt ? (ids[s0] & idmask) : kNone;
-        const uint32_t u1 = s1 < cnt ? (ids[s1] & idmask) : kNone;
-        float a0 = row_partial<G, NCH, ST>(a, u0, qv, nch);
-        float a1 = row_partial<G, NCH, ST>(a, u1, qv, nch);
-        a0 = group_sum<G>(a0);
-        a1 = group_sum<G>(a1);
+    for (int p = 0; p < cnt; p += NG * R) {
+        uint32_t u[R];
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const int sl = p + r * NG + g;
+            u[r] = sl < cnt ? (ids[sl] & idmask) : kNone;
+        }
+        float acc[R];
+        dot_rows<ST, G, NCH, R>(a, u, qs, nch, acc);
+#pragma unroll
+        for (int r = 0; r < R; ++r) acc[r] = group_sum<G>(acc[r]);
         if (j == 0) {
-            if (s0 < cnt) dout[s0] = finish_delta<G, ST>(a, u0, a0);
-            if (s1 < cnt) dout[s1] = finish_delta<G, ST>(a, u1, a1);
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                const int sl = p + r * NG + g;
+                if (sl < cnt) dout[sl] = finish_delta<ST>(a, u[r], acc[r]);
+            }
         }
     }
 }
@@ -227,12 +270,13 @@ struct VisitBitmap {
 };
 
 // Expansions until done or `budget` expansions were made.
-template <int G, int NCH, int ST, class VIS>
-__device__ __forceinline__ void run_search(const SearchArgs &a, const float4 (&qv)[NCH], const Lds &s, VIS &vis,
+template <int ST, int CLS, class VIS>
+__device__ __forceinline__ void run_search(const SearchArgs &a, const Lds &s, VIS &vis,
                                            int &qn, int &ptr, uint32_t &hops, uint32_t &evals, int budget,
                                            bool &done) {
+    constexpr int G = shape_g(ST, CLS), NCH = shape_nch(ST, CLS), R = shape_r(ST);
     const int lane = lane_id();
-    const int Leff = a.Leff, ell = a.ell, nch = (a.d + 3) >> 2;
+    const int Leff = a.Leff, ell = a.ell, nch = (a.d + Fmt<ST>::EPC - 1) / Fmt<ST>::EPC;
     done = false;
     for (; budget > 0; --budget) {
         int sel = -1;
@@ -268,7 +312,7 @@ __device__ __forceinline__ void run_search(const SearchArgs &a, const float4 (&q
         evals += (uint32_t)nnew;
         __syncthreads();
         if (nnew == 0) continue;
-        score_batch<G, NCH, ST>(a, qv, nch, s.ci, 0xFFFFFFFFu, s.cd, nnew);
+        score_batch<ST, G, NCH, R>(a, s.qs, nch, s.ci, 0xFFFFFFFFu, s.cd, nnew);
         __syncthreads();
         const QueueLds<float> ql{s.qd, s.qi, s.cd, s.ci, s.sd, s.si, s.slb};
         if (nnew <= 64)
@@ -279,17 +323,19 @@ __device__ __forceinline__ void run_search(const SearchArgs &a, const float4 (&q
 }
 
 // Queue = [entry]; the visited set is cleared and holds the entry.
-template <int G, int NCH, int ST, class VIS>
-__device__ __forceinline__ void init_state(const SearchArgs &a, const float4 (&qv)[NCH], const Lds &s, VIS &vis,
-                                           int &qn, int &ptr, uint32_t &hops, uint32_t &evals) {
+template <int ST, int CLS, class VIS>
+__device__ __forceinline__ void init_state(const SearchArgs &a, const Lds &s, VIS &vis, int &qn, int &ptr,
+                                           uint32_t &hops, uint32_t &evals) {
+    constexpr int G = shape_g(ST, CLS), NCH = shape_nch(ST, CLS);
     const int lane = lane_id();
     vis.clear();
-    const uint32_t u = lane < G ? a.entry : kNone;
-    float acc = row_partial<G, NCH, ST>(a, u, qv, (a.d + 3) >> 2);
-    acc = group_sum<G>(acc);
+    const uint32_t u[1] = {lane < G ? a.entry : kNone};
+    float acc[1];
+    dot_rows<ST, G, NCH, 1>(a, u, s.qs, (a.d + Fmt<ST>::EPC - 1) / Fmt<ST>::EPC, acc);
+    acc[0] = group_sum<G>(acc[0]);
     __syncthreads();
     if (lane == 0) {
-        s.qd[0] = finish_delta<G, ST>(a, a.entry, acc);
+        s.qd[0] = finish_delta<ST>(a, a.entry, acc[0]);
         s.qi[0] = a.entry;
         vis.mark_entry(a.entry);
     }
@@ -302,9 +348,10 @@ __device__ __forceinline__ void init_state(const SearchArgs &a, const float4 (&q
 }
 
 // Rescore the final queue against FP32 rows and sort it (reduced-precision storage).
-template <int G, int NCH>
-__device__ __forceinline__ void rerank_queue(const SearchArgs &a, const float4 (&qv)[NCH], const Lds &s, int qn) {
-    score_batch<G, NCH, RG_STORE_FP32>(a, qv, (a.d + 3) >> 2, s.qi, ~kExpanded, s.qd, qn);
+template <int CLS>
+__device__ __forceinline__ void rerank_queue(const SearchArgs &a, const Lds &s, int qn) {
+    constexpr int G = shape_g(RG_STORE_FP32, CLS), NCH = shape_nch(RG_STORE_FP32, CLS);
+    score_batch<RG_STORE_FP32, G, NCH, 2>(a, s.qs, (a.d + 3) >> 2, s.qi, ~kExpanded, s.qd, qn);
     __syncthreads();
     constexpr int E = kMaxL / 64;
     const int lane = lane_id();
@@ -329,7 +376,6 @@ __device__ __forceinline__ void rerank_queue(const SearchArgs &a, const float4 (
     __syncthreads();
 }
 
-template <int G, int NCH, int ST>
 __device__ __forceinline__ void write_result(const SearchArgs &a, const Lds &s, int64_t q, int qn, uint32_t hops,
                                              uint32_t evals) {
     const int lane = lane_id();
@@ -344,31 +390,30 @@ __device__ __forceinline__ void write_result(const SearchArgs &a, const Lds &s, 
 }
 
 // One query per workgroup, visited set in LDS.
-template <int G, int NCH, int ST>
+template <int ST, int CLS>
 __global__ __launch_bounds__(64) void k_search(SearchArgs a) {
     extern __shared__ __align__(16) unsigned char smem[];
     const int64_t q = blockIdx.x;
-    const Lds s = carve(smem, a.Leff);
+    const Lds s = carve(smem, a.Leff, a.pitch);
     VisitLds vis{s.htab, a.hash_bits, 1 << a.hash_bits, 0};
-    float4 qv[NCH];
-    load_query<G, NCH>(a.queries + q * a.d, a.d, qv);
+    load_query(a.queries + q * a.d, a.d, a.pitch, s.qs);
     int qn, ptr;
     uint32_t hops, evals;
     bool done;
-    init_state<G, NCH, ST>(a, qv, s, vis, qn, ptr, hops, evals);
-    run_search<G, NCH, ST>(a, qv, s, vis, qn, ptr, hops, evals, INT_MAX, done);
-    if constexpr (ST != RG_STORE_FP32) rerank_queue<G, NCH>(a, qv, s, qn);
-    write_result<G, NCH, ST>(a, s, q, qn, hops, evals);
+    init_state<ST, CLS>(a, s, vis, qn, ptr, hops, evals);
+    run_search<ST, CLS>(a, s, vis, qn, ptr, hops, evals, INT_MAX, done);
+    if constexpr (ST != RG_STORE_FP32) rerank_queue<CLS>(a, s, qn);
+    write_result(a, s, q, qn, hops, evals);
 }
 
 // Persistent grid: each workgroup stays resident, takes queries from a
 // device counter until none are left, and keeps an exact visited bitmap
 // (one bit per base node) in device memory, so LDS holds only the queue and
 // the candidate batch and many more queries are in flight per CU.
-template <int G, int NCH, int ST>
+template <int ST, int CLS>
 __global__ __launch_bounds__(64) void k_search_persistent(SearchArgs a) {
     extern __shared__ __align__(16) unsigned char smem[];
-    const Lds s = carve(smem, a.Leff);
+    const Lds s = carve(smem, a.Leff, a.pitch);
     VisitBitmap vis{a.bitmap + (size_t)blockIdx.x * a.bm_words, a.bm_words};
     const int lane = lane_id();
     for (;;) {
@@ -376,33 +421,31 @@ __global__ __launch_bounds__(64) void k_search_persistent(SearchArgs a) {
         if (lane == 0) q = (int)atomicAdd(a.work, 1u);
         q = __shfl(q, 0);
         if ((int64_t)q >= a.nq) break;
-        float4 qv[NCH];
-        load_query<G, NCH>(a.queries + (int64_t)q * a.d, a.d, qv);
+        load_query(a.queries + (int64_t)q * a.d, a.d, a.pitch, s.qs);
         int qn, ptr;
         uint32_t hops, evals;
         bool done;
-        init_state<G, NCH, ST>(a, qv, s, vis, qn, ptr, hops, evals);
-        run_search<G, NCH, ST>(a, qv, s, vis, qn, ptr, hops, evals, INT_MAX, done);
-        if constexpr (ST != RG_STORE_FP32) rerank_queue<G, NCH>(a, qv, s, qn);
-        write_result<G, NCH, ST>(a, s, q, qn, hops, evals);
+        init_state<ST, CLS>(a, s, vis, qn, ptr, hops, evals);
+        run_search<ST, CLS>(a, s, vis, qn, ptr, hops, evals, INT_MAX, done);
+        if constexpr (ST != RG_STORE_FP32) rerank_queue<CLS>(a, s, qn);
+        write_result(a, s, q, qn, hops, evals);
         __syncthreads();
     }
 }
 
 // One scheduler step of the serving loop: advance each listed slot by up to
 // hops_budget expansions, keeping its whole state in device memory.
-template <int G, int NCH, int ST>
+template <int ST, int CLS>
 __global__ __launch_bounds__(64) void k_serve_step(SlotArgs sa) {
     extern __shared__ __align__(16) unsigned char smem[];
     const int slot = sa.active[blockIdx.x];
     SearchArgs a = sa.s;
     a.k = sa.slot_k[slot];
     a.Leff = max(sa.slot_L[slot], a.k);
-    const Lds s = carve(smem, a.Leff);
+    const Lds s = carve(smem, a.Leff, a.pitch);
     const int lane = lane_id();
     const int H = 1 << a.hash_bits;
-    float4 qv[NCH];
-    load_query<G, NCH>(sa.slot_q + (size_t)slot * a.d, a.d, qv);
+    load_query(sa.slot_q + (size_t)slot * a.d, a.d, a.pitch, s.qs);
     int32_t *st = sa.slot_state + (size_t)slot * 8;
     float *gqd = sa.slot_qd + (size_t)slot * kMaxL;
     uint32_t *gqi = sa.slot_qi + (size_t)slot * kMaxL;
@@ -411,7 +454,7 @@ __global__ __launch_bounds__(64) void k_serve_step(SlotArgs sa) {
     uint32_t hops, evals;
     VisitLds vis{s.htab, a.hash_bits, H, 0};
     if (st[0] == 0) {
-        init_state<G, NCH, ST>(a, qv, s, vis, qn, ptr, hops, evals);
+        init_state<ST, CLS>(a, s, vis, qn, ptr, hops, evals);
     } else {
         qn = st[0];
         ptr = st[1];
@@ -426,9 +469,9 @@ __global__ __launch_bounds__(64) void k_serve_step(SlotArgs sa) {
         __syncthreads();
     }
     bool done;
-    run_search<G, NCH, ST>(a, qv, s, vis, qn, ptr, hops, evals, sa.hops_budget, done);
+    run_search<ST, CLS>(a, s, vis, qn, ptr, hops, evals, sa.hops_budget, done);
     if (done) {
-        if constexpr (ST != RG_STORE_FP32) rerank_queue<G, NCH>(a, qv, s, qn);
+        if constexpr (ST != RG_STORE_FP32) rerank_queue<CLS>(a, s, qn);
         int pos = 0;
         if (lane == 0) pos = (int)atomicAdd(sa.out_count, 1u);
         pos = __shfl(pos, 0);
@@ -473,73 +516,71 @@ __global__ __launch_bounds__(64) void k_serve_admit(int32_t n, const int32_t *sl
     }
 }
 
-template <int G, int NCH, int ST>
+template <int ST, int CLS>
 int launch_one(const SearchArgs &a, hipStream_t stream) {
-    const size_t lds = search_lds_bytes(a.Leff, a.ell, a.hash_bits);
-    hipLaunchKernelGGL((k_search<G, NCH, ST>), dim3((unsigned)a.nq), dim3(64), lds, stream, a);
+    const size_t lds = search_lds_bytes(a.Leff, a.pitch, a.hash_bits);
+    hipLaunchKernelGGL((k_search<ST, CLS>), dim3((unsigned)a.nq), dim3(64), lds, stream, a);
     RG_HIP(hipGetLastError());
     return RG_OK;
 }
 
-template <int G, int NCH, int ST>
+template <int ST, int CLS>
 int launch_persistent(const SearchArgs &a, hipStream_t stream) {
-    const size_t lds = search_lds_bytes(a.Leff, a.ell, 0);
-    hipLaunchKernelGGL((k_search_persistent<G, NCH, ST>), dim3((unsigned)a.grid), dim3(64), lds, stream, a);
+    const size_t lds = search_lds_bytes(a.Leff, a.pitch, 0);
+    hipLaunchKernelGGL((k_search_persistent<ST, CLS>), dim3((unsigned)a.grid), dim3(64), lds, stream, a);
     RG_HIP(hipGetLastError());
     return RG_OK;
 }
 
-template <int G, int NCH, int ST>
-int occupancy_of(int Leff, int *blocks_per_cu) {
-    const size_t lds = search_lds_bytes(Leff, 0, 0);
-    RG_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k_search_persistent<G, NCH, ST>, 64, lds));
+template <int ST, int CLS>
+int occupancy_of(int Leff, int pitch, int *blocks_per_cu) {
+    const size_t lds = search_lds_bytes(Leff, pitch, 0);
+    RG_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k_search_persistent<ST, CLS>, 64, lds));
     return RG_OK;
 }
 
-template <int G, int NCH, int ST>
+template <int ST, int CLS>
 int launch_step(const SlotArgs &sa, hipStream_t stream) {
-    const size_t lds = search_lds_bytes(kMaxL, sa.s.ell, sa.s.hash_bits);
-    hipLaunchKernelGGL((k_serve_step<G, NCH, ST>), dim3((unsigned)sa.n_active), dim3(64), lds, stream, sa);
+    const size_t lds = search_lds_bytes(kMaxL, sa.s.pitch, sa.s.hash_bits);
+    hipLaunchKernelGGL((k_serve_step<ST, CLS>), dim3((unsigned)sa.n_active), dim3(64), lds, stream, sa);
     RG_HIP(hipGetLastError());
     return RG_OK;
 }
 
-// (G, NCH) for a dimension: G lanes per row, NCH float4 chunks per lane.
-template <template <int, int, int> class F, int ST, typename Arg>
+// dimension class of d (see kClassMaxD)
+template <template <int, int> class F, int ST, typename Arg>
 int dispatch_dim(int d, const Arg &a, hipStream_t stream) {
-    const int nch = (d + 3) / 4;
-    if (nch <= 16) return F<16, 1, ST>::run(a, stream);
-    if (nch <= 32) return F<16, 2, ST>::run(a, stream);
-    if (nch <= 56) return F<8, 7, ST>::run(a, stream);
-    if (nch <= 64) return F<16, 4, ST>::run(a, stream);
-    if (nch <= 128) return F<16, 8, ST>::run(a, stream);
-    if (nch <= 256) return F<32, 8, ST>::run(a, stream);
+    if (d <= kClassMaxD[0]) return F<ST, 0>::run(a, stream);
+    if (d <= kClassMaxD[1]) return F<ST, 1>::run(a, stream);
+    if (d <= kClassMaxD[2]) return F<ST, 2>::run(a, stream);
+    if (d <= kClassMaxD[3]) return F<ST, 3>::run(a, stream);
+    if (d <= kClassMaxD[4]) return F<ST, 4>::run(a, stream);
+    if (d <= kClassMaxD[5]) return F<ST, 5>::run(a, stream);
     set_error("search: d > 1024 is not supported");
     return RG_EINVAL;
 }
 
-template <int G, int NCH, int ST>
+template <int ST, int CLS>
 struct SearchLaunch {
-    static int run(const SearchArgs &a, hipStream_t s) { return launch_one<G, NCH, ST>(a, s); }
+    static int run(const SearchArgs &a, hipStream_t s) { return launch_one<ST, CLS>(a, s); }
 };
-template <int G, int NCH, int ST>
+template <int ST, int CLS>
 struct PersistentLaunch {
-    static int run(const SearchArgs &a, hipStream_t s) { return launch_persistent<G, NCH, ST>(a, s); }
+    static int run(const SearchArgs &a, hipStream_t s) { return launch_persistent<ST, CLS>(a, s); }
 };
-template <int G, int NCH, int ST>
+template <int ST, int CLS>
 struct OccLaunch {
-    static int run(const SearchArgs &a, hipStream_t) { return occupancy_of<G, NCH, ST>(a.Leff, a.occ_out); }
+    static int run(const SearchArgs &a, hipStream_t) { return occupancy_of<ST, CLS>(a.Leff, a.pitch, a.occ_out); }
 };
-template <int G, int NCH, int ST>
+template <int ST, int CLS>
 struct StepLaunch {
-    static int run(const SlotArgs &a, hipStream_t s) { return launch_step<G, NCH, ST>(a, s); }
+    static int run(const SlotArgs &a, hipStream_t s) { return launch_step<ST, CLS>(a, s); }
 };
 
 }  // namespace
 
-size_t search_lds_bytes(int Leff, int ell, int hash_bits) {
-    (void)ell;
-    return (size_t)Leff * 8 + (size_t)kCand * 20 + (hash_bits > 0 ? ((size_t)4 << hash_bits) : 0);
+size_t search_lds_bytes(int Leff, int pitch, int hash_bits) {
+    return (size_t)pitch * 4 + (size_t)Leff * 8 + (size_t)kCand * 20 + (hash_bits > 0 ? ((size_t)4 << hash_bits) : 0);
 }
 
 int default_hash_bits(int Leff) {

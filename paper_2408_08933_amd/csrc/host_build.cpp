@@ -278,10 +278,13 @@ void lists_to_csr(const Lists &L, int64_t n, std::vector<int64_t> &off, std::vec
 
 // Enhancement searches on the device (canonical FP64 distance, bit-identical
 // to the host searcher), then each node's own selection on host threads.
+// Double buffered: the device searches batch i+1 while the host selects for
+// batch i.
 int enhance_on_device(const float *X, int64_t n, int32_t d, const Lists &PJ, const std::vector<int64_t> &pjoff,
                       const std::vector<uint32_t> &pjidx, uint32_t entry, int32_t L, int32_t m_ce, int threads,
                       const GpuCtx &gpu, Lists &E, std::vector<uint32_t> &head, std::vector<int32_t> &head_n,
                       double *t_search) {
+    (void)pjoff;
     (void)pjidx;
     int32_t maxdeg = 1;
     for (int64_t x = 0; x < n; ++x) maxdeg = std::max<int32_t>(maxdeg, PJ.deg[x]);
@@ -289,67 +292,100 @@ int enhance_on_device(const float *X, int64_t n, int32_t d, const Lists &PJ, con
     std::vector<uint32_t> adj((size_t)n * ell, kNone);
     for (int64_t x = 0; x < n; ++x)
         for (int j = 0; j < PJ.deg[x]; ++j) adj[x * ell + j] = PJ.row(x)[j].id;
-    (void)pjoff;
-    const int64_t B = std::min<int64_t>(n, 1 << 16);
-    uint32_t *d_adj = nullptr, *d_ids = nullptr;
-    double *d_d = nullptr;
-    int32_t *d_n = nullptr;
+    const int64_t B = std::min<int64_t>(n, 1 << 15);
+    uint32_t *d_adj = nullptr;
+    uint32_t *d_ids[2] = {nullptr, nullptr}, *h_ids[2] = {nullptr, nullptr};
+    double *d_d[2] = {nullptr, nullptr}, *h_d[2] = {nullptr, nullptr};
+    int32_t *d_n[2] = {nullptr, nullptr}, *h_n[2] = {nullptr, nullptr};
+    hipEvent_t ev[2] = {nullptr, nullptr};
     auto release = [&]() {
         if (d_adj) (void)hipFree(d_adj);
-        if (d_ids) (void)hipFree(d_ids);
-        if (d_d) (void)hipFree(d_d);
-        if (d_n) (void)hipFree(d_n);
+        for (int i = 0; i < 2; ++i) {
+            if (d_ids[i]) (void)hipFree(d_ids[i]);
+            if (d_d[i]) (void)hipFree(d_d[i]);
+            if (d_n[i]) (void)hipFree(d_n[i]);
+            if (h_ids[i]) (void)hipHostFree(h_ids[i]);
+            if (h_d[i]) (void)hipHostFree(h_d[i]);
+            if (h_n[i]) (void)hipHostFree(h_n[i]);
+            if (ev[i]) (void)hipEventDestroy(ev[i]);
+        }
     };
-    if (hipMalloc(&d_adj, sizeof(uint32_t) * adj.size()) != hipSuccess ||
-        hipMalloc(&d_ids, sizeof(uint32_t) * B * L) != hipSuccess ||
-        hipMalloc(&d_d, sizeof(double) * B * L) != hipSuccess || hipMalloc(&d_n, sizeof(int32_t) * B) != hipSuccess) {
+    bool ok = hipMalloc(&d_adj, sizeof(uint32_t) * adj.size()) == hipSuccess;
+    for (int i = 0; i < 2 && ok; ++i)
+        ok = hipMalloc(&d_ids[i], sizeof(uint32_t) * B * L) == hipSuccess &&
+             hipMalloc(&d_d[i], sizeof(double) * B * L) == hipSuccess &&
+             hipMalloc(&d_n[i], sizeof(int32_t) * B) == hipSuccess &&
+             hipHostMalloc(&h_ids[i], sizeof(uint32_t) * B * L, hipHostMallocDefault) == hipSuccess &&
+             hipHostMalloc(&h_d[i], sizeof(double) * B * L, hipHostMallocDefault) == hipSuccess &&
+             hipHostMalloc(&h_n[i], sizeof(int32_t) * B, hipHostMallocDefault) == hipSuccess &&
+             hipEventCreateWithFlags(&ev[i], hipEventDisableTiming) == hipSuccess;
+    if (!ok) {
         release();
-        set_error("build: out of device memory for enhancement searches");
+        set_error("build: out of memory for enhancement searches");
         return RG_ENOMEM;
     }
-    std::vector<uint32_t> hid((size_t)B * L);
-    std::vector<double> hd((size_t)B * L);
-    std::vector<int32_t> hn((size_t)B);
     std::vector<std::vector<Cand>> cc((size_t)threads);
     std::vector<std::vector<uint8_t>> kept((size_t)threads);
-    double ts = 0.0;
+    const auto tstart = Clock::now();
+    double t_host = 0.0;
     int rc = RG_OK;
+    // issue the search of batch b into buffer b % 2
+    auto issue = [&](int64_t b) -> int {
+        const int64_t x0 = b * B, cnt = std::min(B, n - x0);
+        const int i = (int)(b & 1);
+        int r = launch_canon_search(gpu.X, d, gpu.pitch, d_adj, ell, entry, L, x0, cnt, d_ids[i], d_d[i], d_n[i],
+                                    gpu.stream);
+        if (r) return r;
+        if (hipMemcpyAsync(h_ids[i], d_ids[i], sizeof(uint32_t) * cnt * L, hipMemcpyDeviceToHost, gpu.stream) !=
+                hipSuccess ||
+            hipMemcpyAsync(h_d[i], d_d[i], sizeof(double) * cnt * L, hipMemcpyDeviceToHost, gpu.stream) !=
+                hipSuccess ||
+            hipMemcpyAsync(h_n[i], d_n[i], sizeof(int32_t) * cnt, hipMemcpyDeviceToHost, gpu.stream) != hipSuccess ||
+            hipEventRecord(ev[i], gpu.stream) != hipSuccess) {
+            set_error("build: enhancement search on the device failed");
+            return RG_EDEVICE;
+        }
+        return RG_OK;
+    };
+    const int64_t nb = (n + B - 1) / B;
     if (hipMemcpyAsync(d_adj, adj.data(), sizeof(uint32_t) * adj.size(), hipMemcpyHostToDevice, gpu.stream) !=
         hipSuccess)
         rc = RG_EDEVICE;
-    for (int64_t x0 = 0; x0 < n && !rc; x0 += B) {
-        const int64_t cnt = std::min(B, n - x0);
-        const auto t0 = Clock::now();
-        rc = launch_canon_search(gpu.X, d, gpu.pitch, d_adj, ell, entry, L, x0, cnt, d_ids, d_d, d_n, gpu.stream);
+    if (!rc) rc = issue(0);
+    for (int64_t b = 0; b < nb && !rc; ++b) {
+        if (b + 1 < nb) rc = issue(b + 1);  // the device works on the next batch meanwhile
         if (rc) break;
-        if (hipMemcpyAsync(hid.data(), d_ids, sizeof(uint32_t) * cnt * L, hipMemcpyDeviceToHost, gpu.stream) !=
-                hipSuccess ||
-            hipMemcpyAsync(hd.data(), d_d, sizeof(double) * cnt * L, hipMemcpyDeviceToHost, gpu.stream) !=
-                hipSuccess ||
-            hipMemcpyAsync(hn.data(), d_n, sizeof(int32_t) * cnt, hipMemcpyDeviceToHost, gpu.stream) != hipSuccess ||
-            hipStreamSynchronize(gpu.stream) != hipSuccess) {
+        const int i = (int)(b & 1);
+        if (hipEventSynchronize(ev[i]) != hipSuccess) {
             set_error("build: enhancement search on the device failed");
             rc = RG_EDEVICE;
             break;
         }
-        ts += secs(t0, Clock::now());
-        parallel_for(cnt, threads, 16, [&](int64_t b, int tid) {
-            const int64_t x = x0 + b;
+        const auto th0 = Clock::now();
+        const int64_t x0 = b * B, cnt = std::min(B, n - x0);
+        const uint32_t *hid = h_ids[i];
+        const double *hd = h_d[i];
+        const int32_t *hn = h_n[i];
+        parallel_for(cnt, threads, 16, [&](int64_t bb, int tid) {
+            const int64_t x = x0 + bb;
             auto &c = cc[tid];
             c.clear();
-            for (int j = 0; j < hn[b]; ++j) {
-                const uint32_t u = hid[b * L + j];
-                if ((int64_t)u != x) c.push_back(Cand{hd[b * L + j], u});
+            for (int j = 0; j < hn[bb]; ++j) {
+                const uint32_t u = hid[bb * L + j];
+                if ((int64_t)u != x) c.push_back(Cand{hd[bb * L + j], u});
             }
             head_n[x] = (int32_t)c.size();
             for (int j = 0; j < kHead && j < (int)c.size(); ++j) head[x * kHead + j] = c[j].id;
             E.deg[x] = acquire_sorted(X, d, c.data(), (int)c.size(), m_ce, false, E.row(x), kept[tid]);
         });
+        t_host += secs(th0, Clock::now());
         if (std::getenv("RG_LOG"))
             std::fprintf(stderr, "[rg] enhancement searches %lld / %lld nodes\n", (long long)(x0 + cnt), (long long)n);
+        // buffer i is reused by batch b + 2, issued in the next iteration
     }
+    (void)hipStreamSynchronize(gpu.stream);
     release();
-    *t_search = ts;
+    *t_search = secs(tstart, Clock::now()) - t_host;
     return rc;
 }
 

@@ -58,7 +58,7 @@ struct SearchArgs {
 int launch_search(const SearchArgs &a, hipStream_t stream);
 int launch_search_persistent(const SearchArgs &a, hipStream_t stream);
 int search_occupancy(const SearchArgs &a, int *blocks_per_cu);
-size_t search_lds_bytes(int Leff, int ell, int hash_bits);
+size_t search_lds_bytes(int Leff, int pitch, int hash_bits);
 int default_hash_bits(int Leff);
 
 // Serving step: same per-query arithmetic as launch_search, resumable.

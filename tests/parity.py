@@ -5,8 +5,8 @@ Tolerance (stated for the search path): every returned distance is within
 no useful relative scale near 0, so the Cauchy-Schwarz bound sets it).
 
 Ids: the GPU computes each distance as FP32 fused multiply-adds along one
-lane (4*NCH terms) followed by a log2(G)-level shuffle tree, so its error is
-at most gamma_m * sum|q_i x_i| <= gamma_m * |q| * |x| with m = 4*NCH +
+lane (EPC*NCH terms) followed by a log2(G)-level shuffle tree, so its error
+is at most gamma_m * sum|q_i x_i| <= gamma_m * |q| * |x| with m = EPC*NCH +
 log2(G) and gamma_m = m u / (1 - m u), u = 2^-24.  The oracle reports, per
 query, the smallest margin of any comparison that decided its search.  When
 that margin exceeds twice the bound, the GPU must take the same decisions:
@@ -19,24 +19,38 @@ import numpy as np
 NONE = 0xFFFFFFFF
 
 
-def kernel_shape(d):
-    """(G, NCH) the search kernel uses for dimension d."""
-    nch = (d + 3) // 4
-    for lim, g, c in ((16, 16, 1), (32, 16, 2), (56, 8, 7), (64, 16, 4), (128, 16, 8), (256, 32, 8)):
-        if nch <= lim:
-            return g, c
+# (G, NCH) per dimension class (d <= 64, 128, 224, 256, 512, 1024) and storage;
+# a chunk holds EPC elements (4 FP32, 8 BF16, 16 E4M3).
+CLASS_MAX_D = (64, 128, 224, 256, 512, 1024)
+SHAPES = {
+    "fp32": (4, ((16, 1), (16, 2), (8, 7), (16, 4), (16, 8), (32, 8))),
+    "bf16": (8, ((8, 1), (16, 1), (8, 4), (8, 4), (16, 4), (32, 4))),
+    "fp8": (16, ((4, 1), (8, 1), (8, 2), (8, 2), (16, 2), (32, 2))),
+}
+
+
+def kernel_shape(d, storage="fp32"):
+    """(G, NCH, EPC) the search kernel uses for dimension d and storage."""
+    epc, table = SHAPES[storage]
+    for lim, gn in zip(CLASS_MAX_D, table):
+        if d <= lim:
+            return gn[0], gn[1], epc
     raise ValueError(d)
 
 
-def gamma_search(d):
-    g, c = kernel_shape(d)
-    m = 4 * c + int(np.log2(g)) + 1
+def gamma_search(d, storage="fp32"):
+    """Error bound factor of the search's FP32 distances; for reduced
+    storage also covers the FP32 rerank."""
     u = 2.0 ** -24
-    return m * u / (1 - m * u)
+    worst = 0
+    for st in {"fp32", storage}:
+        g, c, epc = kernel_shape(d, st)
+        worst = max(worst, epc * c + int(np.log2(g)) + 1)
+    return worst * u / (1 - worst * u)
 
 
 def compare(gpu_ids, gpu_d, or_ids, or_d, gaps, Q, X, tol_rel=1e-5, max_near_tie_frac=1.0,
-            min_agreement=0.99, min_near_same=0.95, label=""):
+            min_agreement=0.99, min_near_same=0.95, label="", storage="fp32"):
     gpu_ids = np.asarray(gpu_ids, np.uint32)
     gpu_d = np.asarray(gpu_d, np.float64)
     Qd = Q.astype(np.float64)
@@ -44,7 +58,7 @@ def compare(gpu_ids, gpu_d, or_ids, or_d, gaps, Q, X, tol_rel=1e-5, max_near_tie
     qn = np.linalg.norm(Qd, axis=1)
     xmax = float(np.linalg.norm(Xd, axis=1).max())
     tol = tol_rel * qn * xmax
-    tau = gamma_search(X.shape[1]) * qn * xmax
+    tau = gamma_search(X.shape[1], storage) * qn * xmax
     nq, k = gpu_ids.shape
     # every returned distance matches the FP64 value of its own pair
     valid = gpu_ids != NONE

@@ -273,7 +273,7 @@ def test_precision_search_parity(dev, oracle_lib, c1, storage):
         torch.cuda.synchronize()
         oi, od, _, _, gaps = oracle_lib.search_rerank(Xq, X, G.offsets, G.indices, G.entry, Q, k, L)
         r = compare(rg.as_u32(ids), ds.cpu().numpy(), oi, od, gaps, Q, X, min_agreement=0.98,
-                    min_near_same=0.9, label=f"{storage} k={k} L={L}")
+                    min_near_same=0.9, label=f"{storage} k={k} L={L}", storage=storage)
         say(f"  {r}")
 
 
