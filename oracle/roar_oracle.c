@@ -24,11 +24,13 @@
  *     with m_pj + m_ce <= M - 1; one slot per node is kept for the
  *     reachability repair.
  *
- * Parity pins live in tests/test_oracle.py.  Construction stages beyond the
- * invariants and hand-worked examples there are "parity unpinned" against
- * the paper itself (its worked examples are figures whose coordinates are not
- * given); they are pinned by agreement with the independent library build.
+ * Parity pins live in tests/test_oracle.py.  Projection and enhancement
+ * beyond the hand-worked five-point build and the invariants checked there
+ * are "parity unpinned" against the paper itself: its worked examples are
+ * figures whose coordinates are not given.
  */
+#define _POSIX_C_SOURCE 200809L
+#include <pthread.h>
 #include <math.h>
 #include <stdint.h>
 #include <stdlib.h>
@@ -427,19 +429,37 @@ double or_e4m3_value(uint8_t c)
     return s ? -v : v;
 }
 
-/* nearest finite code to y (|y| <= 448), ties to the even code */
+/* values of the non-negative finite codes 0..0x7E, filled once from the
+ * definition above; they increase with the code */
+static double e4m3_table[0x7F];
+static pthread_once_t e4m3_once = PTHREAD_ONCE_INIT;
+static void e4m3_fill(void)
+{
+    for (int c = 0; c < 0x7F; ++c)
+        e4m3_table[c] = or_e4m3_value((uint8_t)c);
+}
+
+/* nearest finite code to y (|y| <= 448), ties to the even code.  Because the
+ * table is increasing, the two candidates are the neighbours of |y| in it,
+ * found by bisection. */
 uint8_t or_e4m3_encode(double y)
 {
+    pthread_once(&e4m3_once, e4m3_fill);
     double a = fabs(y);
-    int best = 0;
-    double bd = INFINITY;
-    for (int c = 0; c <= 0x7E; ++c) {
-        double dv = fabs(or_e4m3_value((uint8_t)c) - a);
-        if (dv < bd || (dv == bd && (c & 1) == 0 && (best & 1) == 1)) {
-            bd = dv;
-            best = c;
+    int lo = 0, hi = 0x7E; /* invariant: table[lo] <= a < table[hi] */
+    if (a >= e4m3_table[0x7E]) {
+        lo = hi = 0x7E;
+    } else {
+        while (hi - lo > 1) {
+            int mid = (lo + hi) / 2;
+            if (e4m3_table[mid] <= a)
+                lo = mid;
+            else
+                hi = mid;
         }
     }
+    double dl = a - e4m3_table[lo], dh = e4m3_table[hi] - a;
+    int best = dl < dh ? lo : (dh < dl ? hi : ((lo & 1) == 0 ? lo : hi));
     return (uint8_t)(y < 0 || (y == 0 && signbit(y)) ? (best | 0x80) : best);
 }
 
@@ -447,6 +467,8 @@ uint8_t or_e4m3_encode(double y)
  * (s = 1 for an all-zero row).  codes[i] = e4m3(x_i / s); deq[i] = s * value. */
 void or_quant_fp8(const float *X, int64_t n, int32_t d, uint8_t *codes, float *scales, float *deq)
 {
+    pthread_once(&e4m3_once, e4m3_fill);
+#pragma omp parallel for schedule(static)
     for (int64_t r = 0; r < n; ++r) {
         const float *x = X + r * d;
         double amax = 0.0;
@@ -464,7 +486,7 @@ void or_quant_fp8(const float *X, int64_t n, int32_t d, uint8_t *codes, float *s
         for (int32_t i = 0; i < d; ++i) {
             uint8_t c = or_e4m3_encode((double)x[i] / s);
             codes[r * d + i] = c;
-            deq[r * d + i] = (float)(s * or_e4m3_value(c));
+            deq[r * d + i] = (float)(s * (c & 0x80 ? -e4m3_table[c & 0x7F] : e4m3_table[c]));
         }
     }
 }
