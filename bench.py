@@ -87,36 +87,64 @@ def algorithmic_bytes(rg, torch, ix, Q, k, L, d, bytes_per_row, avg_deg):
     return float(per_q.sum()), float(V.mean()), float(H.mean())
 
 
-def serve_latency(rg, ix, Qh, n_req, rate, seed=0):
+def serve_run(rg, ix, Qh, n_req, rate, seed=0, timeout=120.0):
+    """Requests with k in {1, 10, 100} and L in {32, 128, 512} (uniform),
+    arriving as a Poisson process of the given rate (None: all at once);
+    latency = completion poll time - arrival time on the server's clock."""
     rng = np.random.default_rng(seed)
-    ks = rng.choice([1, 10, 100], n_req)
-    Ls = rng.choice([32, 128, 512], n_req)
-    gaps = rng.exponential(1.0 / rate, n_req)
+    ks = rng.choice([1, 10, 100], n_req).astype(np.int32)
+    Ls = rng.choice([32, 128, 512], n_req).astype(np.int32)
+    arrive = np.cumsum(rng.exponential(1.0 / rate, n_req)) if rate else np.zeros(n_req)
     srv = rg.Server(ix, max_slots=4096, hops_per_step=32)
     done = {}
-    t_next = time.perf_counter()
     i = 0
-    t_start = time.perf_counter()
+    t0 = srv.now()
     while len(done) < n_req:
-        now = time.perf_counter()
-        while i < n_req and now >= t_next:
-            if srv.submit(Qh[i % len(Qh)], int(ks[i]), int(Ls[i]), i) == rg.RG_OK:
-                t_next += gaps[i]
-                i += 1
-            else:
-                break
+        now = srv.now() - t0
+        j = int(np.searchsorted(arrive, now, side="right"))
+        if j > i:
+            idx = np.arange(i, j)
+            i += srv.submit_batch(Qh[idx % len(Qh)], ks[idx], Ls[idx], idx)
         for r in srv.poll():
             done[r["tag"]] = r
-        if time.perf_counter() - t_start > 120:
+        if srv.now() - t0 > timeout:
             break
         time.sleep(0.0002)
-    wall = time.perf_counter() - t_start
+    wall = srv.now() - t0
     st = srv.stats()
     srv.close()
     lat = np.array([r["t_done"] - r["t_submit"] for r in done.values()])
     return {"requests": len(done), "offered_qps": rate, "achieved_qps": len(done) / wall,
             "p50_ms": float(np.percentile(lat, 50) * 1e3), "p99_ms": float(np.percentile(lat, 99) * 1e3),
-            "steps": st["steps"], "k_mix": [1, 10, 100], "L_mix": [32, 128, 512]}
+            "steps": st["steps"]}
+
+
+def serve_latency(rg, ix, Qh, n_req=20000):
+    """Closed-loop capacity, then Poisson arrivals at 0.5, 0.8, 0.95 of it."""
+    cap = serve_run(rg, ix, Qh, n_req, None, seed=1)
+    lam = cap["achieved_qps"]
+    out = {"k_mix": [1, 10, 100], "L_mix": [32, 128, 512], "capacity_qps": lam, "rates": []}
+    for f in (0.5, 0.8, 0.95):
+        r = serve_run(rg, ix, Qh, n_req, f * lam, seed=2)
+        r["load"] = f
+        out["rates"].append(r)
+        log(f"  load {f:.2f}: {r}")
+    return out
+
+
+def graph_checks(off, idx, entry, M):
+    """Invariants of the built index, checked in full: out-degree <= M, no
+    self loops or duplicate edges, every node reachable from the entry."""
+    from scipy.sparse import csr_matrix
+    from scipy.sparse.csgraph import breadth_first_order
+    n = len(off) - 1
+    deg = np.diff(off)
+    rows = np.repeat(np.arange(n, dtype=np.int64), deg)
+    dup = bool((np.diff(idx.astype(np.int64)) == 0)[np.diff(rows) == 0].any()) if len(idx) > 1 else False
+    g = csr_matrix((np.ones(len(idx), np.int8), idx.astype(np.int64), off), shape=(n, n))
+    reached = breadth_first_order(g, entry, directed=True, return_predecessors=False)
+    return {"max_degree": int(deg.max()), "bound_M": int(M), "self_loops": int((idx.astype(np.int64) == rows).sum()),
+            "duplicate_edges": dup, "reachable": int(len(reached)), "n": int(n)}
 
 
 def search_sources_sha() -> str:
@@ -205,6 +233,8 @@ def main():
     off, idx, entry = ix.graph()
     avg_deg = float(np.diff(off).mean())
     info = ix.info()
+    bstats["checks"] = graph_checks(off, idx, entry, w.M)
+    log(f"graph checks: {bstats['checks']}")
     t = time.time()
     gt_ids, _ = rg.rg_knn(Q, X, 10)
     gt = rg.as_u32(gt_ids)
@@ -254,10 +284,9 @@ def main():
 
     serving = None
     if not args.no_serve:
-        rate = 0.5 * min(qps, 200000.0)
-        log(f"serving: Poisson arrivals at {rate:.0f} req/s, k in {{1,10,100}}, L in {{32,128,512}}")
-        serving = serve_latency(rg, ix, Qh, 20000, rate)
-        log(f"serving: {serving}")
+        log("serving: closed-loop capacity, then Poisson arrivals at 0.5/0.8/0.95 of it")
+        serving = serve_latency(rg, ix, Qh)
+        log(f"serving: capacity {serving['capacity_qps']:.0f} req/s")
 
     cpu = None
     if not args.no_cpu_baseline:

@@ -257,6 +257,13 @@ int rg_server_create(const rg_index *idx, const rg_server_limits *lim, rg_server
  * Returns RG_EAGAIN when the pending queue is full.  Errors: RG_EINVAL. */
 int rg_server_submit(rg_server *s, const float *query_host, int32_t k, int32_t L, uint64_t tag);
 
+/* rg_server_submit_batch -- queue n requests at once (query i is
+ * queries_host[i*d .. i*d+d), with k[i], L[i], tags[i]); all get the same
+ * submit time.  *n_accepted = how many were queued (in order); RG_EAGAIN
+ * when the pending queue filled before all n.  Errors: RG_EINVAL. */
+int rg_server_submit_batch(rg_server *s, const float *queries_host, const int32_t *k, const int32_t *L,
+                           const uint64_t *tags, int32_t n, int32_t *n_accepted);
+
 /* rg_server_poll -- move up to max finished results into out; *n_out gets
  * the number written.  Never blocks. */
 int rg_server_poll(rg_server *s, rg_result *out, int32_t max, int32_t *n_out);

@@ -13,7 +13,7 @@ import os
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libroargraph.so")
+LIB_PATH = os.environ.get("RG_LIB", os.path.join(_HERE, "libroargraph.so"))
 
 RG_OK, RG_EINVAL, RG_ENOMEM, RG_EDEVICE, RG_EAGAIN, RG_ECORRUPT, RG_EINTERNAL = 0, -1, -2, -3, -4, -5, -6
 RG_METRIC_IP = 0
@@ -70,6 +70,7 @@ _SIGS = {
     "rg_server_create": (i32, [P, ctypes.POINTER(rg_server_limits), PP]),
     "rg_server_submit": (i32, [P, P, i32, i32, ctypes.c_uint64]),
     "rg_server_poll": (i32, [P, ctypes.POINTER(rg_result), i32, ctypes.POINTER(i32)]),
+    "rg_server_submit_batch": (i32, [P, P, P, P, P, i32, ctypes.POINTER(i32)]),
     "rg_server_stats": (i32, [P] + [ctypes.POINTER(ctypes.c_uint64)] * 4),
     "rg_server_now": (ctypes.c_double, [P]),
     "rg_server_slots": (i32, [P]),
@@ -279,7 +280,7 @@ class Server:
         h = ctypes.c_void_p()
         _check(lib().rg_server_create(index.h, ctypes.byref(lim), ctypes.byref(h)))
         self.h = h
-        self._buf = (rg_result * 256)()
+        self._buf = (rg_result * 1024)()
 
     def submit(self, q: np.ndarray, k: int, L: int, tag: int) -> int:
         q = np.ascontiguousarray(q, dtype=np.float32)
@@ -287,6 +288,19 @@ class Server:
         if rc not in (RG_OK, RG_EAGAIN):
             _check(rc)
         return rc
+
+    def submit_batch(self, Q: np.ndarray, k, L, tags) -> int:
+        """Queue len(Q) requests; returns how many were accepted."""
+        Q = np.ascontiguousarray(Q, dtype=np.float32)
+        k = np.ascontiguousarray(k, dtype=np.int32)
+        L = np.ascontiguousarray(L, dtype=np.int32)
+        t = np.ascontiguousarray(tags, dtype=np.uint64)
+        acc = i32()
+        rc = lib().rg_server_submit_batch(self.h, Q.ctypes.data_as(P), k.ctypes.data_as(P), L.ctypes.data_as(P),
+                                          t.ctypes.data_as(P), len(Q), ctypes.byref(acc))
+        if rc not in (RG_OK, RG_EAGAIN):
+            _check(rc)
+        return acc.value
 
     def poll(self):
         n = i32()

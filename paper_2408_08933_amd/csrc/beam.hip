@@ -91,7 +91,7 @@ constexpr int shape_nch(int st, int cls) {
     constexpr int n32[6] = {1, 2, 7, 4, 8, 8}, n16[6] = {1, 1, 4, 4, 4, 4}, n8[6] = {1, 1, 2, 2, 2, 2};
     return st == RG_STORE_FP32 ? n32[cls] : st == RG_STORE_BF16 ? n16[cls] : n8[cls];
 }
-constexpr int shape_r(int st) { return st == RG_STORE_FP32 ? 2 : st == RG_STORE_BF16 ? 3 : 6; }
+constexpr int shape_r(int st) { return st == RG_STORE_FP32 ? 2 : st == RG_STORE_BF16 ? 2 : 4; }
 
 // Copy the query into LDS, zero padded to the row pitch.
 __device__ __forceinline__ void load_query(const float *q, int d, int pitch, float *qs) {
@@ -299,10 +299,13 @@ __device__ __forceinline__ void run_search(const SearchArgs &a, const Lds &s, VI
         if (lane == 0) s.qi[sel] = v | kExpanded;
         ++hops;
         vis.begin_hop(ell);
+        const uint32_t r0 = lane < ell ? a.adj[(size_t)v * ell + lane] : kNone;
+        const uint32_t r1 = (ell > 64 && lane + 64 < ell) ? a.adj[(size_t)v * ell + lane + 64] : kNone;
         int nnew = 0;
-        for (int b = 0; b < ell; b += 64) {
-            const int e = b + lane;
-            const uint32_t u = e < ell ? a.adj[(size_t)v * ell + e] : kNone;
+#pragma unroll
+        for (int half = 0; half < 2; ++half) {
+            if (half == 1 && ell <= 64) break;
+            const uint32_t u = half == 0 ? r0 : r1;
             const bool fresh = u != kNone && vis.insert(u);
             const uint64_t m = ballot64(fresh);
             if (fresh) s.ci[nnew + lanes_below(m)] = u;
@@ -410,8 +413,10 @@ __global__ __launch_bounds__(64) void k_search(SearchArgs a) {
 // device counter until none are left, and keeps an exact visited bitmap
 // (one bit per base node) in device memory, so LDS holds only the queue and
 // the candidate batch and many more queries are in flight per CU.
+// Four resident wavefronts per SIMD (<= 128 VGPRs) measured fastest for all
+// storage forms, ahead of fewer waves with more registers.
 template <int ST, int CLS>
-__global__ __launch_bounds__(64) void k_search_persistent(SearchArgs a) {
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void k_search_persistent(SearchArgs a) {
     extern __shared__ __align__(16) unsigned char smem[];
     const Lds s = carve(smem, a.Leff, a.pitch);
     VisitBitmap vis{a.bitmap + (size_t)blockIdx.x * a.bm_words, a.bm_words};

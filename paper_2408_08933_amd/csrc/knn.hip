@@ -91,7 +91,7 @@ __device__ __forceinline__ int compact_row(float *bsc, uint32_t *bid, int c, int
     return c < K ? c : K;
 }
 
-__global__ __launch_bounds__(256) void k_knn(KnnArgs a) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k_knn(KnnArgs a) {
     __shared__ float As[KC][LDS_LD];
     __shared__ float Bs[KC][LDS_LD];
     __shared__ float thr[BQ];
@@ -113,20 +113,26 @@ __global__ __launch_bounds__(256) void k_knn(KnnArgs a) {
     const int64_t xt0 = (int64_t)sp * a.xtiles_per_split;
     const int64_t xt1 = min(a.xtiles, xt0 + a.xtiles_per_split);
     const int lr = tid >> 3, lk = (tid & 7) * 4;
+    // the next coordinate slice of the tile is loaded into registers while
+    // the current one feeds the MFMAs
+    float4 va[4], vb[4];
+    auto load_slice = [&](int64_t xt, int k0) {
+        const int64_t x0 = xt * BX;
+#pragma unroll
+        for (int p = 0; p < 4; ++p) {
+            va[p] = ld4(a.Q, a.nq, a.ldq, a.d, q0 + p * 32 + lr, k0 + lk, vq);
+            vb[p] = ld4(a.X, a.n, a.ldx, a.d, x0 + p * 32 + lr, k0 + lk, vx);
+        }
+    };
     for (int64_t xt = xt0; xt < xt1; ++xt) {
         const int64_t x0 = xt * BX;
+        load_slice(xt, 0);
         fx4 acc[4][4];
 #pragma unroll
         for (int i = 0; i < 4; ++i)
 #pragma unroll
             for (int j = 0; j < 4; ++j) acc[i][j] = fx4{0.f, 0.f, 0.f, 0.f};
         for (int k0 = 0; k0 < a.d; k0 += KC) {
-            float4 va[4], vb[4];
-#pragma unroll
-            for (int p = 0; p < 4; ++p) {
-                va[p] = ld4(a.Q, a.nq, a.ldq, a.d, q0 + p * 32 + lr, k0 + lk, vq);
-                vb[p] = ld4(a.X, a.n, a.ldx, a.d, x0 + p * 32 + lr, k0 + lk, vx);
-            }
             __syncthreads();
 #pragma unroll
             for (int p = 0; p < 4; ++p) {
@@ -141,6 +147,7 @@ __global__ __launch_bounds__(256) void k_knn(KnnArgs a) {
                 Bs[lk + 3][r] = vb[p].w;
             }
             __syncthreads();
+            if (k0 + KC < a.d) load_slice(xt, k0 + KC);
 #pragma unroll
             for (int ks = 0; ks < KC / 4; ++ks) {
                 const int kk = ks * 4 + (lane >> 4);

@@ -55,6 +55,13 @@ __device__ __forceinline__ int count_le(const int32_t *slb, int S, int i) {
 template <int E, typename K>
 __device__ __forceinline__ void merge_batch(const QueueLds<K> &s, int cnt, int Leff, int &qn, int &ptr) {
     const int lane = lane_id();
+    if (qn == Leff) {  // full queue: nothing to do unless some candidate beats the last entry
+        const K ld = s.qd[Leff - 1];
+        const uint32_t li = s.qi[Leff - 1] & ~kExpanded;
+        bool any = false;
+        for (int i = lane; i < cnt; i += 64) any |= kless(s.cd[i], s.ci[i], ld, li);
+        if (ballot64(any) == 0) return;
+    }
     K k[E];
     uint32_t id[E];
 #pragma unroll

@@ -287,6 +287,38 @@ int rg_server_submit(rg_server *s, const float *q, int32_t k, int32_t L, uint64_
     return RG_OK;
 }
 
+int rg_server_submit_batch(rg_server *s, const float *queries_host, const int32_t *k, const int32_t *L,
+                           const uint64_t *tags, int32_t n, int32_t *n_accepted) {
+    if (!s || !n_accepted || n < 0 || (n > 0 && (!queries_host || !k || !L || !tags))) {
+        set_error("rg_server_submit_batch: invalid argument");
+        return RG_EINVAL;
+    }
+    *n_accepted = 0;
+    for (int32_t i = 0; i < n; ++i)
+        if (k[i] < 1 || L[i] < 1 || k[i] > kMaxL || std::max(k[i], L[i]) > s->lim.max_L) {
+            set_error("rg_server_submit_batch: invalid k or L");
+            return RG_EINVAL;
+        }
+    const int d = s->ix->d;
+    const double t = s->now();
+    int32_t acc = 0;
+    {
+        std::lock_guard<std::mutex> lk(s->mu);
+        if (s->err) {
+            set_error("rg_server_submit_batch: server stopped after a device error");
+            return s->err;
+        }
+        for (int32_t i = 0; i < n && s->pending.size() < kMaxPending; ++i, ++acc) {
+            s->pending.push_back(Pending{std::vector<float>(queries_host + (size_t)i * d, queries_host + (size_t)(i + 1) * d),
+                                         k[i], L[i], tags[i], t});
+            ++s->n_sub;
+        }
+    }
+    s->cv.notify_one();
+    *n_accepted = acc;
+    return acc < n ? RG_EAGAIN : RG_OK;
+}
+
 int rg_server_poll(rg_server *s, rg_result *out, int32_t max, int32_t *n_out) {
     if (!s || !n_out || (max > 0 && !out)) {
         set_error("rg_server_poll: invalid argument");
