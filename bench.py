@@ -42,18 +42,33 @@ def recall_at(ids: np.ndarray, gt: np.ndarray, k: int) -> float:
 
 
 def sweep(rg, torch, ix, Q, gt, k, grid, target):
-    curve = []
-    op = None
-    for L in grid:
+    """Recall over the L grid up to the first L that reaches the target, then
+    bisection over the integers between that L and the grid point before it:
+    the operating point is the smallest measured L whose recall reaches the
+    target."""
+    curve = {}
+
+    def run(L):
         ids, _ = rg.rg_search(ix, Q, k, L)
         torch.cuda.synchronize()
-        r = recall_at(rg.as_u32(ids), gt, k)
-        curve.append((L, r))
-        log(f"  L={L:4d} recall@{k}={r:.4f}")
-        if r >= target and op is None:
+        curve[L] = recall_at(rg.as_u32(ids), gt, k)
+        log(f"  L={L:4d} recall@{k}={curve[L]:.4f}")
+        return curve[L] >= target
+
+    lo, op = None, None
+    for L in grid:
+        if run(L):
             op = L
             break
-    return op, curve
+        lo = L
+    if op is not None and lo is not None:
+        while op - lo > 1:
+            mid = (lo + op) // 2
+            if run(mid):
+                op = mid
+            else:
+                lo = mid
+    return op, sorted(curve.items())
 
 
 def time_search(rg, torch, ix, Q, k, L, steps, warmup):
@@ -87,10 +102,11 @@ def algorithmic_bytes(rg, torch, ix, Q, k, L, d, bytes_per_row, avg_deg):
     return float(per_q.sum()), float(V.mean()), float(H.mean())
 
 
-def serve_run(rg, ix, Qh, n_req, rate, seed=0, timeout=120.0):
+def serve_run(rg, ix, Qh, gt, n_req, rate, seed=0, timeout=120.0):
     """Requests with k in {1, 10, 100} and L in {32, 128, 512} (uniform),
     arriving as a Poisson process of the given rate (None: all at once);
-    latency = completion poll time - arrival time on the server's clock."""
+    latency = completion poll time - arrival time on the server's clock.
+    Recall@k of each result against the exact top-k of its query."""
     rng = np.random.default_rng(seed)
     ks = rng.choice([1, 10, 100], n_req).astype(np.int32)
     Ls = rng.choice([32, 128, 512], n_req).astype(np.int32)
@@ -114,21 +130,66 @@ def serve_run(rg, ix, Qh, n_req, rate, seed=0, timeout=120.0):
     st = srv.stats()
     srv.close()
     lat = np.array([r["t_done"] - r["t_submit"] for r in done.values()])
+    hit = tot = 0
+    for tag, r in done.items():
+        kk = int(ks[tag])
+        hit += len(np.intersect1d(r["ids"][:kk], gt[tag % len(Qh), :kk]))
+        tot += kk
     return {"requests": len(done), "offered_qps": rate, "achieved_qps": len(done) / wall,
             "p50_ms": float(np.percentile(lat, 50) * 1e3), "p99_ms": float(np.percentile(lat, 99) * 1e3),
-            "steps": st["steps"]}
+            "recall": hit / max(tot, 1), "steps": st["steps"]}
 
 
-def serve_latency(rg, ix, Qh, n_req=20000):
+def serve_latency(rg, ix, Qh, gt, n_req=20000):
     """Closed-loop capacity, then Poisson arrivals at 0.5, 0.8, 0.95 of it."""
-    cap = serve_run(rg, ix, Qh, n_req, None, seed=1)
+    cap = serve_run(rg, ix, Qh, gt, n_req, None, seed=1)
     lam = cap["achieved_qps"]
-    out = {"k_mix": [1, 10, 100], "L_mix": [32, 128, 512], "capacity_qps": lam, "rates": []}
+    out = {"k_mix": [1, 10, 100], "L_mix": [32, 128, 512], "capacity_qps": lam, "capacity_recall": cap["recall"],
+           "rates": []}
     for f in (0.5, 0.8, 0.95):
-        r = serve_run(rg, ix, Qh, n_req, f * lam, seed=2)
+        r = serve_run(rg, ix, Qh, gt, n_req, f * lam, seed=2)
         r["load"] = f
         out["rates"].append(r)
         log(f"  load {f:.2f}: {r}")
+    return out
+
+
+def storage_rows(rg, ix, st, n, d, pitch):
+    """The device's reduced-precision rows, decoded to FP32 on the host
+    (BF16: exact widening; FP8: code value times the row scale)."""
+    import ctypes
+    import torch
+    hip = ctypes.CDLL("libamdhip64.so")
+    pb, pf, ps, p8 = ix.storage_ptrs()
+    if st == rg.RG_STORE_BF16:
+        h = np.empty((n, pitch), np.uint16)
+        assert hip.hipMemcpy(ctypes.c_void_p(h.ctypes.data), ctypes.c_void_p(pb), ctypes.c_size_t(h.nbytes), 2) == 0
+        return torch.from_numpy(h[:, :d].copy()).view(torch.bfloat16).float().numpy()
+    h = np.empty((n, p8), np.uint8)
+    sc = np.empty(n, np.float32)
+    assert hip.hipMemcpy(ctypes.c_void_p(h.ctypes.data), ctypes.c_void_p(pf), ctypes.c_size_t(h.nbytes), 2) == 0
+    assert hip.hipMemcpy(ctypes.c_void_p(sc.ctypes.data), ctypes.c_void_p(ps), ctypes.c_size_t(sc.nbytes), 2) == 0
+    v = torch.from_numpy(h[:, :d].copy()).view(torch.float8_e4m3fn).float().numpy()
+    return v * sc[:, None]
+
+
+def distance_errors(Xh, Qh, ids, ds, rows=None, nq=1000, n_rand=100, seed=3):
+    """Errors against FP64, in units of |q| * max|x|: the returned distances
+    (after the FP32 rerank for reduced storage) and, for reduced storage, the
+    search-phase score on the stored rows for sampled (query, row) pairs."""
+    xmax = float(np.sqrt((Xh.astype(np.float64) ** 2).sum(1)).max())
+    Q64 = Qh[:nq].astype(np.float64)
+    scale = np.linalg.norm(Q64, axis=1) * xmax
+    a = ids[:nq].astype(np.int64)
+    exact = -np.einsum("qkd,qd->qk", Xh[a].astype(np.float64), Q64)
+    out = {"returned_max": float((np.abs(ds[:nq].astype(np.float64) - exact) / scale[:, None]).max())}
+    if rows is not None:
+        rng = np.random.default_rng(seed)
+        pick = np.concatenate([a, rng.integers(0, Xh.shape[0], (nq, n_rand))], axis=1)
+        e64 = -np.einsum("qkd,qd->qk", Xh[pick].astype(np.float64), Q64)
+        eq = -np.einsum("qkd,qd->qk", rows[pick].astype(np.float64), Q64)
+        rel = np.abs(eq - e64) / scale[:, None]
+        out.update({"score_max": float(rel.max()), "score_mean": float(rel.mean())})
     return out
 
 
@@ -236,9 +297,10 @@ def main():
     bstats["checks"] = graph_checks(off, idx, entry, w.M)
     log(f"graph checks: {bstats['checks']}")
     t = time.time()
-    gt_ids, _ = rg.rg_knn(Q, X, 10)
-    gt = rg.as_u32(gt_ids)
-    log(f"ground truth (exact kNN, k=10) in {time.time() - t:.1f} s")
+    gt_ids, _ = rg.rg_knn(Q, X, 100)
+    gt100 = rg.as_u32(gt_ids)
+    gt = gt100[:, :10]
+    log(f"ground truth (exact kNN, k=100) in {time.time() - t:.1f} s")
 
     if args.copy_probe:
         src = torch.empty(1 << 28, dtype=torch.float32, device=dev)
@@ -265,6 +327,17 @@ def main():
     log(f"FP32 L={L} recall={rec:.4f} QPS={qps:.0f} launch={ms_launch:.3f} ms visits={Vm:.0f} hops={Hm:.0f} "
         f"algorithmic {achieved:.0f} GB/s")
 
+    ids_fp32, ds_fp32 = rg.rg_search(ix, Q, k, L)
+    torch.cuda.synchronize()
+    err_fp32 = distance_errors(Xh, Qh, rg.as_u32(ids_fp32), ds_fp32.cpu().numpy())
+    log(f"FP32 distance error vs FP64: {err_fp32}")
+
+    serving = {}
+    if not args.no_serve:
+        log("serving FP32: closed-loop capacity, then Poisson arrivals at 0.5/0.8/0.95 of it")
+        serving["fp32"] = serve_latency(rg, ix, Qh, gt100)
+        log(f"serving fp32: capacity {serving['fp32']['capacity_qps']:.0f} req/s")
+
     precision = {}
     if not args.no_precision:
         for name, st, bpr in (("bf16", rg.RG_STORE_BF16, 2.0 * w.d), ("fp8", rg.RG_STORE_FP8E4M3, w.d + 4.0)):
@@ -276,17 +349,20 @@ def main():
             wp, lm = time_search(rg, torch, ix, Q, k, Lp, args.steps, args.warmup)
             b, vm, hm = algorithmic_bytes(rg, torch, ix, Q, k, Lp, w.d, bpr, avg_deg)
             b += nq * max(Lp, k) * 4.0 * w.d   # the FP32 rerank of the final queue
+            ids_p, ds_p = rg.rg_search(ix, Q, k, Lp)
+            torch.cuda.synchronize()
+            err = distance_errors(Xh, Qh, rg.as_u32(ids_p), ds_p.cpu().numpy(),
+                                  rows=storage_rows(rg, ix, st, n, w.d, info["pitch"]))
             precision[name] = {"L": Lp, "recall_at_10": dict(cp)[Lp], "qps": nq * args.steps / wp,
                                "ms_per_launch": float(np.mean(lm)),
-                               "algorithmic_GBps": b / (np.mean(lm) * 1e-3) / 1e9}
+                               "algorithmic_GBps": b / (np.mean(lm) * 1e-3) / 1e9,
+                               "qps_vs_fp32": nq * args.steps / wp / qps, "dist_err_vs_fp64": err}
             log(f"{name}: {precision[name]}")
+            if not args.no_serve:
+                log(f"serving {name}")
+                serving[name] = serve_latency(rg, ix, Qh, gt100)
+                log(f"serving {name}: capacity {serving[name]['capacity_qps']:.0f} req/s")
         rg.rg_index_set_storage(ix, rg.RG_STORE_FP32)
-
-    serving = None
-    if not args.no_serve:
-        log("serving: closed-loop capacity, then Poisson arrivals at 0.5/0.8/0.95 of it")
-        serving = serve_latency(rg, ix, Qh)
-        log(f"serving: capacity {serving['capacity_qps']:.0f} req/s")
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -317,9 +393,10 @@ def main():
                      "kernel": "k_search_persistent<8,7,0> (FP32 beam search, d=200)",
                      "bytes_per_launch": bytes_total, "mean_visits": Vm, "mean_hops": Hm,
                      "avg_degree": avg_deg, "ms_per_launch": ms_launch},
+        "dist_err_vs_fp64": err_fp32,
         "cpu_baseline": cpu,
         "precision": precision,
-        "serving": serving,
+        "serving": serving or None,
         "build": bstats,
         "index": info,
     }
