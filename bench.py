@@ -250,6 +250,76 @@ def cpu_baseline(X, off, idx, entry, Qh, k, L, seconds):
                       f"FP64 oracle search, OpenMP over queries ({threads} threads), {t:.1f} s"}
 
 
+ABL_GRID = [10, 20, 40, 60, 100, 150, 200, 300, 400, 500]
+
+
+def qps_recall_curve(rg, torch, ix, Q, gt, k=10, grid=ABL_GRID, steps=3):
+    """Recall@k, QPS (mean of `steps` timed launches) and mean visits/hops per L."""
+    out = []
+    for L in grid:
+        ids, _, hops, ev = rg.rg_search(ix, Q, k, L, stats=True)
+        torch.cuda.synchronize()
+        r = recall_at(rg.as_u32(ids), gt, k)
+        wall, _ = time_search(rg, torch, ix, Q, k, L, steps, 1)
+        out.append({"L": L, "recall": r, "qps": Q.shape[0] * steps / wall,
+                    "visits": float(ev.float().mean()), "hops": float(hops.float().mean())})
+        log(f"  L={L:4d} recall@{k}={r:.4f} qps={out[-1]['qps']:.0f} visits={out[-1]['visits']:.0f}")
+    return out
+
+
+def at_recall(curve, target=0.90):
+    """First point of a curve whose recall reaches the target (None if none)."""
+    for c in curve:
+        if c["recall"] >= target:
+            return c
+    return None
+
+
+def ablation(rg, torch, dev, n):
+    """The paper's ablation (Sec. 5.4) and training-set-size study (Sec. 5.5)
+    on the text-to-image-like workload with the same kernels: QPS-recall of
+    greedy routing on G_bi, of G_pj and of the final index; builds from
+    |T| = p |X| for p in {0.1, 0.5, 1}; in-distribution queries (Sec. 5.6)."""
+    import datagen
+    w = datagen.WORKLOADS[2]
+    g = datagen.Generator(2, n=n, n_train=n, n_test=w.n_test)
+    Xh, Th, Qh = g.base(), g.train(), g.test()
+    X, Q = torch.from_numpy(Xh).to(dev), torch.from_numpy(Qh).to(dev)
+    gt = rg.as_u32(rg.rg_knn(Q, X, 10)[0])
+    out = {"workload": w.name, "n_base": n, "d": w.d, "Nq": w.Nq, "M": w.M, "L_build": 500, "k": 10, "graphs": {},
+           "train_fraction": {}}
+    for p in (1.0, 0.5, 0.1):
+        nt = int(round(p * n))
+        log(f"ablation: build with |T| = {p} |X| ({nt} training queries)")
+        Tr = torch.from_numpy(np.ascontiguousarray(Th[:nt])).to(dev)
+        t = time.time()
+        ix = rg.rg_build(X, Tr, w.Nq, w.M, L_build=500, keep_stages=(p == 1.0))
+        torch.cuda.synchronize()
+        bt = time.time() - t
+        del Tr
+        log(f"  built in {bt:.1f} s; RoarGraph curve")
+        curve = qps_recall_curve(rg, torch, ix, Q, gt)
+        out["train_fraction"][str(p)] = {"n_train": nt, "build_s": bt, "build": ix.build_stats(), "curve": curve,
+                                         "at_0.90": at_recall(curve)}
+        if p == 1.0:
+            out["graphs"]["roargraph"] = {"curve": curve, "at_0.90": at_recall(curve)}
+            for name, stage in (("projected", rg.RG_STAGE_PROJECTED), ("bipartite", rg.RG_STAGE_BIPARTITE)):
+                off, idx, entry = ix.stage_graph(stage)
+                gi = rg.rg_index_from_csr(X, off, idx, entry)
+                log(f"  {name} graph: max degree {int(np.diff(off).max())}, mean {float(np.diff(off).mean()):.1f}")
+                c = qps_recall_curve(rg, torch, gi, Q, gt)
+                out["graphs"][name] = {"curve": c, "at_0.90": at_recall(c),
+                                       "mean_degree": float(np.diff(off).mean()), "max_degree": int(np.diff(off).max())}
+                del gi
+            log("  in-distribution queries on the final index")
+            Qid = torch.from_numpy(g.in_distribution(w.n_test)).to(dev)
+            gid = rg.as_u32(rg.rg_knn(Qid, X, 10)[0])
+            c = qps_recall_curve(rg, torch, ix, Qid, gid)
+            out["in_distribution"] = {"curve": c, "at_0.90": at_recall(c)}
+        del ix
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -261,6 +331,8 @@ def main():
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--n", type=int, default=None, help="override base/training size (not the headline)")
     ap.add_argument("--copy-probe", action="store_true", help="run a 1 GiB plain copy kernel (traffic calibration)")
+    ap.add_argument("--ablation", action="store_true",
+                    help="instead of the benchmark: G_bi / G_pj / RoarGraph, |T| = 0.1/0.5/1 |X|, ID queries")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: this build runs on exactly one GPU; --gpus N > 1 is not supported", file=sys.stderr)
@@ -274,6 +346,9 @@ def main():
     rg.lib()
     dev = torch.device("cuda:0")
     w = datagen.WORKLOADS[2]
+    if args.ablation:
+        print(json.dumps({"ablation": ablation(rg, torch, dev, args.n or w.n)}), flush=True)
+        return
     n = args.n or w.n
     g = datagen.Generator(2, n=n, n_train=n, n_test=w.n_test)
     log(f"workload {w.name}: n={n} d={w.d} train={n} test={w.n_test} Nq={w.Nq} M={w.M}")

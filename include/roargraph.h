@@ -68,7 +68,13 @@ typedef struct {
     int32_t threads;   /* host threads for construction; 0 => all hardware threads */
     int32_t knn_slack; /* extra GPU kNN candidates per training query before the exact
                           rerank; 0 => max(16, Nq/4) */
+    int32_t keep_stages; /* nonzero: keep the bipartite and projected graphs on the host
+                            (rg_index_stage_graph, rg_index_bipartite) */
 } rg_build_opts;
+
+/* Graphs the construction passes through (Algorithm 1; the ablation of
+ * Sec. 5.4 searches both). */
+enum { RG_STAGE_PROJECTED = 1, RG_STAGE_BIPARTITE = 2 };
 
 /*
  * rg_build -- build the index (Algorithm 1).
@@ -113,7 +119,9 @@ int rg_build_from_knn(const float *base_host, int64_t n, int32_t d, const uint32
  *   offsets host, n+1 int64, offsets[0] = 0, non-decreasing.
  *   indices host, offsets[n] uint32 ids < n (copied).
  *   entry   start node of every search (< n).
- * Out-degree must be <= 128.  Errors: RG_EINVAL, RG_ENOMEM, RG_EDEVICE.
+ * Graphs with every out-degree <= 128 are held as ELL rows on the device;
+ * wider ones as CSR, searched 128 neighbours at a time.
+ * Errors: RG_EINVAL, RG_ENOMEM, RG_EDEVICE.
  */
 int rg_index_from_csr(const float *base, int64_t n, int32_t d, const int64_t *offsets,
                       const uint32_t *indices, uint32_t entry, int32_t metric, void *stream,
@@ -127,8 +135,42 @@ int rg_index_from_csr(const float *base, int64_t n, int32_t d, const int64_t *of
 int rg_index_graph(const rg_index *idx, const int64_t **offsets, const uint32_t **indices,
                    int64_t *nnz, uint32_t *entry);
 
+/*
+ * rg_index_stage_graph -- host CSR views of a graph the build passed
+ * through; needs a build with keep_stages.
+ *   RG_STAGE_PROJECTED: G_pj, the output of the neighbourhood-aware
+ *     projection (Algorithm 2) before connectivity enhancement, rows sorted
+ *     by neighbour id; entry = the index's entry (the enhancement searches
+ *     start there).
+ *   RG_STAGE_BIPARTITE: greedy routing on the query-base bipartite graph
+ *     G_bi (Sec. 4.2.1: from a base node through its out-neighbours, the
+ *     query nodes it is the pivot of, to their base out-neighbours).  Row x
+ *     lists N_out(t) for each bridge t of x in ascending t, each N_out(t) in
+ *     (delta(t, .), id) order without its pivot; duplicates across bridges
+ *     are kept (the search visits a node once).  A base node that is no
+ *     query's pivot has an empty row.  entry = the row nearest (L2) to the
+ *     mean among pivots.
+ * Both can be searched through rg_index_from_csr (any out-degree).  Views
+ * stay valid until rg_free.  Errors: RG_EINVAL (unknown stage, stages not
+ * kept).
+ */
+int rg_index_stage_graph(const rg_index *idx, int32_t stage, const int64_t **offsets,
+                         const uint32_t **indices, int64_t *nnz, uint32_t *entry);
+
+/*
+ * rg_index_bipartite -- host views of G_bi itself (Algorithm 1, first loop):
+ * bridge_offsets (n+1 int64) and bridges (nt uint32) list, per base node x,
+ * the training queries t whose nearest base row is x (edge x -> t), in
+ * ascending t; nout (nt x nout_len uint32, nout_len = Nq - 1) holds N_out(t),
+ * the other Nq - 1 nearest rows of t in (delta, id) order.  Needs
+ * keep_stages.  Errors: RG_EINVAL.
+ */
+int rg_index_bipartite(const rg_index *idx, const int64_t **bridge_offsets, const uint32_t **bridges,
+                       const uint32_t **nout, int64_t *nt, int32_t *nout_len);
+
 /* rg_index_info -- n, d, the padded row pitch in floats, the ELL row width of
- * the device adjacency, and device bytes held.  Any output may be NULL. */
+ * the device adjacency (0 when the graph is held as CSR because a row is
+ * wider than 128), and device bytes held.  Any output may be NULL. */
 int rg_index_info(const rg_index *idx, int64_t *n, int32_t *d, int32_t *pitch,
                   int32_t *ell_width, int64_t *device_bytes);
 

@@ -99,9 +99,34 @@ def knn(X, Q, k):
     return ids, ds
 
 
-def medoid(X) -> int:
+def medoid(X, mask=None) -> int:
+    """Row nearest (L2) to the mean of all rows; with a mask, among the
+    masked rows only (all rows if none is masked); lower id on ties."""
     X = _f32(X)
-    return int(_load().or_medoid(_p(X), X.shape[0], X.shape[1]))
+    if mask is None:
+        return int(_load().or_medoid(_p(X), X.shape[0], X.shape[1]))
+    m = np.ascontiguousarray(mask, dtype=np.uint8)
+    if not m.any():
+        return int(_load().or_medoid(_p(X), X.shape[0], X.shape[1]))
+    return int(_load().or_medoid_masked(_p(X), X.shape[0], X.shape[1], _p(m)))
+
+
+def bipartite_routing(b_offsets, b_indices, nout):
+    """Greedy routing on the query-base bipartite graph G_bi (Sec. 4.2.1):
+    from base node x to the query nodes x links to (the queries whose pivot
+    is x, ascending), then to those queries' base out-neighbours N_out(t).
+    Returns CSR rows over base nodes: row x = N_out(t) for each bridge t of x,
+    concatenated; a search visits a repeated node once.  Plain loop."""
+    n = len(b_offsets) - 1
+    off = np.zeros(n + 1, np.int64)
+    rows = []
+    for x in range(n):
+        r = [np.asarray(nout[int(t)], np.uint32) for t in b_indices[b_offsets[x]:b_offsets[x + 1]]]
+        r = np.concatenate(r) if r else np.zeros(0, np.uint32)
+        rows.append(r)
+        off[x + 1] = off[x] + len(r)
+    idx = np.concatenate(rows) if off[-1] else np.zeros(0, np.uint32)
+    return off, idx.astype(np.uint32)
 
 
 def acquire(X, x, C, m, fill):

@@ -18,6 +18,7 @@ LIB_PATH = os.environ.get("RG_LIB", os.path.join(_HERE, "libroargraph.so"))
 RG_OK, RG_EINVAL, RG_ENOMEM, RG_EDEVICE, RG_EAGAIN, RG_ECORRUPT, RG_EINTERNAL = 0, -1, -2, -3, -4, -5, -6
 RG_METRIC_IP = 0
 RG_STORE_FP32, RG_STORE_BF16, RG_STORE_FP8E4M3 = 0, 1, 2
+RG_STAGE_PROJECTED, RG_STAGE_BIPARTITE = 1, 2
 NONE = 0xFFFFFFFF
 MAX_L = 512
 
@@ -30,7 +31,7 @@ class RGError(RuntimeError):
 
 class rg_build_opts(ctypes.Structure):
     _fields_ = [("L_build", ctypes.c_int32), ("m_pj", ctypes.c_int32), ("m_ce", ctypes.c_int32),
-                ("threads", ctypes.c_int32), ("knn_slack", ctypes.c_int32)]
+                ("threads", ctypes.c_int32), ("knn_slack", ctypes.c_int32), ("keep_stages", ctypes.c_int32)]
 
 
 class rg_server_limits(ctypes.Structure):
@@ -53,6 +54,8 @@ _SIGS = {
     "rg_index_from_csr": (i32, [P, i64, i32, P, P, u32, i32, P, PP]),
     "rg_build_from_knn": (i32, [P, i64, i32, P, i64, i32, i32, ctypes.POINTER(rg_build_opts), PP]),
     "rg_index_graph": (i32, [P, PP, PP, ctypes.POINTER(i64), ctypes.POINTER(u32)]),
+    "rg_index_stage_graph": (i32, [P, i32, PP, PP, ctypes.POINTER(i64), ctypes.POINTER(u32)]),
+    "rg_index_bipartite": (i32, [P, PP, PP, PP, ctypes.POINTER(i64), ctypes.POINTER(i32)]),
     "rg_index_info": (i32, [P, ctypes.POINTER(i64), ctypes.POINTER(i32), ctypes.POINTER(i32),
                             ctypes.POINTER(i32), ctypes.POINTER(i64)]),
     "rg_index_set_storage": (i32, [P, i32, P]),
@@ -146,6 +149,31 @@ class Index:
             x = np.zeros(0, np.uint32)
         return o, x, int(entry.value)
 
+    def stage_graph(self, stage):
+        """(offsets, indices, entry) copies of RG_STAGE_PROJECTED or RG_STAGE_BIPARTITE."""
+        off, idx = ctypes.c_void_p(), ctypes.c_void_p()
+        nnz, entry = i64(), u32()
+        _check(lib().rg_index_stage_graph(self.h, int(stage), ctypes.byref(off), ctypes.byref(idx), ctypes.byref(nnz),
+                                          ctypes.byref(entry)))
+        n = self.info()["n"]
+        o = np.ctypeslib.as_array(ctypes.cast(off, ctypes.POINTER(ctypes.c_int64)), (n + 1,)).copy()
+        x = (np.ctypeslib.as_array(ctypes.cast(idx, ctypes.POINTER(ctypes.c_uint32)), (nnz.value,)).copy()
+             if nnz.value else np.zeros(0, np.uint32))
+        return o, x, int(entry.value)
+
+    def bipartite(self):
+        """(bridge_offsets n+1, bridges nt, nout nt x (Nq-1)) copies of G_bi."""
+        bo, bi, no = ctypes.c_void_p(), ctypes.c_void_p(), ctypes.c_void_p()
+        nt, q1 = i64(), i32()
+        _check(lib().rg_index_bipartite(self.h, ctypes.byref(bo), ctypes.byref(bi), ctypes.byref(no),
+                                        ctypes.byref(nt), ctypes.byref(q1)))
+        n = self.info()["n"]
+        b_off = np.ctypeslib.as_array(ctypes.cast(bo, ctypes.POINTER(ctypes.c_int64)), (n + 1,)).copy()
+        b_idx = np.ctypeslib.as_array(ctypes.cast(bi, ctypes.POINTER(ctypes.c_uint32)), (nt.value,)).copy()
+        nout = np.ctypeslib.as_array(ctypes.cast(no, ctypes.POINTER(ctypes.c_uint32)),
+                                     (nt.value * q1.value,)).copy().reshape(nt.value, q1.value)
+        return b_off, b_idx, nout
+
     def info(self):
         n, d, pitch, ell, b = i64(), i32(), i32(), i32(), i64()
         _check(lib().rg_index_info(self.h, ctypes.byref(n), ctypes.byref(d), ctypes.byref(pitch),
@@ -167,22 +195,23 @@ class Index:
         return b.value, f.value, s.value, p8.value
 
 
-def rg_build(base, train, Nq, M, L_build=0, m_pj=0, m_ce=0, threads=0, knn_slack=0, stream=None) -> Index:
+def rg_build(base, train, Nq, M, L_build=0, m_pj=0, m_ce=0, threads=0, knn_slack=0, keep_stages=False,
+             stream=None) -> Index:
     base, train = _dev_f32(base, "base"), _dev_f32(train, "train")
-    o = rg_build_opts(L_build, m_pj, m_ce, threads, knn_slack)
+    o = rg_build_opts(L_build, m_pj, m_ce, threads, knn_slack, int(bool(keep_stages)))
     h = ctypes.c_void_p()
     _check(lib().rg_build(_ptr(base), base.shape[0], base.shape[1], _ptr(train), train.shape[0], int(Nq), int(M),
                           RG_METRIC_IP, ctypes.byref(o), _stream(stream), ctypes.byref(h)))
     return Index(h)
 
 
-def rg_build_from_knn(base_host, knn_host, Nq, M, L_build=0, m_pj=0, m_ce=0, threads=0) -> Index:
+def rg_build_from_knn(base_host, knn_host, Nq, M, L_build=0, m_pj=0, m_ce=0, threads=0, keep_stages=False) -> Index:
     """Host-only construction from precomputed kNN lists (numpy inputs)."""
     X = np.ascontiguousarray(base_host, dtype=np.float32)
     K = np.ascontiguousarray(knn_host, dtype=np.uint32)
     if K.ndim != 2 or K.shape[1] != Nq:
         raise ValueError("knn_host must be nt x Nq")
-    o = rg_build_opts(L_build, m_pj, m_ce, threads, 0)
+    o = rg_build_opts(L_build, m_pj, m_ce, threads, 0, int(bool(keep_stages)))
     h = ctypes.c_void_p()
     _check(lib().rg_build_from_knn(X.ctypes.data_as(P), X.shape[0], X.shape[1], K.ctypes.data_as(P), K.shape[0],
                                    int(Nq), int(M), ctypes.byref(o), ctypes.byref(h)))

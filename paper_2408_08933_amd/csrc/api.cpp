@@ -60,11 +60,13 @@ struct DevBuf {
 void free_index_device(rg_index *ix) {
     if (ix->d_base) (void)hipFree(ix->d_base);
     if (ix->d_adj) (void)hipFree(ix->d_adj);
+    if (ix->d_adj_off) (void)hipFree(ix->d_adj_off);
     if (ix->d_bf16) (void)hipFree(ix->d_bf16);
     if (ix->d_fp8) (void)hipFree(ix->d_fp8);
     if (ix->d_scale) (void)hipFree(ix->d_scale);
     ix->d_base = nullptr;
     ix->d_adj = nullptr;
+    ix->d_adj_off = nullptr;
     ix->d_bf16 = nullptr;
     ix->d_fp8 = nullptr;
     ix->d_scale = nullptr;
@@ -81,14 +83,35 @@ int upload_base(rg_index *ix, const float *base_dev, hipStream_t st) {
     return launch_pad_rows(base_dev, ix->n, ix->d, ix->d_base, ix->pitch, st);
 }
 
-// Device ELL adjacency (rows of width ell = max degree rounded up to 8, kNone padded).
+// Device adjacency: ELL rows of width ell = max degree rounded up to 8
+// (kNone padded) when the degree allows, else CSR (offsets + indices, ell = 0).
 int upload_adj(rg_index *ix, hipStream_t st) {
     const int64_t n = ix->n;
     int64_t maxdeg = 1;
     for (int64_t x = 0; x < n; ++x) maxdeg = std::max<int64_t>(maxdeg, ix->offsets[x + 1] - ix->offsets[x]);
     if (maxdeg > kMaxEll) {
-        set_error("index: out-degree " + std::to_string(maxdeg) + " exceeds 128");
-        return RG_EINVAL;
+        if (maxdeg >= (1ll << 31)) {
+            set_error("index: out-degree does not fit 32 bits");
+            return RG_EINVAL;
+        }
+        const int64_t nnz = ix->offsets[n];
+        ix->ell = 0;
+        if (hipMalloc(&ix->d_adj, sizeof(uint32_t) * (size_t)std::max<int64_t>(nnz, 1)) != hipSuccess) {
+            ix->d_adj = nullptr;
+            set_error("index: out of device memory for the adjacency");
+            return RG_ENOMEM;
+        }
+        if (hipMalloc(&ix->d_adj_off, sizeof(int64_t) * (size_t)(n + 1)) != hipSuccess) {
+            ix->d_adj_off = nullptr;
+            set_error("index: out of device memory for the adjacency");
+            return RG_ENOMEM;
+        }
+        RG_HIP(hipMemcpyAsync(ix->d_adj, ix->indices.data(), sizeof(uint32_t) * (size_t)nnz, hipMemcpyHostToDevice,
+                              st));
+        RG_HIP(hipMemcpyAsync(ix->d_adj_off, ix->offsets.data(), sizeof(int64_t) * (size_t)(n + 1),
+                              hipMemcpyHostToDevice, st));
+        RG_HIP(hipStreamSynchronize(st));
+        return RG_OK;
     }
     ix->ell = round_up((int32_t)maxdeg, 8);
     if (hipMalloc(&ix->d_adj, sizeof(uint32_t) * (size_t)n * ix->ell) != hipSuccess) {
@@ -103,6 +126,34 @@ int upload_adj(rg_index *ix, hipStream_t st) {
     RG_HIP(hipMemcpyAsync(ix->d_adj, ell.data(), sizeof(uint32_t) * ell.size(), hipMemcpyHostToDevice, st));
     RG_HIP(hipStreamSynchronize(st));
     return RG_OK;
+}
+
+// Search parameters common to every search entry point.
+SearchArgs search_args(const rg_index *ix, const float *queries, int64_t nq, int32_t k, int32_t L, uint32_t *ids,
+                       float *dists, uint32_t *hops, uint32_t *evals) {
+    SearchArgs a{};
+    a.base = ix->d_base;
+    a.base_bf16 = ix->d_bf16;
+    a.base_fp8 = ix->d_fp8;
+    a.scale_fp8 = ix->d_scale;
+    a.adj = ix->d_adj;
+    a.adj_off = ix->d_adj_off;
+    a.queries = queries;
+    a.out_ids = ids;
+    a.out_d = dists;
+    a.out_hops = hops;
+    a.out_evals = evals;
+    a.nq = nq;
+    a.d = ix->d;
+    a.pitch = ix->pitch;
+    a.pitch8 = ix->pitch8;
+    a.ell = ix->ell;
+    a.k = k;
+    a.Leff = std::max(k, L);
+    a.hash_bits = 0;
+    a.entry = ix->entry;
+    a.storage = ix->storage;
+    return a;
 }
 
 int upload_index(rg_index *ix, const float *base_dev, hipStream_t st) {
@@ -326,13 +377,15 @@ int rg_build(const float *base, int64_t n, int32_t d, const float *train, int64_
     HostGraph g;
     if (!rc) {
         GpuCtx gpu{ix->d_base, ix->pitch, st};
-        rc = host_construct(xh.data(), n, d, knn.data(), nt, Nq, M, L, m_pj, m_ce, threads, &gpu, &g);
+        rc = host_construct(xh.data(), n, d, knn.data(), nt, Nq, M, L, m_pj, m_ce, threads, &gpu, o.keep_stages != 0,
+                            &g);
     }
     if (!rc) {
         ix->entry = g.entry;
         ix->repairs = g.repairs;
         ix->offsets.swap(g.offsets);
         ix->indices.swap(g.indices);
+        ix->stages = std::move(g.stages);
         rc = upload_adj(ix, st);
     }
     if (rc) {
@@ -373,7 +426,7 @@ int rg_build_from_knn(const float *base_host, int64_t n, int32_t d, const uint32
     }
     HostGraph g;
     const int rc = host_construct(base_host, n, d, knn_host, nt, Nq, M, L, m_pj, m_ce, hw_threads(o.threads),
-                                  nullptr, &g);
+                                  nullptr, o.keep_stages != 0, &g);
     if (rc) return rc;
     rg_index *ix = new rg_index();
     ix->n = n;
@@ -387,6 +440,7 @@ int rg_build_from_knn(const float *base_host, int64_t n, int32_t d, const uint32
     ix->repairs = g.repairs;
     ix->offsets.swap(g.offsets);
     ix->indices.swap(g.indices);
+    ix->stages = std::move(g.stages);
     ix->t_project = g.t_project;
     ix->t_enhance = g.t_enhance;
     ix->t_total = g.t_total;
@@ -437,6 +491,42 @@ int rg_index_graph(const rg_index *ix, const int64_t **offsets, const uint32_t *
     return RG_OK;
 }
 
+int rg_index_stage_graph(const rg_index *ix, int32_t stage, const int64_t **offsets, const uint32_t **indices,
+                         int64_t *nnz, uint32_t *entry) {
+    if (!ix || (stage != RG_STAGE_PROJECTED && stage != RG_STAGE_BIPARTITE)) {
+        set_error("rg_index_stage_graph: invalid argument");
+        return RG_EINVAL;
+    }
+    const StageGraphs &sg = ix->stages;
+    if (!sg.kept) {
+        set_error("rg_index_stage_graph: the build did not keep its stage graphs (keep_stages)");
+        return RG_EINVAL;
+    }
+    const bool pj = stage == RG_STAGE_PROJECTED;
+    const std::vector<int64_t> &off = pj ? sg.pj_off : sg.bi_off;
+    const std::vector<uint32_t> &idx = pj ? sg.pj_idx : sg.bi_idx;
+    if (offsets) *offsets = off.data();
+    if (indices) *indices = idx.data();
+    if (nnz) *nnz = off[ix->n];
+    if (entry) *entry = pj ? ix->entry : sg.entry_bi;
+    return RG_OK;
+}
+
+int rg_index_bipartite(const rg_index *ix, const int64_t **bridge_offsets, const uint32_t **bridges,
+                       const uint32_t **nout, int64_t *nt, int32_t *nout_len) {
+    if (!ix || !ix->stages.kept) {
+        set_error("rg_index_bipartite: the build did not keep its stage graphs (keep_stages)");
+        return RG_EINVAL;
+    }
+    const StageGraphs &sg = ix->stages;
+    if (bridge_offsets) *bridge_offsets = sg.b_off.data();
+    if (bridges) *bridges = sg.b_idx.data();
+    if (nout) *nout = sg.nout.data();
+    if (nt) *nt = sg.nt;
+    if (nout_len) *nout_len = sg.q1;
+    return RG_OK;
+}
+
 int rg_index_info(const rg_index *ix, int64_t *n, int32_t *d, int32_t *pitch, int32_t *ell, int64_t *bytes) {
     if (!ix) {
         set_error("rg_index_info: null index");
@@ -447,7 +537,8 @@ int rg_index_info(const rg_index *ix, int64_t *n, int32_t *d, int32_t *pitch, in
     if (pitch) *pitch = ix->pitch;
     if (ell) *ell = ix->ell;
     if (bytes) {
-        int64_t b = (int64_t)ix->n * ix->pitch * 4 + (int64_t)ix->n * ix->ell * 4;
+        int64_t b = (int64_t)ix->n * ix->pitch * 4;
+        b += ix->d_adj_off ? ix->offsets[ix->n] * 4 + (ix->n + 1) * 8 : (int64_t)ix->n * ix->ell * 4;
         if (ix->d_bf16) b += (int64_t)ix->n * ix->pitch * 2;
         if (ix->d_fp8) b += (int64_t)ix->n * ix->pitch8 + ix->n * 4;
         *bytes = b;
@@ -524,27 +615,7 @@ int rg_search(const rg_index *ix, const float *queries, int64_t nq, int32_t k, i
     }
     if (nq == 0) return RG_OK;
     hipStream_t st = (hipStream_t)stream;
-    SearchArgs a{};
-    a.base = ix->d_base;
-    a.base_bf16 = ix->d_bf16;
-    a.base_fp8 = ix->d_fp8;
-    a.scale_fp8 = ix->d_scale;
-    a.adj = ix->d_adj;
-    a.queries = queries;
-    a.out_ids = ids;
-    a.out_d = dists;
-    a.out_hops = hops;
-    a.out_evals = evals;
-    a.nq = nq;
-    a.d = ix->d;
-    a.pitch = ix->pitch;
-    a.pitch8 = ix->pitch8;
-    a.ell = ix->ell;
-    a.k = k;
-    a.Leff = std::max(k, L);
-    a.hash_bits = 0;
-    a.entry = ix->entry;
-    a.storage = ix->storage;
+    SearchArgs a = search_args(ix, queries, nq, k, L, ids, dists, hops, evals);
     // persistent grid: as many resident workgroups as the chip holds, each
     // with its own visited bitmap (bounded to 8 GiB in total)
     int per_cu = 0, cus = 0;
@@ -587,31 +658,13 @@ int rg_search_hashbits(const rg_index *ix, const float *queries, int64_t nq, int
         set_error("rg_search_hashbits: index has no device data");
         return RG_EINVAL;
     }
-    if ((1 << hash_bits) < 2 * ix->ell + 2) {
+    const int width = ix->d_adj_off ? kMaxEll : ix->ell;  // ids inserted per batch
+    if ((1 << hash_bits) < 2 * width + 2) {
         set_error("rg_search_hashbits: table too small for the row width");
         return RG_EINVAL;
     }
-    SearchArgs a{};
-    a.base = ix->d_base;
-    a.base_bf16 = ix->d_bf16;
-    a.base_fp8 = ix->d_fp8;
-    a.scale_fp8 = ix->d_scale;
-    a.adj = ix->d_adj;
-    a.queries = queries;
-    a.out_ids = ids;
-    a.out_d = dists;
-    a.out_hops = hops;
-    a.out_evals = evals;
-    a.nq = nq;
-    a.d = ix->d;
-    a.pitch = ix->pitch;
-    a.pitch8 = ix->pitch8;
-    a.ell = ix->ell;
-    a.k = k;
-    a.Leff = std::max(k, L);
+    SearchArgs a = search_args(ix, queries, nq, k, L, ids, dists, hops, evals);
     a.hash_bits = hash_bits;
-    a.entry = ix->entry;
-    a.storage = ix->storage;
     return launch_search(a, (hipStream_t)stream);
 }
 
@@ -672,7 +725,7 @@ int rg_load(const char *path, void *stream, rg_index **out) {
     const char want[8] = {'R', 'G', 'I', 'D', 'X', 0, 0, 1};
     bool ok = get(magic, 8) && std::memcmp(magic, want, 8) == 0 && get(&n, 8) && get(hdr, sizeof(hdr)) &&
               get(&repairs, 8) && get(&nnz, 8) && n >= 1 && n < (1ll << 31) && hdr[0] >= 1 && nnz >= 0 &&
-              nnz <= n * (int64_t)kMaxEll;
+              nnz < (1ll << 40);
     rg_index *ix = nullptr;
     std::vector<float> base;
     if (ok) {

@@ -12,7 +12,8 @@
 //     work done, never the result;
 //   * the candidate batch of the current expansion.
 // Per expansion: pick the first unexpanded queue entry, read its adjacency
-// row (ELL, one id per lane), filter through the visited set, gather the
+// row (ELL, one id per lane; or a CSR row of any length, 128 ids at a time),
+// filter through the visited set, gather the
 // new neighbours' rows (G lanes per row, 16-byte loads, R rows per group in
 // flight), reduce the FP32 dot products inside each G-lane group with xor
 // shuffles, sort the batch in registers, and merge the entries that beat the
@@ -298,30 +299,44 @@ __device__ __forceinline__ void run_search(const SearchArgs &a, const Lds &s, VI
         __syncthreads();
         if (lane == 0) s.qi[sel] = v | kExpanded;
         ++hops;
-        vis.begin_hop(ell);
-        const uint32_t r0 = lane < ell ? a.adj[(size_t)v * ell + lane] : kNone;
-        const uint32_t r1 = (ell > 64 && lane + 64 < ell) ? a.adj[(size_t)v * ell + lane + 64] : kNone;
-        int nnew = 0;
-#pragma unroll
-        for (int half = 0; half < 2; ++half) {
-            if (half == 1 && ell <= 64) break;
-            const uint32_t u = half == 0 ? r0 : r1;
-            const bool fresh = u != kNone && vis.insert(u);
-            const uint64_t m = ballot64(fresh);
-            if (fresh) s.ci[nnew + lanes_below(m)] = u;
-            nnew += (int)__popcll(m);
+        // ELL row (width ell), or a CSR row of any length taken kCand ids
+        // at a time; each chunk is scored and merged before the next, which
+        // ends in the same queue as one merge of the whole row.
+        int64_t row = (int64_t)v * ell;
+        int deg = ell;
+        if (a.adj_off) {
+            row = a.adj_off[v];
+            deg = (int)(a.adj_off[v + 1] - row);
         }
-        vis.added(nnew);
-        evals += (uint32_t)nnew;
-        __syncthreads();
-        if (nnew == 0) continue;
-        score_batch<ST, G, NCH, R>(a, s.qs, nch, s.ci, 0xFFFFFFFFu, s.cd, nnew);
-        __syncthreads();
-        const QueueLds<float> ql{s.qd, s.qi, s.cd, s.ci, s.sd, s.si, s.slb};
-        if (nnew <= 64)
-            merge_batch<1, float>(ql, nnew, Leff, qn, ptr);
-        else
-            merge_batch<2, float>(ql, nnew, Leff, qn, ptr);
+        for (int c0 = 0; c0 < deg; c0 += kCand) {
+            const int cl = min(kCand, deg - c0);
+            const uint32_t *ids = a.adj + row + c0;
+            vis.begin_hop(cl);
+            const uint32_t r0 = lane < cl ? ids[lane] : kNone;
+            const uint32_t r1 = lane + 64 < cl ? ids[lane + 64] : kNone;
+            int nnew = 0;
+#pragma unroll
+            for (int half = 0; half < 2; ++half) {
+                if (half == 1 && cl <= 64) break;
+                const uint32_t u = half == 0 ? r0 : r1;
+                const bool fresh = u != kNone && vis.insert(u);
+                const uint64_t m = ballot64(fresh);
+                if (fresh) s.ci[nnew + lanes_below(m)] = u;
+                nnew += (int)__popcll(m);
+            }
+            vis.added(nnew);
+            evals += (uint32_t)nnew;
+            __syncthreads();
+            if (nnew == 0) continue;
+            score_batch<ST, G, NCH, R>(a, s.qs, nch, s.ci, 0xFFFFFFFFu, s.cd, nnew);
+            __syncthreads();
+            const QueueLds<float> ql{s.qd, s.qi, s.cd, s.ci, s.sd, s.si, s.slb};
+            if (nnew <= 64)
+                merge_batch<1, float>(ql, nnew, Leff, qn, ptr);
+            else
+                merge_batch<2, float>(ql, nnew, Leff, qn, ptr);
+            __syncthreads();
+        }
     }
 }
 

@@ -404,7 +404,8 @@ int hw_threads(int requested) {
 }
 
 int host_construct(const float *X, int64_t n, int32_t d, const uint32_t *knn, int64_t nt, int32_t Nq, int32_t M,
-                   int32_t L, int32_t m_pj, int32_t m_ce, int threads, const GpuCtx *gpu, HostGraph *out) {
+                   int32_t L, int32_t m_pj, int32_t m_ce, int threads, const GpuCtx *gpu, bool keep_stages,
+                   HostGraph *out) {
     const auto t0 = Clock::now();
     threads = hw_threads(threads);
     const int q1 = Nq - 1;
@@ -480,39 +481,43 @@ int host_construct(const float *X, int64_t n, int32_t d, const uint32_t *knn, in
     if (log) std::fprintf(stderr, "[rg] projection done in %.2f s\n", secs(t0, t1));
 
     // --- entry: nearest to the mean among nodes with a projected out-edge --
-    uint32_t entry = 0;
-    {
-        std::vector<double> mu((size_t)d, 0.0);
-        for (int64_t i = 0; i < n; ++i)
-            for (int j = 0; j < d; ++j) mu[j] += (double)X[i * d + j];
-        for (int j = 0; j < d; ++j) mu[j] = mu[j] / (double)n;
+    std::vector<double> mu((size_t)d, 0.0);
+    for (int64_t i = 0; i < n; ++i)
+        for (int j = 0; j < d; ++j) mu[j] += (double)X[i * d + j];
+    for (int j = 0; j < d; ++j) mu[j] = mu[j] / (double)n;
+    // the row nearest (L2) to the mean among rows with keep(i), or among all
+    // rows when none qualifies; lower id on ties
+    auto nearest_mean = [&](auto keep) -> uint32_t {
         bool any = false;
-        for (int64_t i = 0; i < n && !any; ++i) any = PJ.deg[i] > 0;
+        for (int64_t i = 0; i < n && !any; ++i) any = keep(i);
         const int64_t chunk = 4096;
         const int64_t nchunk = (n + chunk - 1) / chunk;
         std::vector<double> bestd((size_t)nchunk, INFINITY);
         std::vector<int64_t> besti((size_t)nchunk, -1);
         parallel_for(nchunk, threads, 1, [&](int64_t c, int) {
             for (int64_t i = c * chunk; i < std::min(n, (c + 1) * chunk); ++i) {
-                if (any && PJ.deg[i] == 0) continue;
-                double s = 0.0;
+                if (any && !keep(i)) continue;
+                double s2 = 0.0;
                 for (int j = 0; j < d; ++j) {
                     const double t = (double)X[i * d + j] - mu[j];
-                    s += t * t;
+                    s2 += t * t;
                 }
-                if (s < bestd[c]) {
-                    bestd[c] = s;
+                if (s2 < bestd[c]) {
+                    bestd[c] = s2;
                     besti[c] = i;
                 }
             }
         });
         double b = INFINITY;
+        uint32_t e = 0;
         for (int64_t c = 0; c < nchunk; ++c)
             if (besti[c] >= 0 && bestd[c] < b) {
                 b = bestd[c];
-                entry = (uint32_t)besti[c];
+                e = (uint32_t)besti[c];
             }
-    }
+        return e;
+    };
+    const uint32_t entry = nearest_mean([&](int64_t i) { return PJ.deg[i] > 0; });
 
     // --- enhancement: searches on G_pj and each node's own selection E(x) --
     Lists E;
@@ -631,6 +636,33 @@ int host_construct(const float *X, int64_t n, int32_t d, const uint32_t *knn, in
     });
     out->entry = entry;
     out->repairs = repairs;
+    if (keep_stages) {
+        // G_bi routing: row x = N_out(t) for each bridge t of x, ascending t
+        StageGraphs &sg = out->stages;
+        sg.kept = true;
+        sg.nt = nt;
+        sg.q1 = q1;
+        sg.nout.resize((size_t)nt * q1);
+        for (int64_t t = 0; t < nt; ++t)
+            std::copy(knn + t * Nq + 1, knn + (t + 1) * Nq, sg.nout.begin() + t * q1);
+        sg.bi_off.assign((size_t)n + 1, 0);
+        for (int64_t x = 0; x < n; ++x) sg.bi_off[x + 1] = sg.bi_off[x] + (boff[x + 1] - boff[x]) * q1;
+        sg.bi_idx.resize((size_t)sg.bi_off[n]);
+        parallel_for(n, threads, 1024, [&](int64_t x, int) {
+            int64_t o = sg.bi_off[x];
+            for (int64_t b = boff[x]; b < boff[x + 1]; ++b, o += q1)
+                std::copy(sg.nout.begin() + (int64_t)bidx[b] * q1, sg.nout.begin() + ((int64_t)bidx[b] + 1) * q1,
+                          sg.bi_idx.begin() + o);
+        });
+        sg.entry_bi = nearest_mean([&](int64_t i) { return boff[i + 1] > boff[i]; });
+        sg.b_off.swap(boff);
+        sg.b_idx.swap(bidx);
+        sg.pj_off.swap(pjoff);
+        sg.pj_idx.swap(pjidx);
+        parallel_for(n, threads, 4096, [&](int64_t x, int) {
+            std::sort(sg.pj_idx.begin() + sg.pj_off[x], sg.pj_idx.begin() + sg.pj_off[x + 1]);
+        });
+    }
     const auto t3 = Clock::now();
     if (log) std::fprintf(stderr, "[rg] repair (%lld edges) and CSR done in %.2f s\n", (long long)repairs, secs(t2, t3));
     out->t_project = secs(t0, t1);

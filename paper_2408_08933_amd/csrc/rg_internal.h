@@ -14,7 +14,7 @@ namespace rg {
 constexpr uint32_t kNone = 0xFFFFFFFFu;
 constexpr uint32_t kExpanded = 0x80000000u;  // queue-entry flag (ids < 2^31)
 constexpr int kMaxL = 512;                    // largest queue the search kernel holds
-constexpr int kMaxEll = 128;                  // largest out-degree the search kernel reads
+constexpr int kMaxEll = 128;                  // widest ELL row; wider graphs are searched as CSR
 
 void set_error(const std::string &msg);
 
@@ -34,7 +34,8 @@ struct SearchArgs {
     const uint16_t *base_bf16;  // bf16 rows (pitch elements) or null
     const uint8_t *base_fp8;    // e4m3 rows (pitch8 bytes) or null
     const float *scale_fp8;     // per-row power-of-two scales
-    const uint32_t *adj;        // ELL adjacency, n x ell, kNone padded
+    const uint32_t *adj;        // ELL adjacency, n x ell, kNone padded; or CSR indices
+    const int64_t *adj_off;     // CSR offsets (n + 1), or null for ELL
     const float *queries;       // nq x d
     uint32_t *out_ids;          // nq x k
     float *out_d;               // nq x k
@@ -110,7 +111,27 @@ int launch_quant_fp8(const float *src, int64_t n, int32_t d, int32_t pitch, uint
 int launch_copy_probe(void *dst, const void *src, int64_t bytes, hipStream_t stream);
 
 // host_build.cpp
+// Graphs the construction passes through, kept on request: the bipartite
+// graph G_bi (bridge lists B(x) of the base nodes, ascending t, and the
+// out-lists N_out(t) of the training queries without their pivot), its
+// base-to-base routing rows (row x = N_out(t) for each t in B(x)) with their
+// entry, and the projected graph G_pj (rows sorted by neighbour id).
+struct StageGraphs {
+    bool kept = false;
+    int64_t nt = 0;
+    int32_t q1 = 0;
+    std::vector<int64_t> b_off;
+    std::vector<uint32_t> b_idx;
+    std::vector<uint32_t> nout;  // nt x q1
+    std::vector<int64_t> bi_off;
+    std::vector<uint32_t> bi_idx;
+    uint32_t entry_bi = 0;
+    std::vector<int64_t> pj_off;
+    std::vector<uint32_t> pj_idx;
+};
+
 struct HostGraph {
+    rg::StageGraphs stages;
     std::vector<int64_t> offsets;
     std::vector<uint32_t> indices;
     uint32_t entry = 0;
@@ -127,7 +148,7 @@ struct GpuCtx {
 // knn lists: nt x Nq canonical ids.  X: host n x d.  gpu == nullptr: host only.
 int host_construct(const float *X, int64_t n, int32_t d, const uint32_t *knn, int64_t nt,
                    int32_t Nq, int32_t M, int32_t L, int32_t m_pj, int32_t m_ce, int threads,
-                   const GpuCtx *gpu, HostGraph *out);
+                   const GpuCtx *gpu, bool keep_stages, HostGraph *out);
 
 // canon.hip: construction-time searches with the canonical FP64 distance
 int launch_canon_search(const float *X, int32_t d, int32_t pitch, const uint32_t *adj, int32_t ell,
@@ -157,10 +178,12 @@ struct rg_index {
     std::vector<int64_t> offsets;    // host CSR
     std::vector<uint32_t> indices;
     float *d_base = nullptr;          // n x pitch fp32
-    uint32_t *d_adj = nullptr;        // n x ell
+    uint32_t *d_adj = nullptr;        // n x ell (ELL) or nnz (CSR)
+    int64_t *d_adj_off = nullptr;     // CSR offsets, null for ELL
     uint16_t *d_bf16 = nullptr;       // n x pitch
     uint8_t *d_fp8 = nullptr;         // n x pitch8
     float *d_scale = nullptr;         // n
     int device = 0;
     double t_knn = 0, t_project = 0, t_enhance = 0, t_total = 0;
+    rg::StageGraphs stages;
 };

@@ -130,6 +130,7 @@ void rg_server::loop() {
         sa.s.base_fp8 = ix->d_fp8;
         sa.s.scale_fp8 = ix->d_scale;
         sa.s.adj = ix->d_adj;
+        sa.s.adj_off = ix->d_adj_off;
         sa.s.d = d;
         sa.s.pitch = ix->pitch;
         sa.s.pitch8 = ix->pitch8;

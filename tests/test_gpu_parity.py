@@ -190,8 +190,8 @@ def test_search_rejects_bad_args(dev, c1_index):
 @pytest.fixture(scope="module")
 def c1_built(dev, c1):
     X, Tr, Q, G = c1
-    say("rg_build c1 (10k x 64, Nq=32, M=32, L=500)")
-    return rg.rg_build(T(X, dev), T(Tr, dev), 32, 32, L_build=500)
+    say("rg_build c1 (10k x 64, Nq=32, M=32, L=500), stage graphs kept")
+    return rg.rg_build(T(X, dev), T(Tr, dev), 32, 32, L_build=500, keep_stages=True)
 
 
 def test_build_bit_exact_c1(c1, c1_built):
@@ -200,6 +200,85 @@ def test_build_bit_exact_c1(c1, c1_built):
     assert entry == G.entry
     assert np.array_equal(off, G.offsets) and np.array_equal(idx, G.indices)
     assert c1_built.build_stats()["repairs"] == G.repairs
+
+
+def test_build_stage_graphs_c1(oracle_lib, c1, c1_built):
+    X, Tr, Q, G = c1
+    b_off, b_idx, nout = c1_built.bipartite()
+    assert np.array_equal(b_off, G.b_offsets) and np.array_equal(b_idx, G.b_indices) and np.array_equal(nout, G.nout)
+    off, idx, entry = c1_built.stage_graph(rg.RG_STAGE_PROJECTED)
+    assert np.array_equal(off, G.pj_offsets) and entry == G.entry
+    assert np.array_equal(idx, np.concatenate([np.sort(r) for r in G.rows("pj")]))
+    ro, ri = oracle_lib.bipartite_routing(G.b_offsets, G.b_indices, G.nout)
+    off, idx, entry = c1_built.stage_graph(rg.RG_STAGE_BIPARTITE)
+    assert np.array_equal(off, ro) and np.array_equal(idx, ri)
+    assert entry == oracle_lib.medoid(X, mask=np.diff(G.b_offsets) > 0)
+
+
+@pytest.mark.parametrize("stage", ["projected", "bipartite"])
+def test_search_stage_graph_parity(dev, oracle_lib, c1, stage):
+    # the ablation's graphs (Sec. 5.4): G_pj and routing on G_bi through
+    # query nodes; G_bi rows are |B(x)| * (Nq - 1) long, past the ELL width
+    X, Tr, Q, G = c1
+    if stage == "projected":
+        off, idx, entry = G.pj_offsets, G.pj_indices, G.entry
+    else:
+        off, idx = oracle_lib.bipartite_routing(G.b_offsets, G.b_indices, G.nout)
+        entry = oracle_lib.medoid(X, mask=np.diff(G.b_offsets) > 0)
+    ix = rg.rg_index_from_csr(T(X, dev), off, idx, entry)
+    if stage == "bipartite":
+        assert np.diff(off).max() > 128 and ix.info()["ell"] == 0   # held and searched as CSR
+    for k, L in ((10, 32), (10, 128), (100, 100)):
+        say(f"search on {stage} graph k={k} L={L}")
+        ids, ds = rg.rg_search(ix, T(Q, dev), k, L)
+        torch.cuda.synchronize()
+        oi, od, _, _, gaps = oracle_lib.search(X, off, idx, entry, Q, k, L)
+        r = compare(rg.as_u32(ids), ds.cpu().numpy(), oi, od, gaps, Q, X, min_agreement=0.97, min_near_same=0.9,
+                    label=f"{stage} k={k} L={L}")
+        say(f"  {r}")
+
+
+def test_search_wide_csr_rows(dev, oracle_lib):
+    # rows of 200..700 neighbours (several 128-id chunks, ragged last chunk):
+    # every entry point that searches (persistent, LDS table, serving)
+    rng = np.random.default_rng(21)
+    n, d = 3000, 40
+    X = rng.standard_normal((n, d)).astype(np.float32)
+    Q = rng.standard_normal((150, d)).astype(np.float32)
+    deg = rng.integers(200, 701, n)
+    off = np.zeros(n + 1, np.int64)
+    off[1:] = np.cumsum(deg)
+    idx = np.concatenate([rng.choice(n, int(g), replace=False) for g in deg]).astype(np.uint32)
+    ix = rg.rg_index_from_csr(T(X, dev), off, idx, 17)
+    assert ix.info()["ell"] == 0
+    for k, L in ((10, 20), (10, 64), (50, 200)):
+        say(f"wide csr k={k} L={L}")
+        ids, ds, hops, ev = rg.rg_search(ix, T(Q, dev), k, L, stats=True)
+        torch.cuda.synchronize()
+        oi, od, oh, oe, gaps = oracle_lib.search(X, off, idx, 17, Q, k, L)
+        compare(rg.as_u32(ids), ds.cpu().numpy(), oi, od, gaps, Q, X, min_agreement=0.97, min_near_same=0.9,
+                label=f"wide k={k} L={L}")
+        b = rg.rg_search(ix, T(Q, dev), k, L, stats=True, hash_bits=9)
+        torch.cuda.synchronize()
+        assert torch.equal(b[0], ids) and torch.equal(b[1], ds) and torch.equal(b[2], hops)
+    # serving on the same index gives each request's rg_search result
+    srv = rg.Server(ix, max_slots=64, hops_per_step=8)
+    for i in range(40):
+        assert srv.submit(Q[i], 10, 64, i) == rg.RG_OK
+    got = {}
+    import time
+    t0 = time.time()
+    while len(got) < 40 and time.time() - t0 < 60:
+        for r in srv.poll():
+            got[r["tag"]] = r
+        time.sleep(0.001)
+    srv.close()
+    assert len(got) == 40
+    ids, ds = rg.rg_search(ix, T(Q[:40], dev), 10, 64)
+    torch.cuda.synchronize()
+    a = rg.as_u32(ids)
+    for i in range(40):
+        assert np.array_equal(got[i]["ids"], a[i])
 
 
 def test_recall_on_built_index(dev, oracle_lib, c1, c1_built):

@@ -80,3 +80,38 @@ def test_build_from_knn_rejects_bad_input():
         rg.rg_build_from_knn(X, np.zeros((5, 2), np.uint32), 2, 2)        # M < 3
     with pytest.raises(rg.RGError):
         rg.rg_build_from_knn(X, np.full((5, 2), 99, np.uint32), 2, 8)     # ids out of range
+
+
+@pytest.mark.parametrize("cfg,n,nt,Nq,M,L", [(1, 1500, 1500, 16, 16, 100), (1, 2000, 300, 24, 20, 120)])
+def test_stage_graphs_bit_exact_with_oracle(oracle_lib, cfg, n, nt, Nq, M, L):
+    # the graphs the ablation searches: G_bi (bridges, N_out lists and the
+    # routing rows through query nodes) and G_pj, against the oracle's build
+    gen = datagen.Generator(cfg, n=n, n_train=nt, n_test=10)
+    X, T = gen.base(), gen.train()
+    G = oracle_lib.Graph(X, T, Nq, M, L)
+    knn, _ = oracle_lib.knn(X, T, Nq)
+    ix = rg.rg_build_from_knn(X, knn, Nq, M, L_build=L, keep_stages=True)
+    b_off, b_idx, nout = ix.bipartite()
+    assert np.array_equal(b_off, G.b_offsets) and np.array_equal(b_idx, G.b_indices)
+    assert np.array_equal(nout, G.nout)
+    off, idx, entry = ix.stage_graph(rg.RG_STAGE_PROJECTED)
+    pj_sorted = np.concatenate([np.sort(r) for r in G.rows("pj")])
+    assert np.array_equal(off, G.pj_offsets) and np.array_equal(idx, pj_sorted) and entry == G.entry
+    ro, ri = oracle_lib.bipartite_routing(G.b_offsets, G.b_indices, G.nout)
+    off, idx, entry = ix.stage_graph(rg.RG_STAGE_BIPARTITE)
+    assert np.array_equal(off, ro) and np.array_equal(idx, ri)
+    assert entry == oracle_lib.medoid(X, mask=np.diff(G.b_offsets) > 0)
+    # the final graph is unchanged by keeping the stages
+    a = ix.graph()
+    assert np.array_equal(a[0], G.offsets) and np.array_equal(a[1], G.indices) and a[2] == G.entry
+
+
+def test_stage_graphs_need_keep_stages(oracle_lib):
+    gen = datagen.Generator(1, n=300, n_train=300, n_test=10)
+    X = gen.base()
+    knn, _ = oracle_lib.knn(X, gen.train(), 8)
+    ix = rg.rg_build_from_knn(X, knn, 8, 8, L_build=50)
+    with pytest.raises(rg.RGError):
+        ix.stage_graph(rg.RG_STAGE_PROJECTED)
+    with pytest.raises(rg.RGError):
+        ix.bipartite()

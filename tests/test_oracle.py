@@ -140,6 +140,34 @@ def test_build_hand_worked_five_points(oracle_lib):
     assert list(G.pivot) == [0, 3]
 
 
+def test_bipartite_routing_hand_worked(oracle_lib):
+    # greedy routing on G_bi through query nodes (Sec. 4.2.1), by hand
+    g = json.load(open(os.path.join(GOLDEN, "projection_5pt.json")))
+    X = np.array([unit2(a) for a in g["base_angles_deg"]], np.float32)
+    T = np.array([unit2(a) for a in g["train_angles_deg"]], np.float32)
+    G = oracle_lib.Graph(X, T, g["Nq"], g["M"], g["L"])
+    off, idx = oracle_lib.bipartite_routing(G.b_offsets, G.b_indices, G.nout)
+    assert [idx[off[i]:off[i + 1]].tolist() for i in range(5)] == g["bi_rows"]
+    entry = oracle_lib.medoid(X, mask=np.diff(G.b_offsets) > 0)
+    assert entry == g["bi_entry"]
+    s = g["bi_search"]
+    q = np.array([unit2(s["query_deg"])], np.float32)
+    ids, _, _, _, _ = oracle_lib.search(X, off, idx, entry, q, s["k"], s["L"])
+    assert ids[0].tolist() == s["ids"]
+
+
+def test_bipartite_routing_rows_are_two_hop_sets(oracle_lib, small_graph):
+    # every routed neighbour of x is an out-neighbour of a query node that x
+    # links to, and each such out-neighbour appears
+    X, T, Q, G = small_graph
+    off, idx = oracle_lib.bipartite_routing(G.b_offsets, G.b_indices, G.nout)
+    for x in range(0, G.n, 7):
+        ts = [int(t) for t in range(len(G.pivot)) if G.pivot[t] == x]
+        want = sorted(set(int(u) for t in ts for u in G.nout[t]))
+        assert sorted(set(idx[off[x]:off[x + 1]].tolist())) == want
+        assert off[x + 1] - off[x] == len(ts) * (G.Nq - 1)
+
+
 # --------------------------------------------------------------------------
 # construction invariants on the tiny OOD workload law
 # --------------------------------------------------------------------------
