@@ -10,6 +10,7 @@ import numpy as np
 import pytest
 
 import datagen
+from oracle import NONE
 
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
 
@@ -370,3 +371,74 @@ def test_rerank_search_with_exact_storage_equals_plain(oracle_lib, small_graph):
     a = oracle_lib.search(X, G.offsets, G.indices, G.entry, Q[:40], 10, 32)
     b = oracle_lib.search_rerank(X, X, G.offsets, G.indices, G.entry, Q[:40], 10, 32)
     assert (a[0] == b[0]).all() and (a[1] == b[1]).all() and (a[2] == b[2]).all()
+
+
+# --------------------------------------------------------------------------
+# updates: insertion through the bipartite graph, tombstones (Sec. 6)
+# --------------------------------------------------------------------------
+def _five_point_state(oracle_lib):
+    from oracle.updates import Updatable
+    g = json.load(open(os.path.join(GOLDEN, "projection_5pt.json")))
+    X = np.array([unit2(a) for a in g["base_angles_deg"]], np.float32)
+    T = np.array([unit2(a) for a in g["train_angles_deg"]], np.float32)
+    G = oracle_lib.Graph(X, T, g["Nq"], g["M"], g["L"])
+    return Updatable.from_graph(G, X, T)
+
+
+def test_insert_hand_worked(oracle_lib):
+    u = json.load(open(os.path.join(GOLDEN, "updates_5pt.json")))
+    st = _five_point_state(oracle_lib)
+    assert st.rows == u["start_rows"] and st.nout == u["start_nout"]
+    for i, a in enumerate(u["inserts_deg"]):
+        ids = st.insert(np.array([unit2(a)], np.float32))
+        assert ids.tolist() == [5 + i]
+    assert st.rows == u["final_rows"]
+    assert st.nout == u["final_nout"]
+
+
+def test_insert_invariants(oracle_lib, small_graph):
+    from oracle.updates import Updatable
+    X, T, Q, G = small_graph
+    st = Updatable.from_graph(G, X, T)
+    gen = datagen.Generator(1, n=1500, n_train=1500, n_test=200)
+    V = np.concatenate([gen.in_distribution(60), Q[:60]])
+    before = sum(len(r) for r in st.nout)
+    st.insert(V[:70], L=64)
+    st.insert(V[70:], L=64)
+    n = st.n
+    assert n == G.n + len(V)
+    off, idx = st.csr()
+    deg = np.diff(off)
+    assert deg.max() <= G.M and (deg[G.n:] > 0).all()
+    assert _bfs(off, idx, st.entry, n).all()                 # every node, old and new, reachable
+    rows = [idx[off[i]:off[i + 1]] for i in range(n)]
+    assert all(len(set(r.tolist())) == len(r) and i not in r for i, r in enumerate(rows))
+    assert sum(len(r) for r in st.nout) - before <= len(V)    # each v joins at most one N_out
+    # old rows only ever gain new ids
+    old = G.rows("final")
+    assert all(np.array_equal(rows[i][:len(old[i])], old[i]) and (rows[i][len(old[i]):] >= G.n).all()
+               for i in range(G.n))
+
+
+def test_tombstones_exact_on_complete_graph(oracle_lib):
+    # a complete graph with L >= n visits everything: the results are the
+    # exact nearest non-deleted rows (brute force)
+    from oracle.updates import Updatable
+    rng = np.random.default_rng(4)
+    n, d = 60, 12
+    X = rng.standard_normal((n, d)).astype(np.float32)
+    Q = rng.standard_normal((9, d)).astype(np.float32)
+    rows = [[j for j in range(n) if j != i] for i in range(n)]
+    st = Updatable(rows, 0, n, n, X, X[:1], [0], [[]])
+    dead = rng.choice(n, 25, replace=False)
+    st.delete(dead)
+    ids, ds = st.search(Q, 10, n)
+    S = -(Q.astype(np.float64) @ X.astype(np.float64).T)
+    S[:, dead] = np.inf
+    want = np.argsort(S, axis=1, kind="stable")[:, :10]
+    assert np.array_equal(ids, want.astype(np.uint32))
+    assert np.allclose(ds, np.take_along_axis(S, want, 1))
+    # more deleted than the queue can skip: padding
+    st.delete(range(n))
+    ids, ds = st.search(Q, 10, 20)
+    assert (ids == NONE).all() and np.isinf(ds).all()
