@@ -317,6 +317,22 @@ def ablation(rg, torch, dev, n):
             c = qps_recall_curve(rg, torch, ix, Qid, gid)
             out["in_distribution"] = {"curve": c, "at_0.90": at_recall(c)}
         del ix
+    # insertion (Sec. 6): build on the first 90% of the base, insert the
+    # last 10% in batches of 10k, compare with the full build above
+    n0 = int(round(0.9 * n))
+    log(f"updates: build on {n0} rows, then insert {n - n0}")
+    Tr = torch.from_numpy(np.ascontiguousarray(Th)).to(dev)
+    ix = rg.rg_build(X[:n0].contiguous(), Tr, w.Nq, w.M, L_build=500, keep_stages=True)
+    del Tr
+    t = time.time()
+    for a in range(n0, n, 10000):
+        ix.insert(Xh[a:min(n, a + 10000)])
+    torch.cuda.synchronize()
+    ti = time.time() - t
+    log(f"  inserted {n - n0} rows in {ti:.1f} s")
+    c = qps_recall_curve(rg, torch, ix, Q, gt)
+    out["insertion"] = {"built_rows": n0, "inserted": n - n0, "insert_s": ti, "curve": c, "at_0.90": at_recall(c),
+                        "rebuilt_at_0.90": out["graphs"]["roargraph"]["at_0.90"]}
     return out
 
 

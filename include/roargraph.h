@@ -105,13 +105,16 @@ int rg_build(const float *base, int64_t n, int32_t d, const float *train, int64_
  *   base_host  host, n x d float32.
  *   knn_host   host, nt x Nq uint32, each row in (delta, id) order with the
  *              canonical FP64 distance (as rg_knn returns them).
+ *   train_host host, nt x d float32 training queries, or NULL; kept (with
+ *              keep_stages) only for rg_insert, which needs them.
  * Runs bipartite graph, projection, enhancement, repair and CSR on host
  * threads; the index holds only the graph (rg_index_graph, rg_save need
  * no device data; rg_search returns RG_EINVAL).  No HIP call is made.
  * Errors: RG_EINVAL (as rg_build, plus ids >= n), RG_EINTERNAL.
  */
 int rg_build_from_knn(const float *base_host, int64_t n, int32_t d, const uint32_t *knn_host,
-                      int64_t nt, int32_t Nq, int32_t M, const rg_build_opts *opts, rg_index **out);
+                      const float *train_host, int64_t nt, int32_t Nq, int32_t M,
+                      const rg_build_opts *opts, rg_index **out);
 
 /*
  * rg_index_from_csr -- wrap an existing graph as an index.
@@ -159,14 +162,57 @@ int rg_index_stage_graph(const rg_index *idx, int32_t stage, const int64_t **off
 
 /*
  * rg_index_bipartite -- host views of G_bi itself (Algorithm 1, first loop):
- * bridge_offsets (n+1 int64) and bridges (nt uint32) list, per base node x,
- * the training queries t whose nearest base row is x (edge x -> t), in
- * ascending t; nout (nt x nout_len uint32, nout_len = Nq - 1) holds N_out(t),
- * the other Nq - 1 nearest rows of t in (delta, id) order.  Needs
- * keep_stages.  Errors: RG_EINVAL.
+ * bridge_offsets (n_built+1 int64) and bridges (nt uint32) list, per base
+ * node x of the build (n_built = the rows the build had; inserted rows are
+ * no query's pivot), the training queries t whose nearest base row is x
+ * (edge x -> t), in ascending t; nout_offsets (nt+1 int64) and nout hold
+ * N_out(t), the other Nq - 1 nearest rows of t in (delta, id) order,
+ * followed by the rows rg_insert has added to it.  Needs keep_stages.
+ * Views stay valid until the next rg_insert or rg_free.  Errors: RG_EINVAL.
  */
 int rg_index_bipartite(const rg_index *idx, const int64_t **bridge_offsets, const uint32_t **bridges,
-                       const uint32_t **nout, int64_t *nt, int32_t *nout_len);
+                       int64_t *n_built, const int64_t **nout_offsets, const uint32_t **nout, int64_t *nt);
+
+/*
+ * rg_insert -- insert nv new base vectors (host, nv x d float32) through the
+ * saved bipartite graph (Sec. 6, "Update"); they get ids n .. n+nv-1 in
+ * input order.  Needs an index built with keep_stages (from kNN lists: with
+ * train_host).  Each vector v is searched on the index as it stood when the
+ * call began (canonical FP64 distance, queue length L; 0 => the build's L),
+ * on the device when the index has device data, else on host threads.
+ * Then, in input order:
+ *   - b = the first node of v's queue joined to a query node (b is the pivot
+ *     of t or b is in N_out(t)); q = the joined query nearest to v by
+ *     (delta(v, t), t);
+ *   - the sub-bipartite graph N_out(q) u {q, v} is projected with v as pivot
+ *     (Algorithm 2 for one pivot: candidates N_out(q) by (delta(v, .), id), at
+ *     most L, AcquireNeighbors with fill to m_pj); the selection is v's row;
+ *   - each selected p gains the edge p -> v while its row has fewer than M
+ *     entries; if none does, v gets one in-edge by the build's repair rule
+ *     (first queue node with a free slot, else the first in BFS order);
+ *   - v is appended to N_out(q).  With no joined node in the queue, v's
+ *     candidates are its queue and no N_out changes.
+ * Out-degrees stay <= M and every node stays reachable from the entry.  The
+ * device copies (rows, adjacency, tombstones, the chosen storage form) are
+ * remade.  Deterministic.  Not concurrent with other calls on the index.
+ * Errors: RG_EINVAL (no kept stages or training queries, L > 512, graph held
+ * as CSR), RG_ENOMEM, RG_EDEVICE, RG_EINTERNAL.
+ */
+int rg_insert(rg_index *idx, const float *vectors, int64_t nv, int32_t L, void *stream);
+
+/*
+ * rg_delete -- mark nodes deleted (tombstones, Sec. 6): they stay in the
+ * graph and keep routing searches, but rg_search and the server skip them
+ * when taking the k results from the final queue (so fewer than k results
+ * can come back, padded with 0xFFFFFFFF / +inf).  ids host, each < n;
+ * deleting a node twice is harmless.  Not concurrent with other calls on
+ * the index.  Errors: RG_EINVAL, RG_ENOMEM, RG_EDEVICE.
+ */
+int rg_delete(rg_index *idx, const uint32_t *ids, int64_t count, void *stream);
+
+/* rg_index_tombstones -- host view of the deleted-node bitmap (bit i of word
+ * i/32; NULL while nothing was deleted) and the number of deleted nodes. */
+int rg_index_tombstones(const rg_index *idx, const uint32_t **bits, int64_t *count);
 
 /* rg_index_info -- n, d, the padded row pitch in floats, the ELL row width of
  * the device adjacency (0 when the graph is held as CSR because a row is
@@ -250,7 +296,7 @@ int rg_index_storage_ptrs(const rg_index *idx, const void **bf16, const void **f
 
 /* rg_save / rg_load -- index file: header, parameters, entry, CSR, FP32 base
  * rows, and a 64-bit checksum over everything (rg_save needs an index with
- * device data).  Errors: RG_EINVAL,
+ * device data).  Stage graphs and tombstones are not stored.  Errors: RG_EINVAL,
  * RG_ENOMEM, RG_EDEVICE, RG_ECORRUPT (bad magic, size or checksum). */
 int rg_save(const rg_index *idx, const char *path);
 int rg_load(const char *path, void *stream, rg_index **out);

@@ -52,10 +52,13 @@ PP = ctypes.POINTER(ctypes.c_void_p)
 _SIGS = {
     "rg_build": (i32, [P, i64, i32, P, i64, i32, i32, i32, ctypes.POINTER(rg_build_opts), P, PP]),
     "rg_index_from_csr": (i32, [P, i64, i32, P, P, u32, i32, P, PP]),
-    "rg_build_from_knn": (i32, [P, i64, i32, P, i64, i32, i32, ctypes.POINTER(rg_build_opts), PP]),
+    "rg_build_from_knn": (i32, [P, i64, i32, P, P, i64, i32, i32, ctypes.POINTER(rg_build_opts), PP]),
     "rg_index_graph": (i32, [P, PP, PP, ctypes.POINTER(i64), ctypes.POINTER(u32)]),
     "rg_index_stage_graph": (i32, [P, i32, PP, PP, ctypes.POINTER(i64), ctypes.POINTER(u32)]),
-    "rg_index_bipartite": (i32, [P, PP, PP, PP, ctypes.POINTER(i64), ctypes.POINTER(i32)]),
+    "rg_index_bipartite": (i32, [P, PP, PP, ctypes.POINTER(i64), PP, PP, ctypes.POINTER(i64)]),
+    "rg_insert": (i32, [P, P, i64, i32, P]),
+    "rg_delete": (i32, [P, P, i64, P]),
+    "rg_index_tombstones": (i32, [P, PP, ctypes.POINTER(i64)]),
     "rg_index_info": (i32, [P, ctypes.POINTER(i64), ctypes.POINTER(i32), ctypes.POINTER(i32),
                             ctypes.POINTER(i32), ctypes.POINTER(i64)]),
     "rg_index_set_storage": (i32, [P, i32, P]),
@@ -127,9 +130,13 @@ def as_u32(t) -> np.ndarray:
 class Index:
     """Owns an rg_index handle."""
 
-    def __init__(self, handle, keep=None):
+    def __init__(self, handle, keep=None, on_device=True):
         self.h = handle
         self._keep = keep
+        self.on_device = on_device   # False: built on the host alone (rg_build_from_knn)
+
+    def _st(self, stream):
+        return _stream(stream) if self.on_device else ctypes.c_void_p(None)
 
     def __del__(self):
         if getattr(self, "h", None):
@@ -162,17 +169,36 @@ class Index:
         return o, x, int(entry.value)
 
     def bipartite(self):
-        """(bridge_offsets n+1, bridges nt, nout nt x (Nq-1)) copies of G_bi."""
-        bo, bi, no = ctypes.c_void_p(), ctypes.c_void_p(), ctypes.c_void_p()
-        nt, q1 = i64(), i32()
-        _check(lib().rg_index_bipartite(self.h, ctypes.byref(bo), ctypes.byref(bi), ctypes.byref(no),
-                                        ctypes.byref(nt), ctypes.byref(q1)))
-        n = self.info()["n"]
-        b_off = np.ctypeslib.as_array(ctypes.cast(bo, ctypes.POINTER(ctypes.c_int64)), (n + 1,)).copy()
+        """(bridge_offsets, bridges, nout_offsets, nout) copies of G_bi (N_out lists include inserted rows)."""
+        bo, bi, no, nx = ctypes.c_void_p(), ctypes.c_void_p(), ctypes.c_void_p(), ctypes.c_void_p()
+        nb, nt = i64(), i64()
+        _check(lib().rg_index_bipartite(self.h, ctypes.byref(bo), ctypes.byref(bi), ctypes.byref(nb), ctypes.byref(no),
+                                        ctypes.byref(nx), ctypes.byref(nt)))
+        b_off = np.ctypeslib.as_array(ctypes.cast(bo, ctypes.POINTER(ctypes.c_int64)), (nb.value + 1,)).copy()
         b_idx = np.ctypeslib.as_array(ctypes.cast(bi, ctypes.POINTER(ctypes.c_uint32)), (nt.value,)).copy()
-        nout = np.ctypeslib.as_array(ctypes.cast(no, ctypes.POINTER(ctypes.c_uint32)),
-                                     (nt.value * q1.value,)).copy().reshape(nt.value, q1.value)
-        return b_off, b_idx, nout
+        n_off = np.ctypeslib.as_array(ctypes.cast(no, ctypes.POINTER(ctypes.c_int64)), (nt.value + 1,)).copy()
+        nout = np.ctypeslib.as_array(ctypes.cast(nx, ctypes.POINTER(ctypes.c_uint32)), (int(n_off[-1]),)).copy()
+        return b_off, b_idx, n_off, nout
+
+    def insert(self, vectors, L=0, stream=None):
+        """Insert host vectors (nv x d); returns their new ids."""
+        V = np.ascontiguousarray(vectors, dtype=np.float32)
+        n0 = self.info()["n"]
+        _check(lib().rg_insert(self.h, V.ctypes.data_as(P), V.shape[0], int(L), self._st(stream)))
+        return np.arange(n0, n0 + V.shape[0], dtype=np.uint32)
+
+    def delete(self, ids, stream=None):
+        a = np.ascontiguousarray(ids, dtype=np.uint32)
+        _check(lib().rg_delete(self.h, a.ctypes.data_as(P), a.size, self._st(stream)))
+
+    def tombstones(self):
+        """(bitmap words copy or None, number deleted)."""
+        b, c = ctypes.c_void_p(), i64()
+        _check(lib().rg_index_tombstones(self.h, ctypes.byref(b), ctypes.byref(c)))
+        if not b.value:
+            return None, c.value
+        n = self.info()["n"]
+        return np.ctypeslib.as_array(ctypes.cast(b, ctypes.POINTER(ctypes.c_uint32)), ((n + 31) // 32,)).copy(), c.value
 
     def info(self):
         n, d, pitch, ell, b = i64(), i32(), i32(), i32(), i64()
@@ -205,17 +231,24 @@ def rg_build(base, train, Nq, M, L_build=0, m_pj=0, m_ce=0, threads=0, knn_slack
     return Index(h)
 
 
-def rg_build_from_knn(base_host, knn_host, Nq, M, L_build=0, m_pj=0, m_ce=0, threads=0, keep_stages=False) -> Index:
+def rg_build_from_knn(base_host, knn_host, Nq, M, L_build=0, m_pj=0, m_ce=0, threads=0, keep_stages=False,
+                      train_host=None) -> Index:
     """Host-only construction from precomputed kNN lists (numpy inputs)."""
     X = np.ascontiguousarray(base_host, dtype=np.float32)
     K = np.ascontiguousarray(knn_host, dtype=np.uint32)
     if K.ndim != 2 or K.shape[1] != Nq:
         raise ValueError("knn_host must be nt x Nq")
+    Tp = None
+    if train_host is not None:
+        Tr = np.ascontiguousarray(train_host, dtype=np.float32)
+        if Tr.shape != (K.shape[0], X.shape[1]):
+            raise ValueError("train_host must be nt x d")
+        Tp = Tr.ctypes.data_as(P)
     o = rg_build_opts(L_build, m_pj, m_ce, threads, 0, int(bool(keep_stages)))
     h = ctypes.c_void_p()
-    _check(lib().rg_build_from_knn(X.ctypes.data_as(P), X.shape[0], X.shape[1], K.ctypes.data_as(P), K.shape[0],
+    _check(lib().rg_build_from_knn(X.ctypes.data_as(P), X.shape[0], X.shape[1], K.ctypes.data_as(P), Tp, K.shape[0],
                                    int(Nq), int(M), ctypes.byref(o), ctypes.byref(h)))
-    return Index(h)
+    return Index(h, on_device=False)
 
 
 def rg_index_from_csr(base, offsets, indices, entry, stream=None) -> Index:

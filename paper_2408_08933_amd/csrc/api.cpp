@@ -61,12 +61,14 @@ void free_index_device(rg_index *ix) {
     if (ix->d_base) (void)hipFree(ix->d_base);
     if (ix->d_adj) (void)hipFree(ix->d_adj);
     if (ix->d_adj_off) (void)hipFree(ix->d_adj_off);
+    if (ix->d_tomb) (void)hipFree(ix->d_tomb);
     if (ix->d_bf16) (void)hipFree(ix->d_bf16);
     if (ix->d_fp8) (void)hipFree(ix->d_fp8);
     if (ix->d_scale) (void)hipFree(ix->d_scale);
     ix->d_base = nullptr;
     ix->d_adj = nullptr;
     ix->d_adj_off = nullptr;
+    ix->d_tomb = nullptr;
     ix->d_bf16 = nullptr;
     ix->d_fp8 = nullptr;
     ix->d_scale = nullptr;
@@ -138,6 +140,7 @@ SearchArgs search_args(const rg_index *ix, const float *queries, int64_t nq, int
     a.scale_fp8 = ix->d_scale;
     a.adj = ix->d_adj;
     a.adj_off = ix->d_adj_off;
+    a.tomb = ix->d_tomb;
     a.queries = queries;
     a.out_ids = ids;
     a.out_d = dists;
@@ -360,8 +363,10 @@ int rg_build(const float *base, int64_t n, int32_t d, const float *train, int64_
     if (std::getenv("RG_LOG"))
         std::fprintf(stderr, "[rg] kNN preprocessing done in %.2f s\n",
                      std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count());
-    th.clear();
-    th.shrink_to_fit();
+    if (!o.keep_stages) {
+        th.clear();
+        th.shrink_to_fit();
+    }
     const auto t1 = std::chrono::steady_clock::now();
     rg_index *ix = new rg_index();
     ix->n = n;
@@ -386,6 +391,10 @@ int rg_build(const float *base, int64_t n, int32_t d, const float *train, int64_
         ix->offsets.swap(g.offsets);
         ix->indices.swap(g.indices);
         ix->stages = std::move(g.stages);
+        if (ix->stages.kept) {
+            ix->stages.base.swap(xh);
+            ix->stages.train.swap(th);
+        }
         rc = upload_adj(ix, st);
     }
     if (rc) {
@@ -402,8 +411,9 @@ int rg_build(const float *base, int64_t n, int32_t d, const float *train, int64_
     return RG_OK;
 }
 
-int rg_build_from_knn(const float *base_host, int64_t n, int32_t d, const uint32_t *knn_host, int64_t nt,
-                      int32_t Nq, int32_t M, const rg_build_opts *opts, rg_index **out) {
+int rg_build_from_knn(const float *base_host, int64_t n, int32_t d, const uint32_t *knn_host,
+                      const float *train_host, int64_t nt, int32_t Nq, int32_t M, const rg_build_opts *opts,
+                      rg_index **out) {
     if (!base_host || !knn_host || !out || n < 1 || n >= (1ll << 31) || d < 1 || nt < 1 || Nq < 2 || Nq > n ||
         M < 3 || M > kMaxEll) {
         set_error("rg_build_from_knn: invalid argument");
@@ -441,6 +451,10 @@ int rg_build_from_knn(const float *base_host, int64_t n, int32_t d, const uint32
     ix->offsets.swap(g.offsets);
     ix->indices.swap(g.indices);
     ix->stages = std::move(g.stages);
+    if (ix->stages.kept) {
+        ix->stages.base.assign(base_host, base_host + n * d);
+        if (train_host) ix->stages.train.assign(train_host, train_host + nt * d);
+    }
     ix->t_project = g.t_project;
     ix->t_enhance = g.t_enhance;
     ix->t_total = g.t_total;
@@ -513,17 +527,187 @@ int rg_index_stage_graph(const rg_index *ix, int32_t stage, const int64_t **offs
 }
 
 int rg_index_bipartite(const rg_index *ix, const int64_t **bridge_offsets, const uint32_t **bridges,
-                       const uint32_t **nout, int64_t *nt, int32_t *nout_len) {
+                       int64_t *n_built, const int64_t **nout_offsets, const uint32_t **nout, int64_t *nt) {
     if (!ix || !ix->stages.kept) {
         set_error("rg_index_bipartite: the build did not keep its stage graphs (keep_stages)");
         return RG_EINVAL;
     }
     const StageGraphs &sg = ix->stages;
+    if (sg.nout_view_off.empty()) {  // N_out(t) as built, then the ids inserted into it
+        sg.nout_view_off.assign((size_t)sg.nt + 1, 0);
+        for (int64_t t = 0; t < sg.nt; ++t)
+            sg.nout_view_off[t + 1] =
+                sg.nout_view_off[t] + sg.q1 + (sg.nout_add.empty() ? 0 : (int64_t)sg.nout_add[t].size());
+        sg.nout_view_idx.resize((size_t)sg.nout_view_off[sg.nt]);
+        for (int64_t t = 0; t < sg.nt; ++t) {
+            auto o = std::copy(sg.nout.begin() + t * sg.q1, sg.nout.begin() + (t + 1) * sg.q1,
+                               sg.nout_view_idx.begin() + sg.nout_view_off[t]);
+            if (!sg.nout_add.empty()) std::copy(sg.nout_add[t].begin(), sg.nout_add[t].end(), o);
+        }
+    }
     if (bridge_offsets) *bridge_offsets = sg.b_off.data();
     if (bridges) *bridges = sg.b_idx.data();
-    if (nout) *nout = sg.nout.data();
+    if (n_built) *n_built = sg.n_built;
+    if (nout_offsets) *nout_offsets = sg.nout_view_off.data();
+    if (nout) *nout = sg.nout_view_idx.data();
     if (nt) *nt = sg.nt;
-    if (nout_len) *nout_len = sg.q1;
+    return RG_OK;
+}
+
+// Grow the device base by nv rows taken from host memory; the reduced-
+// precision copies are dropped (they are made again for the new size).
+int grow_device_base(rg_index *ix, const float *rows_host, int64_t nv, hipStream_t st) {
+    DevBuf tmp;
+    int rc = tmp.alloc(sizeof(float) * (size_t)nv * ix->d);
+    if (rc) return rc;
+    RG_HIP(hipMemcpyAsync(tmp.p, rows_host, sizeof(float) * (size_t)nv * ix->d, hipMemcpyHostToDevice, st));
+    float *nb = nullptr;
+    if (hipMalloc(&nb, sizeof(float) * (size_t)(ix->n + nv) * ix->pitch) != hipSuccess) {
+        set_error("insert: out of device memory for the base rows");
+        return RG_ENOMEM;
+    }
+    if (hipMemcpyAsync(nb, ix->d_base, sizeof(float) * (size_t)ix->n * ix->pitch, hipMemcpyDeviceToDevice, st) !=
+            hipSuccess ||
+        launch_pad_rows(tmp.as<float>(), nv, ix->d, nb + (size_t)ix->n * ix->pitch, ix->pitch, st) != RG_OK ||
+        hipStreamSynchronize(st) != hipSuccess) {
+        (void)hipFree(nb);
+        set_error("insert: device copy of the base rows failed");
+        return RG_EDEVICE;
+    }
+    (void)hipFree(ix->d_base);
+    ix->d_base = nb;
+    for (void **p : {(void **)&ix->d_bf16, (void **)&ix->d_fp8, (void **)&ix->d_scale})
+        if (*p) {
+            (void)hipFree(*p);
+            *p = nullptr;
+        }
+    return RG_OK;
+}
+
+int upload_tomb(rg_index *ix, hipStream_t st) {
+    if (ix->d_tomb) (void)hipFree(ix->d_tomb);
+    ix->d_tomb = nullptr;
+    if (ix->n_deleted == 0 || !ix->d_base) return RG_OK;
+    if (hipMalloc(&ix->d_tomb, sizeof(uint32_t) * ix->tomb.size()) != hipSuccess) {
+        ix->d_tomb = nullptr;
+        set_error("delete: out of device memory for the tombstones");
+        return RG_ENOMEM;
+    }
+    RG_HIP(hipMemcpyAsync(ix->d_tomb, ix->tomb.data(), sizeof(uint32_t) * ix->tomb.size(), hipMemcpyHostToDevice, st));
+    RG_HIP(hipStreamSynchronize(st));
+    return RG_OK;
+}
+
+int rg_insert(rg_index *ix, const float *vectors, int64_t nv, int32_t L, void *stream) {
+    if (!ix || nv < 0 || (nv > 0 && !vectors) || L < 0 || L > kMaxL) {
+        set_error("rg_insert: invalid argument");
+        return RG_EINVAL;
+    }
+    StageGraphs &sg = ix->stages;
+    if (!sg.kept || sg.train.empty()) {
+        set_error("rg_insert: needs an index built with keep_stages (and, from kNN lists, the training queries)");
+        return RG_EINVAL;
+    }
+    if (ix->n + nv >= (1ll << 31)) {
+        set_error("rg_insert: too many rows");
+        return RG_EINVAL;
+    }
+    if (nv == 0) return RG_OK;
+    if (L == 0) L = ix->L_build;
+    hipStream_t st = (hipStream_t)stream;
+    // the reduced-precision copies are remade for the new size at the end;
+    // until then the index searches its FP32 rows
+    const int32_t storage = ix->storage;
+    ix->storage = RG_STORE_FP32;
+    const int64_t n0 = ix->n;
+    const int32_t d = ix->d;
+    sg.base.insert(sg.base.end(), vectors, vectors + nv * d);
+    std::vector<uint32_t> qid((size_t)nv * L);
+    std::vector<int32_t> qn((size_t)nv);
+    int rc = RG_OK;
+    if (ix->d_base) {
+        // canonical searches of the new rows on the device, graph as it stands
+        if (ix->d_adj_off) {
+            set_error("rg_insert: the index graph is held as CSR (out-degree > 128)");
+            return RG_EINVAL;
+        }
+        rc = grow_device_base(ix, vectors, nv, st);
+        if (rc) {
+            sg.base.resize((size_t)n0 * d);
+            return rc;
+        }
+        const int64_t B = std::min<int64_t>(nv, 1 << 15);
+        DevBuf di, dd, dn;
+        rc = di.alloc(sizeof(uint32_t) * B * L);
+        if (!rc) rc = dd.alloc(sizeof(double) * B * L);
+        if (!rc) rc = dn.alloc(sizeof(int32_t) * B);
+        for (int64_t x0 = 0; x0 < nv && !rc; x0 += B) {
+            const int64_t cnt = std::min(B, nv - x0);
+            rc = launch_canon_search(ix->d_base, d, ix->pitch, ix->d_adj, ix->ell, ix->entry, L, n0 + x0, cnt,
+                                     di.as<uint32_t>(), dd.as<double>(), dn.as<int32_t>(), st);
+            if (!rc && (hipMemcpyAsync(qid.data() + x0 * L, di.p, sizeof(uint32_t) * cnt * L, hipMemcpyDeviceToHost,
+                                       st) != hipSuccess ||
+                        hipMemcpyAsync(qn.data() + x0, dn.p, sizeof(int32_t) * cnt, hipMemcpyDeviceToHost, st) !=
+                            hipSuccess ||
+                        hipStreamSynchronize(st) != hipSuccess)) {
+                set_error("rg_insert: device search failed");
+                rc = RG_EDEVICE;
+            }
+        }
+    } else {
+        host_canon_searches(sg.base.data(), d, ix->offsets.data(), ix->indices.data(), ix->entry, L, n0, nv, 0,
+                            qid.data(), qn.data());
+    }
+    if (!rc)
+        rc = host_insert(sg, d, ix->M, ix->m_pj, L, ix->entry, n0, nv, qid.data(), qn.data(), ix->offsets,
+                         ix->indices);
+    if (rc) {
+        sg.base.resize((size_t)n0 * d);
+        return rc;
+    }
+    ix->n = n0 + nv;
+    if (!ix->tomb.empty()) ix->tomb.resize((size_t)((ix->n + 31) / 32), 0u);
+    if (ix->d_base) {
+        if (ix->d_adj) (void)hipFree(ix->d_adj);
+        ix->d_adj = nullptr;
+        rc = upload_adj(ix, st);
+        if (!rc) rc = upload_tomb(ix, st);
+        if (!rc && storage != RG_STORE_FP32) rc = rg_index_set_storage(ix, storage, stream);
+    } else {
+        ix->storage = storage;
+    }
+    return rc;
+}
+
+int rg_delete(rg_index *ix, const uint32_t *ids, int64_t count, void *stream) {
+    if (!ix || count < 0 || (count > 0 && !ids)) {
+        set_error("rg_delete: invalid argument");
+        return RG_EINVAL;
+    }
+    for (int64_t i = 0; i < count; ++i)
+        if (ids[i] >= (uint64_t)ix->n) {
+            set_error("rg_delete: id out of range");
+            return RG_EINVAL;
+        }
+    if (ix->tomb.empty()) ix->tomb.assign((size_t)((ix->n + 31) / 32), 0u);
+    for (int64_t i = 0; i < count; ++i) {
+        uint32_t &w = ix->tomb[ids[i] >> 5];
+        const uint32_t bit = 1u << (ids[i] & 31u);
+        if (!(w & bit)) {
+            w |= bit;
+            ++ix->n_deleted;
+        }
+    }
+    return upload_tomb(ix, (hipStream_t)stream);
+}
+
+int rg_index_tombstones(const rg_index *ix, const uint32_t **bits, int64_t *count) {
+    if (!ix) {
+        set_error("rg_index_tombstones: null index");
+        return RG_EINVAL;
+    }
+    if (bits) *bits = ix->tomb.empty() ? nullptr : ix->tomb.data();
+    if (count) *count = ix->n_deleted;
     return RG_OK;
 }
 

@@ -394,13 +394,45 @@ __device__ __forceinline__ void rerank_queue(const SearchArgs &a, const Lds &s, 
     __syncthreads();
 }
 
+// The k results: the first k entries of the final queue that are not
+// deleted (a tombstoned node still routes the search but is never
+// returned), padded with kNone / +inf.
+__device__ __forceinline__ void emit_topk(const SearchArgs &a, const Lds &s, int qn, uint32_t *ids, float *ds) {
+    const int lane = lane_id();
+    if (!a.tomb) {
+        for (int i = lane; i < a.k; i += 64) {
+            ids[i] = i < qn ? (s.qi[i] & ~kExpanded) : kNone;
+            ds[i] = i < qn ? s.qd[i] : __builtin_inff();
+        }
+        return;
+    }
+    int w = 0;
+    for (int b0 = 0; b0 < qn && w < a.k; b0 += 64) {
+        const int i = b0 + lane;
+        uint32_t u = kNone;
+        bool alive = false;
+        if (i < qn) {
+            u = s.qi[i] & ~kExpanded;
+            alive = ((a.tomb[u >> 5] >> (u & 31u)) & 1u) == 0u;
+        }
+        const uint64_t m = ballot64(alive);
+        const int pos = w + lanes_below(m);
+        if (alive && pos < a.k) {
+            ids[pos] = u;
+            ds[pos] = s.qd[i];
+        }
+        w += (int)__popcll(m);
+    }
+    for (int i = min(w, a.k) + lane; i < a.k; i += 64) {
+        ids[i] = kNone;
+        ds[i] = __builtin_inff();
+    }
+}
+
 __device__ __forceinline__ void write_result(const SearchArgs &a, const Lds &s, int64_t q, int qn, uint32_t hops,
                                              uint32_t evals) {
     const int lane = lane_id();
-    for (int i = lane; i < a.k; i += 64) {
-        a.out_ids[q * a.k + i] = i < qn ? (s.qi[i] & ~kExpanded) : kNone;
-        a.out_d[q * a.k + i] = i < qn ? s.qd[i] : __builtin_inff();
-    }
+    emit_topk(a, s, qn, a.out_ids + q * a.k, a.out_d + q * a.k);
     if (lane == 0) {
         if (a.out_hops) a.out_hops[q] = hops;
         if (a.out_evals) a.out_evals[q] = evals;
@@ -496,10 +528,7 @@ __global__ __launch_bounds__(64) void k_serve_step(SlotArgs sa) {
         if (lane == 0) pos = (int)atomicAdd(sa.out_count, 1u);
         pos = __shfl(pos, 0);
         ServeRecord *r = sa.out_rec + pos;
-        for (int i = lane; i < a.k; i += 64) {
-            r->ids[i] = i < qn ? (s.qi[i] & ~kExpanded) : kNone;
-            r->d[i] = i < qn ? s.qd[i] : __builtin_inff();
-        }
+        emit_topk(a, s, qn, r->ids, r->d);
         if (lane == 0) {
             r->slot = slot;
             r->qn = qn;

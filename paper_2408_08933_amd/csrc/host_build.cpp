@@ -642,6 +642,7 @@ int host_construct(const float *X, int64_t n, int32_t d, const uint32_t *knn, in
         sg.kept = true;
         sg.nt = nt;
         sg.q1 = q1;
+        sg.n_built = n;
         sg.nout.resize((size_t)nt * q1);
         for (int64_t t = 0; t < nt; ++t)
             std::copy(knn + t * Nq + 1, knn + (t + 1) * Nq, sg.nout.begin() + t * q1);
@@ -668,6 +669,166 @@ int host_construct(const float *X, int64_t n, int32_t d, const uint32_t *knn, in
     out->t_project = secs(t0, t1);
     out->t_enhance = secs(t1, t2);
     out->t_total = secs(t0, t3);
+    return RG_OK;
+}
+
+void host_canon_searches(const float *X, int32_t d, const int64_t *off, const uint32_t *idx, uint32_t entry,
+                         int32_t L, int64_t x0, int64_t count, int threads, uint32_t *ids, int32_t *counts) {
+    const int64_t n = x0;  // graph nodes are the rows before x0
+    threads = hw_threads(threads);
+    std::vector<Searcher> sr((size_t)threads);
+    parallel_for(count, threads, 8, [&](int64_t i, int tid) {
+        Searcher &s = sr[tid];
+        if (s.stamp.empty()) s.init(n, L);
+        const int qn = s.run(X, d, off, idx, entry, X + (x0 + i) * d, L);
+        counts[i] = qn;
+        std::copy(s.qi.begin(), s.qi.begin() + qn, ids + i * L);
+    });
+}
+
+// Insertion through the saved bipartite graph (the paper's update
+// procedure), one new row v at a time in input order:
+//   1. b = the first node of v's queue that is joined to a query node (b is
+//      the pivot of t, or b is in N_out(t)); q = the nearest such t to v by
+//      (delta(v, t), t).  Without any, v's candidates are its queue.
+//   2. Project the sub-bipartite graph N_out(q) u {q, v} with v as pivot:
+//      candidates N_out(q) ranked by (delta(v, c), c), cut to L,
+//      AcquireNeighbors with fill to m_pj -> v's row.
+//   3. Merge: each selected p, in order, gains p -> v while its row holds
+//      fewer than M entries.  If none did, v gets one in-edge by the build's
+//      repair rule (first queue node with a free slot, else the first node
+//      in BFS order from the entry).
+//   4. Append v to N_out(q).
+int host_insert(StageGraphs &sg, int32_t d, int32_t M, int32_t m_pj, int32_t L, uint32_t entry, int64_t n0,
+                int64_t nv, const uint32_t *queue_ids, const int32_t *queue_n, std::vector<int64_t> &offsets,
+                std::vector<uint32_t> &indices) {
+    const float *X = sg.base.data();
+    const float *T = sg.train.data();
+    const int64_t nb = sg.n_built, q1 = sg.q1;
+    if (sg.inq_off.empty()) {  // queries holding each built node in N_out
+        sg.inq_off.assign((size_t)nb + 1, 0);
+        for (int64_t e = 0; e < sg.nt * q1; ++e) sg.inq_off[sg.nout[e] + 1]++;
+        for (int64_t x = 0; x < nb; ++x) sg.inq_off[x + 1] += sg.inq_off[x];
+        sg.inq_idx.resize((size_t)sg.inq_off[nb]);
+        std::vector<int64_t> fp(sg.inq_off.begin(), sg.inq_off.end() - 1);
+        for (int64_t t = 0; t < sg.nt; ++t)
+            for (int64_t j = 0; j < q1; ++j) sg.inq_idx[fp[sg.nout[t * q1 + j]]++] = (uint32_t)t;
+        sg.nout_add.assign((size_t)sg.nt, {});
+    }
+    sg.inq_add.resize((size_t)(n0 + nv - nb));
+    std::vector<std::vector<uint32_t>> add((size_t)(n0 + nv));  // ids appended to existing rows
+    std::vector<std::vector<uint32_t>> fresh((size_t)nv);       // rows of the new nodes
+    auto degree = [&](int64_t p) -> int64_t {
+        const int64_t base = p < n0 ? offsets[p + 1] - offsets[p] : (int64_t)fresh[p - n0].size();
+        return base + (int64_t)add[p].size();
+    };
+    auto joined = [&](uint32_t b, std::vector<uint32_t> &out) {
+        out.clear();
+        if ((int64_t)b < nb) {
+            for (int64_t e = sg.b_off[b]; e < sg.b_off[b + 1]; ++e) out.push_back(sg.b_idx[e]);
+            for (int64_t e = sg.inq_off[b]; e < sg.inq_off[b + 1]; ++e) out.push_back(sg.inq_idx[e]);
+        } else {
+            for (uint32_t t : sg.inq_add[b - nb]) out.push_back(t);
+        }
+    };
+    std::vector<uint32_t> qs;
+    std::vector<Cand> cand, res((size_t)std::max(m_pj, 1));
+    std::vector<uint8_t> kept;
+    for (int64_t i = 0; i < nv; ++i) {
+        const int64_t v = n0 + i;
+        const float *xv = X + v * d;
+        const uint32_t *queue = queue_ids + i * L;
+        const int qn = queue_n[i];
+        int64_t q = -1;
+        for (int j = 0; j < qn && q < 0; ++j) {
+            joined(queue[j], qs);
+            if (qs.empty()) continue;
+            double best = INFINITY;
+            for (uint32_t t : qs) {
+                const double dt = canon_dist(xv, T + (int64_t)t * d, d);
+                if (q < 0 || dt < best || (dt == best && t < (uint32_t)q)) {
+                    best = dt;
+                    q = t;
+                }
+            }
+        }
+        cand.clear();
+        if (q >= 0) {
+            for (int64_t j = 0; j < q1; ++j) cand.push_back(Cand{0.0, sg.nout[q * q1 + j]});
+            for (uint32_t u : sg.nout_add[q]) cand.push_back(Cand{0.0, u});
+        } else {
+            for (int j = 0; j < qn; ++j) cand.push_back(Cand{0.0, queue[j]});
+        }
+        for (Cand &c : cand) c.d = canon_dist(xv, X + (int64_t)c.id * d, d);
+        std::sort(cand.begin(), cand.end(), cless);
+        cand.erase(std::unique(cand.begin(), cand.end(), [](const Cand &a, const Cand &b) { return a.id == b.id; }),
+                   cand.end());
+        const int nc = (int)std::min<int64_t>((int64_t)cand.size(), L);
+        const int ns = acquire_sorted(X, d, cand.data(), nc, m_pj, true, res.data(), kept);
+        auto &row = fresh[i];
+        for (int j = 0; j < ns; ++j) row.push_back(res[j].id);
+        bool took = false;
+        for (int j = 0; j < ns; ++j) {
+            const uint32_t p = res[j].id;
+            if (degree(p) < M) {
+                add[p].push_back((uint32_t)v);
+                took = true;
+            }
+        }
+        std::sort(row.begin(), row.end());
+        if (!took) {
+            int64_t r = -1;
+            for (int j = 0; j < qn && r < 0; ++j)
+                if (degree(queue[j]) < M) r = queue[j];
+            if (r < 0) {  // BFS from the entry over the graph as it stands, neighbours ascending
+                std::vector<uint8_t> seen((size_t)v, 0);
+                std::vector<uint32_t> order{entry};
+                seen[entry] = 1;
+                for (size_t h = 0; h < order.size() && r < 0; ++h) {
+                    const uint32_t x = order[h];
+                    if (degree(x) < M) {
+                        r = x;
+                        break;
+                    }
+                    auto visit = [&](uint32_t w) {
+                        if (!seen[w]) {
+                            seen[w] = 1;
+                            order.push_back(w);
+                        }
+                    };
+                    if ((int64_t)x < n0)
+                        for (int64_t e = offsets[x]; e < offsets[x + 1]; ++e) visit(indices[e]);
+                    else
+                        for (uint32_t w : fresh[x - n0]) visit(w);
+                    for (uint32_t w : add[x]) visit(w);
+                }
+            }
+            if (r < 0) {
+                set_error("insert: no node with a free slot");
+                return RG_EINTERNAL;
+            }
+            add[r].push_back((uint32_t)v);
+        }
+        if (q >= 0) {
+            sg.nout_add[q].push_back((uint32_t)v);
+            sg.inq_add[v - nb].push_back((uint32_t)q);
+        }
+    }
+    // rows of old nodes gain only new (larger) ids, in increasing order
+    std::vector<int64_t> off2((size_t)(n0 + nv) + 1, 0);
+    for (int64_t x = 0; x < n0 + nv; ++x) off2[x + 1] = off2[x] + degree(x);
+    std::vector<uint32_t> idx2((size_t)off2[n0 + nv]);
+    for (int64_t x = 0; x < n0 + nv; ++x) {
+        auto o = idx2.begin() + off2[x];
+        if (x < n0)
+            o = std::copy(indices.begin() + offsets[x], indices.begin() + offsets[x + 1], o);
+        else
+            o = std::copy(fresh[x - n0].begin(), fresh[x - n0].end(), o);
+        std::copy(add[x].begin(), add[x].end(), o);
+    }
+    offsets.swap(off2);
+    indices.swap(idx2);
+    sg.nout_view_off.clear();
     return RG_OK;
 }
 

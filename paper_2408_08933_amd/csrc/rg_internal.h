@@ -36,6 +36,7 @@ struct SearchArgs {
     const float *scale_fp8;     // per-row power-of-two scales
     const uint32_t *adj;        // ELL adjacency, n x ell, kNone padded; or CSR indices
     const int64_t *adj_off;     // CSR offsets (n + 1), or null for ELL
+    const uint32_t *tomb;       // deleted-node bitmap (ceil(n/32) words), or null
     const float *queries;       // nq x d
     uint32_t *out_ids;          // nq x k
     float *out_d;               // nq x k
@@ -116,11 +117,15 @@ int launch_copy_probe(void *dst, const void *src, int64_t bytes, hipStream_t str
 // out-lists N_out(t) of the training queries without their pivot), its
 // base-to-base routing rows (row x = N_out(t) for each t in B(x)) with their
 // entry, and the projected graph G_pj (rows sorted by neighbour id).
+// Insertion (updates through the saved bipartite graph) also needs the
+// vectors on the host, the ids appended to each N_out(t) since the build,
+// and, per base node, the queries whose N_out holds it.
 struct StageGraphs {
     bool kept = false;
     int64_t nt = 0;
     int32_t q1 = 0;
-    std::vector<int64_t> b_off;
+    int64_t n_built = 0;
+    std::vector<int64_t> b_off;  // n_built + 1
     std::vector<uint32_t> b_idx;
     std::vector<uint32_t> nout;  // nt x q1
     std::vector<int64_t> bi_off;
@@ -128,6 +133,15 @@ struct StageGraphs {
     uint32_t entry_bi = 0;
     std::vector<int64_t> pj_off;
     std::vector<uint32_t> pj_idx;
+    // updates
+    std::vector<float> base;                       // n x d, grows with insertions
+    std::vector<float> train;                      // nt x d (empty: no insertion)
+    std::vector<std::vector<uint32_t>> nout_add;   // per query: inserted ids appended to N_out(t)
+    std::vector<int64_t> inq_off;                  // per built node: queries t with x in N_out(t)
+    std::vector<uint32_t> inq_idx;
+    std::vector<std::vector<uint32_t>> inq_add;    // per inserted node: the query it joined
+    mutable std::vector<int64_t> nout_view_off;    // full N_out(t) lists as CSR (rg_index_bipartite),
+    mutable std::vector<uint32_t> nout_view_idx;   // made on request, dropped by an insertion
 };
 
 struct HostGraph {
@@ -149,6 +163,19 @@ struct GpuCtx {
 int host_construct(const float *X, int64_t n, int32_t d, const uint32_t *knn, int64_t nt,
                    int32_t Nq, int32_t M, int32_t L, int32_t m_pj, int32_t m_ce, int threads,
                    const GpuCtx *gpu, bool keep_stages, HostGraph *out);
+
+// Insertion (updates through the saved bipartite graph).  The nv new rows
+// are already appended to sg.base (ids n0 .. n0+nv-1); queue_ids / queue_n
+// hold each new row's canonical search queue (L entries per row) on the
+// graph (offsets, indices) as it stood before the call.  Updates the graph
+// in place to n0 + nv rows.
+int host_insert(StageGraphs &sg, int32_t d, int32_t M, int32_t m_pj, int32_t L, uint32_t entry, int64_t n0,
+                int64_t nv, const uint32_t *queue_ids, const int32_t *queue_n, std::vector<int64_t> &offsets,
+                std::vector<uint32_t> &indices);
+// Canonical searches of rows x0 .. x0+count-1 of X (host) on a host CSR
+// graph, queue length L, on host threads (indexes without device data).
+void host_canon_searches(const float *X, int32_t d, const int64_t *off, const uint32_t *idx, uint32_t entry,
+                         int32_t L, int64_t x0, int64_t count, int threads, uint32_t *ids, int32_t *counts);
 
 // canon.hip: construction-time searches with the canonical FP64 distance
 int launch_canon_search(const float *X, int32_t d, int32_t pitch, const uint32_t *adj, int32_t ell,
@@ -180,6 +207,9 @@ struct rg_index {
     float *d_base = nullptr;          // n x pitch fp32
     uint32_t *d_adj = nullptr;        // n x ell (ELL) or nnz (CSR)
     int64_t *d_adj_off = nullptr;     // CSR offsets, null for ELL
+    uint32_t *d_tomb = nullptr;       // deleted-node bitmap, null while nothing is deleted
+    std::vector<uint32_t> tomb;       // host copy of the bitmap
+    int64_t n_deleted = 0;
     uint16_t *d_bf16 = nullptr;       // n x pitch
     uint8_t *d_fp8 = nullptr;         // n x pitch8
     float *d_scale = nullptr;         // n

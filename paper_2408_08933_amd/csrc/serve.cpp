@@ -131,6 +131,7 @@ void rg_server::loop() {
         sa.s.scale_fp8 = ix->d_scale;
         sa.s.adj = ix->d_adj;
         sa.s.adj_off = ix->d_adj_off;
+        sa.s.tomb = ix->d_tomb;
         sa.s.d = d;
         sa.s.pitch = ix->pitch;
         sa.s.pitch8 = ix->pitch8;

@@ -204,8 +204,9 @@ def test_build_bit_exact_c1(c1, c1_built):
 
 def test_build_stage_graphs_c1(oracle_lib, c1, c1_built):
     X, Tr, Q, G = c1
-    b_off, b_idx, nout = c1_built.bipartite()
-    assert np.array_equal(b_off, G.b_offsets) and np.array_equal(b_idx, G.b_indices) and np.array_equal(nout, G.nout)
+    b_off, b_idx, n_off, nout = c1_built.bipartite()
+    assert np.array_equal(b_off, G.b_offsets) and np.array_equal(b_idx, G.b_indices)
+    assert np.array_equal(nout.reshape(G.nout.shape), G.nout) and n_off[-1] == G.nout.size
     off, idx, entry = c1_built.stage_graph(rg.RG_STAGE_PROJECTED)
     assert np.array_equal(off, G.pj_offsets) and entry == G.entry
     assert np.array_equal(idx, np.concatenate([np.sort(r) for r in G.rows("pj")]))

@@ -91,9 +91,9 @@ def test_stage_graphs_bit_exact_with_oracle(oracle_lib, cfg, n, nt, Nq, M, L):
     G = oracle_lib.Graph(X, T, Nq, M, L)
     knn, _ = oracle_lib.knn(X, T, Nq)
     ix = rg.rg_build_from_knn(X, knn, Nq, M, L_build=L, keep_stages=True)
-    b_off, b_idx, nout = ix.bipartite()
+    b_off, b_idx, n_off, nout = ix.bipartite()
     assert np.array_equal(b_off, G.b_offsets) and np.array_equal(b_idx, G.b_indices)
-    assert np.array_equal(nout, G.nout)
+    assert np.array_equal(n_off, np.arange(nt + 1) * (Nq - 1)) and np.array_equal(nout.reshape(nt, Nq - 1), G.nout)
     off, idx, entry = ix.stage_graph(rg.RG_STAGE_PROJECTED)
     pj_sorted = np.concatenate([np.sort(r) for r in G.rows("pj")])
     assert np.array_equal(off, G.pj_offsets) and np.array_equal(idx, pj_sorted) and entry == G.entry
@@ -115,3 +115,80 @@ def test_stage_graphs_need_keep_stages(oracle_lib):
         ix.stage_graph(rg.RG_STAGE_PROJECTED)
     with pytest.raises(rg.RGError):
         ix.bipartite()
+
+
+# --------------------------------------------------------------------------
+# updates (Sec. 6): the library's insertion and tombstones against the oracle
+# --------------------------------------------------------------------------
+def _unit2(a):
+    import math
+    return [math.cos(math.radians(a)), math.sin(math.radians(a))]
+
+
+def test_insert_hand_worked_five_points(oracle_lib):
+    import json
+    g = json.load(open(os.path.join(ROOT, "tests", "golden", "projection_5pt.json")))
+    u = json.load(open(os.path.join(ROOT, "tests", "golden", "updates_5pt.json")))
+    X = np.array([_unit2(a) for a in g["base_angles_deg"]], np.float32)
+    T = np.array([_unit2(a) for a in g["train_angles_deg"]], np.float32)
+    knn, _ = oracle_lib.knn(X, T, g["Nq"])
+    ix = rg.rg_build_from_knn(X, knn, g["Nq"], g["M"], L_build=g["L"], keep_stages=True, train_host=T)
+    for i, a in enumerate(u["inserts_deg"]):
+        assert ix.insert(np.array([_unit2(a)], np.float32)).tolist() == [5 + i]
+    off, idx, entry = ix.graph()
+    assert [idx[off[i]:off[i + 1]].tolist() for i in range(len(off) - 1)] == u["final_rows"]
+    _, _, n_off, nout = ix.bipartite()
+    assert [nout[n_off[t]:n_off[t + 1]].tolist() for t in range(2)] == u["final_nout"]
+
+
+@pytest.mark.parametrize("batches", [[70, 50], [1, 1, 30]])
+def test_insert_bit_exact_with_oracle(oracle_lib, batches):
+    from oracle.updates import Updatable
+    gen = datagen.Generator(1, n=1500, n_train=1500, n_test=120)
+    X, T, Q = gen.base(), gen.train(), gen.test()
+    Nq, M, L = 16, 16, 120
+    G = oracle_lib.Graph(X, T, Nq, M, L)
+    knn, _ = oracle_lib.knn(X, T, Nq)
+    ix = rg.rg_build_from_knn(X, knn, Nq, M, L_build=L, keep_stages=True, train_host=T)
+    st = Updatable.from_graph(G, X, T)
+    V = np.concatenate([gen.in_distribution(60), Q])[:sum(batches)]
+    s0 = 0
+    for b in batches:
+        ix.insert(V[s0:s0 + b], L=64)
+        st.insert(V[s0:s0 + b], L=64)
+        s0 += b
+    off, idx, entry = ix.graph()
+    o2, i2 = st.csr()
+    assert np.array_equal(off, o2) and np.array_equal(idx, i2) and entry == st.entry
+    _, _, n_off, nout = ix.bipartite()
+    assert [nout[n_off[t]:n_off[t + 1]].tolist() for t in range(len(st.nout))] == st.nout
+
+
+def test_insert_needs_stages_and_training_queries(oracle_lib):
+    gen = datagen.Generator(1, n=300, n_train=300, n_test=10)
+    X, T = gen.base(), gen.train()
+    knn, _ = oracle_lib.knn(X, T, 8)
+    v = X[:2] + 0.01
+    with pytest.raises(rg.RGError):
+        rg.rg_build_from_knn(X, knn, 8, 8, L_build=50).insert(v)
+    with pytest.raises(rg.RGError):
+        rg.rg_build_from_knn(X, knn, 8, 8, L_build=50, keep_stages=True).insert(v)
+    ix = rg.rg_build_from_knn(X, knn, 8, 8, L_build=50, keep_stages=True, train_host=T)
+    assert ix.insert(np.zeros((0, X.shape[1]), np.float32)).size == 0
+    with pytest.raises(rg.RGError):
+        ix.insert(v, L=513)
+
+
+def test_delete_marks_tombstones(oracle_lib):
+    gen = datagen.Generator(1, n=300, n_train=300, n_test=10)
+    X, T = gen.base(), gen.train()
+    knn, _ = oracle_lib.knn(X, T, 8)
+    ix = rg.rg_build_from_knn(X, knn, 8, 8, L_build=50)
+    assert ix.tombstones() == (None, 0)
+    ix.delete([3, 40, 3, 299])
+    bits, cnt = ix.tombstones()
+    assert cnt == 3
+    dead = [i for i in range(300) if (bits[i >> 5] >> (i & 31)) & 1]
+    assert dead == [3, 40, 299]
+    with pytest.raises(rg.RGError):
+        ix.delete([300])
