@@ -19,11 +19,17 @@ Readings of the passage (the paper gives it in prose only):
   (delta(v, c), c) and cut to L, then AcquireNeighbors with fill to m_pj.
   In that small projected graph every selected p gains the edge p -> v.
 * Merging into the index: v's row is its selection; each selected p, in
-  selection order, gains p -> v only while its row holds fewer than M
-  entries (the degree bound stays M).  If no p took v, v gets one in-edge by
+  selection order, reconsiders its row as Algorithm 2's reverse step does:
+  row(p) <- AcquireNeighbors(p, row(p) u {v}, M) with fill (a row with room
+  simply gains v; a full row keeps the M best by the selection rule, which
+  may drop v or an old neighbour).  If no p kept v, v gets one in-edge by
   the build's repair rule: from the first node of its queue with a free
   slot, else the first node in BFS order from the entry (neighbours in
   ascending id) with a free slot.
+* At the end of the call, every node the entry no longer reaches (an old
+  neighbour dropped above can lose its last in-edge) gets one in-edge, in
+  ascending id, from the first node in BFS order with a free slot, and the
+  BFS continues from it.
 * Finally v is appended to N_out(q).  If no node of the queue is connected,
   v's candidates are its queue itself and N_out is not changed.
 * Tombstones: a deleted node stays in the graph and in every queue (it
@@ -103,9 +109,9 @@ class Updatable:
             self.rows.append(sorted(sel))
             took = False
             for p in sel:
-                if len(self.rows[p]) < self.M:
-                    self.rows[p].append(v)          # v is the largest id: rows stay sorted
-                    took = True
+                kept = acquire(self.X, p, np.array(self.rows[p] + [v], np.uint32), self.M, True)
+                self.rows[p] = sorted(int(u) for u in kept)
+                took = took or v in self.rows[p]
             if not took:
                 r = next((u for u in queue if len(self.rows[u]) < self.M), None)
                 if r is None:
@@ -115,7 +121,36 @@ class Updatable:
                 self.rows[r].append(v)
             if q is not None:
                 self.nout[q].append(v)
+        self.repair()
         return np.arange(first, first + len(V), dtype=np.uint32)
+
+    def repair(self):
+        """Reconnect every node the entry does not reach (see the module text)."""
+        seen = np.zeros(self.n, bool)
+        seen[self.entry] = True
+        order = [self.entry]
+        h = 0
+
+        def bfs(h):
+            while h < len(order):
+                for w in self.rows[order[h]]:
+                    if not seen[w]:
+                        seen[w] = True
+                        order.append(w)
+                h += 1
+            return h
+
+        h = bfs(h)
+        for u in range(self.n):
+            if seen[u]:
+                continue
+            r = next((x for x in order if len(self.rows[x]) < self.M), None)
+            if r is None:
+                raise RuntimeError("insert: no node with a free slot")
+            self.rows[r] = sorted(self.rows[r] + [u])
+            seen[u] = True
+            order.append(u)
+            h = bfs(h)
 
     def delete(self, ids):
         for u in ids:

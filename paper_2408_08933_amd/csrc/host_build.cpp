@@ -694,17 +694,21 @@ void host_canon_searches(const float *X, int32_t d, const int64_t *off, const ui
 //   2. Project the sub-bipartite graph N_out(q) u {q, v} with v as pivot:
 //      candidates N_out(q) ranked by (delta(v, c), c), cut to L,
 //      AcquireNeighbors with fill to m_pj -> v's row.
-//   3. Merge: each selected p, in order, gains p -> v while its row holds
-//      fewer than M entries.  If none did, v gets one in-edge by the build's
-//      repair rule (first queue node with a free slot, else the first node
-//      in BFS order from the entry).
+//   3. Merge as Algorithm 2's reverse step: each selected p, in order, takes
+//      row(p) <- AcquireNeighbors(p, row(p) u {v}, M) with fill (a row with
+//      room gains v; a full row keeps M by the rule).  If no p kept v, v gets
+//      one in-edge by the build's repair rule (first queue node with a free
+//      slot, else the first node in BFS order from the entry).
 //   4. Append v to N_out(q).
+// At the end, every node the entry no longer reaches (a full row may drop an
+// old neighbour) gets one in-edge, in ascending id, from the first node in
+// BFS order with a free slot.
 int host_insert(StageGraphs &sg, int32_t d, int32_t M, int32_t m_pj, int32_t L, uint32_t entry, int64_t n0,
                 int64_t nv, const uint32_t *queue_ids, const int32_t *queue_n, std::vector<int64_t> &offsets,
                 std::vector<uint32_t> &indices) {
     const float *X = sg.base.data();
     const float *T = sg.train.data();
-    const int64_t nb = sg.n_built, q1 = sg.q1;
+    const int64_t nb = sg.n_built, q1 = sg.q1, N = n0 + nv;
     if (sg.inq_off.empty()) {  // queries holding each built node in N_out
         sg.inq_off.assign((size_t)nb + 1, 0);
         for (int64_t e = 0; e < sg.nt * q1; ++e) sg.inq_off[sg.nout[e] + 1]++;
@@ -715,13 +719,10 @@ int host_insert(StageGraphs &sg, int32_t d, int32_t M, int32_t m_pj, int32_t L, 
             for (int64_t j = 0; j < q1; ++j) sg.inq_idx[fp[sg.nout[t * q1 + j]]++] = (uint32_t)t;
         sg.nout_add.assign((size_t)sg.nt, {});
     }
-    sg.inq_add.resize((size_t)(n0 + nv - nb));
-    std::vector<std::vector<uint32_t>> add((size_t)(n0 + nv));  // ids appended to existing rows
-    std::vector<std::vector<uint32_t>> fresh((size_t)nv);       // rows of the new nodes
-    auto degree = [&](int64_t p) -> int64_t {
-        const int64_t base = p < n0 ? offsets[p + 1] - offsets[p] : (int64_t)fresh[p - n0].size();
-        return base + (int64_t)add[p].size();
-    };
+    sg.inq_add.resize((size_t)(N - nb));
+    // rows, sorted by id, as they change
+    std::vector<std::vector<uint32_t>> rows((size_t)N);
+    for (int64_t x = 0; x < n0; ++x) rows[x].assign(indices.begin() + offsets[x], indices.begin() + offsets[x + 1]);
     auto joined = [&](uint32_t b, std::vector<uint32_t> &out) {
         out.clear();
         if ((int64_t)b < nb) {
@@ -731,8 +732,25 @@ int host_insert(StageGraphs &sg, int32_t d, int32_t M, int32_t m_pj, int32_t L, 
             for (uint32_t t : sg.inq_add[b - nb]) out.push_back(t);
         }
     };
+    // BFS from the entry over the current rows (neighbours ascending); the
+    // first node with a free slot, or -1
+    auto first_free_in_bfs = [&](int64_t limit) -> int64_t {
+        std::vector<uint8_t> seen((size_t)limit, 0);
+        std::vector<uint32_t> order{entry};
+        seen[entry] = 1;
+        for (size_t h = 0; h < order.size(); ++h) {
+            const uint32_t x = order[h];
+            if ((int64_t)rows[x].size() < M) return x;
+            for (uint32_t w : rows[x])
+                if (!seen[w]) {
+                    seen[w] = 1;
+                    order.push_back(w);
+                }
+        }
+        return -1;
+    };
     std::vector<uint32_t> qs;
-    std::vector<Cand> cand, res((size_t)std::max(m_pj, 1));
+    std::vector<Cand> cand, res((size_t)std::max(M, std::max(m_pj, 1)));
     std::vector<uint8_t> kept;
     for (int64_t i = 0; i < nv; ++i) {
         const int64_t v = n0 + i;
@@ -742,7 +760,6 @@ int host_insert(StageGraphs &sg, int32_t d, int32_t M, int32_t m_pj, int32_t L, 
         int64_t q = -1;
         for (int j = 0; j < qn && q < 0; ++j) {
             joined(queue[j], qs);
-            if (qs.empty()) continue;
             double best = INFINITY;
             for (uint32_t t : qs) {
                 const double dt = canon_dist(xv, T + (int64_t)t * d, d);
@@ -765,67 +782,82 @@ int host_insert(StageGraphs &sg, int32_t d, int32_t M, int32_t m_pj, int32_t L, 
                    cand.end());
         const int nc = (int)std::min<int64_t>((int64_t)cand.size(), L);
         const int ns = acquire_sorted(X, d, cand.data(), nc, m_pj, true, res.data(), kept);
-        auto &row = fresh[i];
-        for (int j = 0; j < ns; ++j) row.push_back(res[j].id);
+        std::vector<uint32_t> sel((size_t)ns);
+        for (int j = 0; j < ns; ++j) sel[j] = res[j].id;
+        rows[v] = sel;
+        std::sort(rows[v].begin(), rows[v].end());
         bool took = false;
-        for (int j = 0; j < ns; ++j) {
-            const uint32_t p = res[j].id;
-            if (degree(p) < M) {
-                add[p].push_back((uint32_t)v);
+        for (const uint32_t p : sel) {
+            auto &r = rows[p];
+            if ((int64_t)r.size() < M) {
+                r.push_back((uint32_t)v);  // v is the largest id: the row stays sorted
                 took = true;
+                continue;
             }
+            const float *xp = X + (int64_t)p * d;
+            cand.clear();
+            for (uint32_t u : r) cand.push_back(Cand{canon_dist(xp, X + (int64_t)u * d, d), u});
+            cand.push_back(Cand{canon_dist(xp, xv, d), (uint32_t)v});
+            std::sort(cand.begin(), cand.end(), cless);
+            const int nk = acquire_sorted(X, d, cand.data(), (int)cand.size(), M, true, res.data(), kept);
+            r.clear();
+            for (int j = 0; j < nk; ++j) r.push_back(res[j].id);
+            std::sort(r.begin(), r.end());
+            took = took || std::binary_search(r.begin(), r.end(), (uint32_t)v);
         }
-        std::sort(row.begin(), row.end());
         if (!took) {
             int64_t r = -1;
             for (int j = 0; j < qn && r < 0; ++j)
-                if (degree(queue[j]) < M) r = queue[j];
-            if (r < 0) {  // BFS from the entry over the graph as it stands, neighbours ascending
-                std::vector<uint8_t> seen((size_t)v, 0);
-                std::vector<uint32_t> order{entry};
-                seen[entry] = 1;
-                for (size_t h = 0; h < order.size() && r < 0; ++h) {
-                    const uint32_t x = order[h];
-                    if (degree(x) < M) {
-                        r = x;
-                        break;
-                    }
-                    auto visit = [&](uint32_t w) {
-                        if (!seen[w]) {
-                            seen[w] = 1;
-                            order.push_back(w);
-                        }
-                    };
-                    if ((int64_t)x < n0)
-                        for (int64_t e = offsets[x]; e < offsets[x + 1]; ++e) visit(indices[e]);
-                    else
-                        for (uint32_t w : fresh[x - n0]) visit(w);
-                    for (uint32_t w : add[x]) visit(w);
-                }
-            }
+                if ((int64_t)rows[queue[j]].size() < M) r = queue[j];
+            if (r < 0) r = first_free_in_bfs(v);
             if (r < 0) {
                 set_error("insert: no node with a free slot");
                 return RG_EINTERNAL;
             }
-            add[r].push_back((uint32_t)v);
+            rows[r].push_back((uint32_t)v);
         }
         if (q >= 0) {
             sg.nout_add[q].push_back((uint32_t)v);
             sg.inq_add[v - nb].push_back((uint32_t)q);
         }
     }
-    // rows of old nodes gain only new (larger) ids, in increasing order
-    std::vector<int64_t> off2((size_t)(n0 + nv) + 1, 0);
-    for (int64_t x = 0; x < n0 + nv; ++x) off2[x + 1] = off2[x] + degree(x);
-    std::vector<uint32_t> idx2((size_t)off2[n0 + nv]);
-    for (int64_t x = 0; x < n0 + nv; ++x) {
-        auto o = idx2.begin() + off2[x];
-        if (x < n0)
-            o = std::copy(indices.begin() + offsets[x], indices.begin() + offsets[x + 1], o);
-        else
-            o = std::copy(fresh[x - n0].begin(), fresh[x - n0].end(), o);
-        std::copy(add[x].begin(), add[x].end(), o);
+    // reachability after the call
+    {
+        std::vector<uint8_t> seen((size_t)N, 0);
+        std::vector<uint32_t> order{entry};
+        seen[entry] = 1;
+        size_t h = 0;
+        auto bfs = [&]() {
+            while (h < order.size()) {
+                const uint32_t x = order[h++];
+                for (uint32_t w : rows[x])
+                    if (!seen[w]) {
+                        seen[w] = 1;
+                        order.push_back(w);
+                    }
+            }
+        };
+        bfs();
+        for (int64_t u = 0; u < N; ++u) {
+            if (seen[u]) continue;
+            int64_t r = -1;
+            for (size_t j = 0; j < order.size() && r < 0; ++j)
+                if ((int64_t)rows[order[j]].size() < M) r = order[j];
+            if (r < 0) {
+                set_error("insert: no node with a free slot");
+                return RG_EINTERNAL;
+            }
+            auto &rr = rows[r];
+            rr.insert(std::upper_bound(rr.begin(), rr.end(), (uint32_t)u), (uint32_t)u);
+            seen[u] = 1;
+            order.push_back((uint32_t)u);
+            bfs();
+        }
     }
+    std::vector<int64_t> off2((size_t)N + 1, 0);
+    for (int64_t x = 0; x < N; ++x) off2[x + 1] = off2[x] + (int64_t)rows[x].size();
+    std::vector<uint32_t> idx2((size_t)off2[N]);
+    for (int64_t x = 0; x < N; ++x) std::copy(rows[x].begin(), rows[x].end(), idx2.begin() + off2[x]);
     offsets.swap(off2);
     indices.swap(idx2);
     sg.nout_view_off.clear();

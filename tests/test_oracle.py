@@ -414,10 +414,12 @@ def test_insert_invariants(oracle_lib, small_graph):
     rows = [idx[off[i]:off[i + 1]] for i in range(n)]
     assert all(len(set(r.tolist())) == len(r) and i not in r for i, r in enumerate(rows))
     assert sum(len(r) for r in st.nout) - before <= len(V)    # each v joins at most one N_out
-    # old rows only ever gain new ids
+    # a row loses a neighbour only by the selection rule on a full row, and
+    # such a row stays full
     old = G.rows("final")
-    assert all(np.array_equal(rows[i][:len(old[i])], old[i]) and (rows[i][len(old[i]):] >= G.n).all()
-               for i in range(G.n))
+    lost = [i for i in range(G.n) if set(old[i].tolist()) - set(rows[i].tolist())]
+    assert all(len(rows[i]) == G.M for i in lost)
+    assert any(len(rows[i]) > len(old[i]) for i in range(G.n))
 
 
 def test_tombstones_exact_on_complete_graph(oracle_lib):
