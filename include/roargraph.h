@@ -242,7 +242,10 @@ int rg_index_set_storage(rg_index *idx, int32_t storage, void *stream);
  * The search expands the closest unexpanded queue entry until none is left;
  * a neighbour enters the queue if the queue is not full or it beats the last
  * entry.  With reduced-precision storage the final L_eff queue is rescored
- * against the FP32 rows and the best k are returned.  Asynchronous on stream.
+ * against the FP32 rows and the best k are returned.  FP32 storage keeps an
+ * exact visited bitmap per resident query in device memory; BF16 / FP8 keep
+ * a 2^10-entry visited table in LDS that forgets and rescores (the results
+ * are the same; evals counts the rescoring).  Asynchronous on stream.
  * Errors: RG_EINVAL, RG_EDEVICE.
  */
 int rg_search(const rg_index *idx, const float *queries, int64_t nq, int32_t k, int32_t L,
@@ -325,6 +328,9 @@ typedef struct {
     int64_t hbm_pool_bytes;   /* bound on slot state bytes; 0 => no bound beyond max_slots */
     int32_t hops_per_step;    /* expansions per slot per step; 0 => 32 */
     int32_t max_L;            /* largest L_eff accepted (<= 512); 0 => 512 */
+    int32_t hash_bits;        /* visited table of 2^hash_bits ids per slot (8..13, and at least
+                                 twice the candidate batch); it bounds work, not results;
+                                 0 => 11 for FP32 storage, 9 for BF16 / FP8 */
 } rg_server_limits;
 
 typedef struct {

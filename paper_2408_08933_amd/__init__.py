@@ -36,7 +36,7 @@ class rg_build_opts(ctypes.Structure):
 
 class rg_server_limits(ctypes.Structure):
     _fields_ = [("max_slots", ctypes.c_int32), ("hbm_pool_bytes", ctypes.c_int64),
-                ("hops_per_step", ctypes.c_int32), ("max_L", ctypes.c_int32)]
+                ("hops_per_step", ctypes.c_int32), ("max_L", ctypes.c_int32), ("hash_bits", ctypes.c_int32)]
 
 
 class rg_result(ctypes.Structure):
@@ -336,9 +336,9 @@ def rg_load(path: str, stream=None) -> Index:
 class Server:
     """Continuous-batching search server over an Index (rg_server_*)."""
 
-    def __init__(self, index: Index, max_slots=1024, hbm_pool_bytes=0, hops_per_step=32, max_L=512):
+    def __init__(self, index: Index, max_slots=1024, hbm_pool_bytes=0, hops_per_step=32, max_L=512, hash_bits=0):
         self.index = index
-        lim = rg_server_limits(max_slots, hbm_pool_bytes, hops_per_step, max_L)
+        lim = rg_server_limits(max_slots, hbm_pool_bytes, hops_per_step, max_L, hash_bits)
         h = ctypes.c_void_p()
         _check(lib().rg_server_create(index.h, ctypes.byref(lim), ctypes.byref(h)))
         self.h = h

@@ -130,6 +130,9 @@ int upload_adj(rg_index *ix, hipStream_t st) {
     return RG_OK;
 }
 
+// LDS visited-table size of the BF16 / FP8 search (2^10 ids per query).
+constexpr int kReducedHashBits = 10;
+
 // Search parameters common to every search entry point.
 SearchArgs search_args(const rg_index *ix, const float *queries, int64_t nq, int32_t k, int32_t L, uint32_t *ids,
                        float *dists, uint32_t *hops, uint32_t *evals) {
@@ -153,6 +156,7 @@ SearchArgs search_args(const rg_index *ix, const float *queries, int64_t nq, int
     a.ell = ix->ell;
     a.k = k;
     a.Leff = std::max(k, L);
+    a.cand = cand_capacity(ix->ell, ix->d_adj_off != nullptr);
     a.hash_bits = 0;
     a.entry = ix->entry;
     a.storage = ix->storage;
@@ -614,6 +618,7 @@ int rg_insert(rg_index *ix, const float *vectors, int64_t nv, int32_t L, void *s
     }
     if (nv == 0) return RG_OK;
     if (L == 0) L = ix->L_build;
+    const auto t0 = std::chrono::steady_clock::now();
     hipStream_t st = (hipStream_t)stream;
     // the reduced-precision copies are remade for the new size at the end;
     // until then the index searches its FP32 rows
@@ -658,9 +663,11 @@ int rg_insert(rg_index *ix, const float *vectors, int64_t nv, int32_t L, void *s
         host_canon_searches(sg.base.data(), d, ix->offsets.data(), ix->indices.data(), ix->entry, L, n0, nv, 0,
                             qid.data(), qn.data());
     }
+    const auto t_search = std::chrono::steady_clock::now();
     if (!rc)
         rc = host_insert(sg, d, ix->M, ix->m_pj, L, ix->entry, n0, nv, qid.data(), qn.data(), ix->offsets,
-                         ix->indices);
+                         ix->indices, 0);
+    const auto t_merge = std::chrono::steady_clock::now();
     if (rc) {
         sg.base.resize((size_t)n0 * d);
         return rc;
@@ -675,6 +682,12 @@ int rg_insert(rg_index *ix, const float *vectors, int64_t nv, int32_t L, void *s
         if (!rc && storage != RG_STORE_FP32) rc = rg_index_set_storage(ix, storage, stream);
     } else {
         ix->storage = storage;
+    }
+    if (std::getenv("RG_LOG")) {
+        auto sec = [](auto a, auto b) { return std::chrono::duration<double>(b - a).count(); };
+        std::fprintf(stderr, "[rg] insert %lld rows: searches %.2f s, merge %.2f s, device update %.2f s\n",
+                     (long long)nv, sec(t0, t_search), sec(t_search, t_merge),
+                     sec(t_merge, std::chrono::steady_clock::now()));
     }
     return rc;
 }
@@ -800,7 +813,14 @@ int rg_search(const rg_index *ix, const float *queries, int64_t nq, int32_t k, i
     if (nq == 0) return RG_OK;
     hipStream_t st = (hipStream_t)stream;
     SearchArgs a = search_args(ix, queries, nq, k, L, ids, dists, hops, evals);
-    // persistent grid: as many resident workgroups as the chip holds, each
+    if (ix->storage != RG_STORE_FP32) {
+        // BF16 / FP8 rows: the search waits on memory latency, not bandwidth;
+        // a small LDS visited table (no device atomics) is faster even though
+        // it forgets and rescores some rows (same results)
+        a.hash_bits = kReducedHashBits;
+        return launch_search(a, st);
+    }
+    // FP32 rows, bandwidth bound: persistent grid: as many resident workgroups as the chip holds, each
     // with its own visited bitmap (bounded to 8 GiB in total)
     int per_cu = 0, cus = 0;
     int rc = search_occupancy(a, &per_cu);

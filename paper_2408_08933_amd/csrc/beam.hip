@@ -35,7 +35,7 @@ namespace rg {
 namespace {
 
 constexpr uint32_t kEmpty = 0xFFFFFFFFu;
-constexpr int kCand = 128;  // candidate-batch capacity (>= the largest ELL width)
+constexpr int kCand = 128;  // largest candidate batch (the widest ELL row, a CSR chunk)
 
 struct Lds {
     float *qs;      // the query, zero padded to the row pitch
@@ -49,17 +49,18 @@ struct Lds {
     uint32_t *htab;
 };
 
-__device__ __forceinline__ Lds carve(unsigned char *p, int Leff, int pitch) {
+// cand = the candidate-batch capacity of this launch (64 or 128)
+__device__ __forceinline__ Lds carve(unsigned char *p, int Leff, int pitch, int cand) {
     Lds s;
     s.qs = reinterpret_cast<float *>(p);
     s.qd = s.qs + pitch;
     s.qi = reinterpret_cast<uint32_t *>(s.qd + Leff);
     s.cd = reinterpret_cast<float *>(s.qi + Leff);
-    s.ci = reinterpret_cast<uint32_t *>(s.cd + kCand);
-    s.sd = reinterpret_cast<float *>(s.ci + kCand);
-    s.si = reinterpret_cast<uint32_t *>(s.sd + kCand);
-    s.slb = reinterpret_cast<int32_t *>(s.si + kCand);
-    s.htab = reinterpret_cast<uint32_t *>(s.slb + kCand);
+    s.ci = reinterpret_cast<uint32_t *>(s.cd + cand);
+    s.sd = reinterpret_cast<float *>(s.ci + cand);
+    s.si = reinterpret_cast<uint32_t *>(s.sd + cand);
+    s.slb = reinterpret_cast<int32_t *>(s.si + cand);
+    s.htab = reinterpret_cast<uint32_t *>(s.slb + cand);
     return s;
 }
 
@@ -299,7 +300,7 @@ __device__ __forceinline__ void run_search(const SearchArgs &a, const Lds &s, VI
         __syncthreads();
         if (lane == 0) s.qi[sel] = v | kExpanded;
         ++hops;
-        // ELL row (width ell), or a CSR row of any length taken kCand ids
+        // ELL row (width ell), or a CSR row of any length taken a.cand ids
         // at a time; each chunk is scored and merged before the next, which
         // ends in the same queue as one merge of the whole row.
         int64_t row = (int64_t)v * ell;
@@ -308,8 +309,8 @@ __device__ __forceinline__ void run_search(const SearchArgs &a, const Lds &s, VI
             row = a.adj_off[v];
             deg = (int)(a.adj_off[v + 1] - row);
         }
-        for (int c0 = 0; c0 < deg; c0 += kCand) {
-            const int cl = min(kCand, deg - c0);
+        for (int c0 = 0; c0 < deg; c0 += a.cand) {
+            const int cl = min(a.cand, deg - c0);
             const uint32_t *ids = a.adj + row + c0;
             vis.begin_hop(cl);
             const uint32_t r0 = lane < cl ? ids[lane] : kNone;
@@ -439,12 +440,14 @@ __device__ __forceinline__ void write_result(const SearchArgs &a, const Lds &s, 
     }
 }
 
-// One query per workgroup, visited set in LDS.
+// One query per workgroup, visited set in LDS.  Five resident wavefronts per
+// SIMD (<= 102 VGPRs) measured fastest for the BF16/FP8 searches, which wait
+// on memory latency more than on bandwidth; six or more spill.
 template <int ST, int CLS>
-__global__ __launch_bounds__(64) void k_search(SearchArgs a) {
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(5))) void k_search(SearchArgs a) {
     extern __shared__ __align__(16) unsigned char smem[];
     const int64_t q = blockIdx.x;
-    const Lds s = carve(smem, a.Leff, a.pitch);
+    const Lds s = carve(smem, a.Leff, a.pitch, a.cand);
     VisitLds vis{s.htab, a.hash_bits, 1 << a.hash_bits, 0};
     load_query(a.queries + q * a.d, a.d, a.pitch, s.qs);
     int qn, ptr;
@@ -465,7 +468,7 @@ __global__ __launch_bounds__(64) void k_search(SearchArgs a) {
 template <int ST, int CLS>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void k_search_persistent(SearchArgs a) {
     extern __shared__ __align__(16) unsigned char smem[];
-    const Lds s = carve(smem, a.Leff, a.pitch);
+    const Lds s = carve(smem, a.Leff, a.pitch, a.cand);
     VisitBitmap vis{a.bitmap + (size_t)blockIdx.x * a.bm_words, a.bm_words};
     const int lane = lane_id();
     for (;;) {
@@ -494,7 +497,7 @@ __global__ __launch_bounds__(64) void k_serve_step(SlotArgs sa) {
     SearchArgs a = sa.s;
     a.k = sa.slot_k[slot];
     a.Leff = max(sa.slot_L[slot], a.k);
-    const Lds s = carve(smem, a.Leff, a.pitch);
+    const Lds s = carve(smem, a.Leff, a.pitch, a.cand);
     const int lane = lane_id();
     const int H = 1 << a.hash_bits;
     load_query(sa.slot_q + (size_t)slot * a.d, a.d, a.pitch, s.qs);
@@ -567,7 +570,7 @@ __global__ __launch_bounds__(64) void k_serve_admit(int32_t n, const int32_t *sl
 
 template <int ST, int CLS>
 int launch_one(const SearchArgs &a, hipStream_t stream) {
-    const size_t lds = search_lds_bytes(a.Leff, a.pitch, a.hash_bits);
+    const size_t lds = search_lds_bytes(a.Leff, a.pitch, a.hash_bits, a.cand);
     hipLaunchKernelGGL((k_search<ST, CLS>), dim3((unsigned)a.nq), dim3(64), lds, stream, a);
     RG_HIP(hipGetLastError());
     return RG_OK;
@@ -575,22 +578,22 @@ int launch_one(const SearchArgs &a, hipStream_t stream) {
 
 template <int ST, int CLS>
 int launch_persistent(const SearchArgs &a, hipStream_t stream) {
-    const size_t lds = search_lds_bytes(a.Leff, a.pitch, 0);
+    const size_t lds = search_lds_bytes(a.Leff, a.pitch, 0, a.cand);
     hipLaunchKernelGGL((k_search_persistent<ST, CLS>), dim3((unsigned)a.grid), dim3(64), lds, stream, a);
     RG_HIP(hipGetLastError());
     return RG_OK;
 }
 
 template <int ST, int CLS>
-int occupancy_of(int Leff, int pitch, int *blocks_per_cu) {
-    const size_t lds = search_lds_bytes(Leff, pitch, 0);
+int occupancy_of(int Leff, int pitch, int cand, int *blocks_per_cu) {
+    const size_t lds = search_lds_bytes(Leff, pitch, 0, cand);
     RG_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k_search_persistent<ST, CLS>, 64, lds));
     return RG_OK;
 }
 
 template <int ST, int CLS>
 int launch_step(const SlotArgs &sa, hipStream_t stream) {
-    const size_t lds = search_lds_bytes(kMaxL, sa.s.pitch, sa.s.hash_bits);
+    const size_t lds = search_lds_bytes(kMaxL, sa.s.pitch, sa.s.hash_bits, sa.s.cand);
     hipLaunchKernelGGL((k_serve_step<ST, CLS>), dim3((unsigned)sa.n_active), dim3(64), lds, stream, sa);
     RG_HIP(hipGetLastError());
     return RG_OK;
@@ -619,7 +622,9 @@ struct PersistentLaunch {
 };
 template <int ST, int CLS>
 struct OccLaunch {
-    static int run(const SearchArgs &a, hipStream_t) { return occupancy_of<ST, CLS>(a.Leff, a.pitch, a.occ_out); }
+    static int run(const SearchArgs &a, hipStream_t) {
+        return occupancy_of<ST, CLS>(a.Leff, a.pitch, a.cand, a.occ_out);
+    }
 };
 template <int ST, int CLS>
 struct StepLaunch {
@@ -628,9 +633,11 @@ struct StepLaunch {
 
 }  // namespace
 
-size_t search_lds_bytes(int Leff, int pitch, int hash_bits) {
-    return (size_t)pitch * 4 + (size_t)Leff * 8 + (size_t)kCand * 20 + (hash_bits > 0 ? ((size_t)4 << hash_bits) : 0);
+size_t search_lds_bytes(int Leff, int pitch, int hash_bits, int cand) {
+    return (size_t)pitch * 4 + (size_t)Leff * 8 + (size_t)cand * 20 + (hash_bits > 0 ? ((size_t)4 << hash_bits) : 0);
 }
+
+int cand_capacity(int ell, bool csr) { return csr || ell > 64 ? kCand : 64; }
 
 int default_hash_bits(int Leff) {
     // table of about 16 entries per queue slot, 2^11 .. 2^13

@@ -23,6 +23,9 @@
 #include <atomic>
 #include <chrono>
 #include <cmath>
+#include <condition_variable>
+#include <functional>
+#include <mutex>
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
@@ -60,6 +63,73 @@ void parallel_for(int64_t n, int threads, int64_t grain, F &&f) {
     for (int t = 0; t < threads; ++t) pool.emplace_back(work, t);
     for (auto &th : pool) th.join();
 }
+
+// A fixed set of worker threads for many small parallel loops in a row
+// (thread start-up would dominate them).  run(n, f) calls f(i, tid) for
+// i < n on the workers and the caller, and returns when all are done.
+class Pool {
+  public:
+    explicit Pool(int threads) : n_threads_(std::max(1, threads)) {
+        for (int t = 1; t < n_threads_; ++t) th_.emplace_back([this, t] { worker(t); });
+    }
+    ~Pool() {
+        {
+            std::lock_guard<std::mutex> lk(m_);
+            stop_ = true;
+        }
+        cv_.notify_all();
+        for (auto &t : th_) t.join();
+    }
+    int size() const { return n_threads_; }
+    void run(int n, const std::function<void(int, int)> &f) {
+        if (n <= 0) return;
+        if (n == 1 || n_threads_ == 1) {
+            for (int i = 0; i < n; ++i) f(i, 0);
+            return;
+        }
+        {
+            std::lock_guard<std::mutex> lk(m_);
+            job_ = &f;
+            n_ = n;
+            next_.store(0);
+            pending_ = n_threads_ - 1;
+            ++gen_;
+        }
+        cv_.notify_all();
+        drain(0);
+        std::unique_lock<std::mutex> lk(m_);
+        done_.wait(lk, [this] { return pending_ == 0; });
+        job_ = nullptr;
+    }
+
+  private:
+    void drain(int tid) {
+        for (int i = next_.fetch_add(1); i < n_; i = next_.fetch_add(1)) (*job_)(i, tid);
+    }
+    void worker(int tid) {
+        uint64_t seen = 0;
+        for (;;) {
+            {
+                std::unique_lock<std::mutex> lk(m_);
+                cv_.wait(lk, [&] { return stop_ || gen_ != seen; });
+                if (stop_) return;
+                seen = gen_;
+            }
+            drain(tid);
+            std::lock_guard<std::mutex> lk(m_);
+            if (--pending_ == 0) done_.notify_one();
+        }
+    }
+    int n_threads_;
+    std::vector<std::thread> th_;
+    std::mutex m_;
+    std::condition_variable cv_, done_;
+    const std::function<void(int, int)> *job_ = nullptr;
+    int n_ = 0, pending_ = 0;
+    std::atomic<int> next_{0};
+    uint64_t gen_ = 0;
+    bool stop_ = false;
+};
 
 // Eight canonical distances at once; each chain is its own left-to-right sum.
 void dist8(const float *q, const float *const r[8], int d, double out[8]) {
@@ -705,7 +775,7 @@ void host_canon_searches(const float *X, int32_t d, const int64_t *off, const ui
 // BFS order with a free slot.
 int host_insert(StageGraphs &sg, int32_t d, int32_t M, int32_t m_pj, int32_t L, uint32_t entry, int64_t n0,
                 int64_t nv, const uint32_t *queue_ids, const int32_t *queue_n, std::vector<int64_t> &offsets,
-                std::vector<uint32_t> &indices) {
+                std::vector<uint32_t> &indices, int threads) {
     const float *X = sg.base.data();
     const float *T = sg.train.data();
     const int64_t nb = sg.n_built, q1 = sg.q1, N = n0 + nv;
@@ -752,6 +822,11 @@ int host_insert(StageGraphs &sg, int32_t d, int32_t M, int32_t m_pj, int32_t L, 
     std::vector<uint32_t> qs;
     std::vector<Cand> cand, res((size_t)std::max(M, std::max(m_pj, 1)));
     std::vector<uint8_t> kept;
+    Pool pool(hw_threads(threads));
+    std::vector<std::vector<Cand>> tcand((size_t)pool.size()), tres((size_t)pool.size());
+    std::vector<std::vector<uint8_t>> tkept((size_t)pool.size());
+    std::vector<uint32_t> full;
+    std::vector<uint8_t> keeps_v;
     for (int64_t i = 0; i < nv; ++i) {
         const int64_t v = n0 + i;
         const float *xv = X + v * d;
@@ -786,25 +861,37 @@ int host_insert(StageGraphs &sg, int32_t d, int32_t M, int32_t m_pj, int32_t L, 
         for (int j = 0; j < ns; ++j) sel[j] = res[j].id;
         rows[v] = sel;
         std::sort(rows[v].begin(), rows[v].end());
+        // each selected row is reconsidered on its own (rows are disjoint, so
+        // the full ones run in parallel with the same result)
         bool took = false;
+        full.clear();
         for (const uint32_t p : sel) {
-            auto &r = rows[p];
-            if ((int64_t)r.size() < M) {
-                r.push_back((uint32_t)v);  // v is the largest id: the row stays sorted
+            if ((int64_t)rows[p].size() < M) {
+                rows[p].push_back((uint32_t)v);  // v is the largest id: the row stays sorted
                 took = true;
-                continue;
+            } else {
+                full.push_back(p);
             }
-            const float *xp = X + (int64_t)p * d;
-            cand.clear();
-            for (uint32_t u : r) cand.push_back(Cand{canon_dist(xp, X + (int64_t)u * d, d), u});
-            cand.push_back(Cand{canon_dist(xp, xv, d), (uint32_t)v});
-            std::sort(cand.begin(), cand.end(), cless);
-            const int nk = acquire_sorted(X, d, cand.data(), (int)cand.size(), M, true, res.data(), kept);
-            r.clear();
-            for (int j = 0; j < nk; ++j) r.push_back(res[j].id);
-            std::sort(r.begin(), r.end());
-            took = took || std::binary_search(r.begin(), r.end(), (uint32_t)v);
         }
+        keeps_v.assign(full.size(), 0);
+        pool.run((int)full.size(), [&](int f, int tid) {
+            const uint32_t p = full[f];
+            auto &r = rows[p];
+            const float *xp = X + (int64_t)p * d;
+            auto &c = tcand[tid];
+            c.clear();
+            for (uint32_t u : r) c.push_back(Cand{canon_dist(xp, X + (int64_t)u * d, d), u});
+            c.push_back(Cand{canon_dist(xp, xv, d), (uint32_t)v});
+            std::sort(c.begin(), c.end(), cless);
+            auto &rs = tres[tid];
+            rs.resize((size_t)M);
+            const int nk = acquire_sorted(X, d, c.data(), (int)c.size(), M, true, rs.data(), tkept[tid]);
+            r.clear();
+            for (int j = 0; j < nk; ++j) r.push_back(rs[j].id);
+            std::sort(r.begin(), r.end());
+            keeps_v[f] = std::binary_search(r.begin(), r.end(), (uint32_t)v);
+        });
+        for (uint8_t k : keeps_v) took = took || k;
         if (!took) {
             int64_t r = -1;
             for (int j = 0; j < qn && r < 0; ++j)

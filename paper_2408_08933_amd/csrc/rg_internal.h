@@ -45,6 +45,7 @@ struct SearchArgs {
     int64_t nq;
     int32_t d, pitch, pitch8, ell;
     int32_t k, Leff;
+    int32_t cand;               // candidate-batch capacity (64 or 128; cand_capacity)
     int32_t hash_bits;
     uint32_t entry;
     int32_t storage;            // RG_STORE_*
@@ -60,7 +61,8 @@ struct SearchArgs {
 int launch_search(const SearchArgs &a, hipStream_t stream);
 int launch_search_persistent(const SearchArgs &a, hipStream_t stream);
 int search_occupancy(const SearchArgs &a, int *blocks_per_cu);
-size_t search_lds_bytes(int Leff, int pitch, int hash_bits);
+size_t search_lds_bytes(int Leff, int pitch, int hash_bits, int cand);
+int cand_capacity(int ell, bool csr);  // candidate-batch capacity for a graph layout
 int default_hash_bits(int Leff);
 
 // Serving step: same per-query arithmetic as launch_search, resumable.
@@ -171,7 +173,7 @@ int host_construct(const float *X, int64_t n, int32_t d, const uint32_t *knn, in
 // in place to n0 + nv rows.
 int host_insert(StageGraphs &sg, int32_t d, int32_t M, int32_t m_pj, int32_t L, uint32_t entry, int64_t n0,
                 int64_t nv, const uint32_t *queue_ids, const int32_t *queue_n, std::vector<int64_t> &offsets,
-                std::vector<uint32_t> &indices);
+                std::vector<uint32_t> &indices, int threads);
 // Canonical searches of rows x0 .. x0+count-1 of X (host) on a host CSR
 // graph, queue length L, on host threads (indexes without device data).
 void host_canon_searches(const float *X, int32_t d, const int64_t *off, const uint32_t *idx, uint32_t entry,

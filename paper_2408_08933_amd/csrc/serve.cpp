@@ -136,6 +136,7 @@ void rg_server::loop() {
         sa.s.pitch = ix->pitch;
         sa.s.pitch8 = ix->pitch8;
         sa.s.ell = ix->ell;
+        sa.s.cand = cand_capacity(ix->ell, ix->d_adj_off != nullptr);
         sa.s.hash_bits = hash_bits;
         sa.s.entry = ix->entry;
         sa.s.storage = ix->storage;
@@ -204,6 +205,11 @@ void rg_server::loop() {
 
 extern "C" {
 
+// default visited-table size per slot: 2^11 ids for FP32 rows, 2^9 for BF16
+// and FP8 (measured on the mixed-L serving load; a small table costs
+// rescoring, which the reduced rows make cheap)
+int serve_hash_bits(int32_t storage) { return storage == RG_STORE_FP32 ? 11 : 9; }
+
 int rg_server_create(const rg_index *ix, const rg_server_limits *lim, rg_server **out) {
     if (!ix || !out || !ix->d_base) {
         set_error("rg_server_create: invalid argument");
@@ -215,10 +221,16 @@ int rg_server_create(const rg_index *ix, const rg_server_limits *lim, rg_server 
     if (l.max_slots < 1) l.max_slots = 1024;
     if (l.hops_per_step <= 0) l.hops_per_step = 32;
     if (l.max_L <= 0 || l.max_L > kMaxL) l.max_L = kMaxL;
+    if (l.hash_bits == 0) l.hash_bits = serve_hash_bits(ix->storage);
+    if (l.hash_bits < 8 || l.hash_bits > 13 ||
+        (1 << l.hash_bits) < 2 * cand_capacity(ix->ell, ix->d_adj_off != nullptr) + 2) {
+        set_error("rg_server_create: hash_bits out of range");
+        return RG_EINVAL;
+    }
     rg_server *s = new rg_server();
     s->ix = ix;
     s->lim = l;
-    s->hash_bits = 12;
+    s->hash_bits = l.hash_bits;
     // device bytes one slot keeps between steps: query, k/L, queue (keys + ids),
     // state words, visited table, its result record
     const int64_t per_slot = (int64_t)ix->d * 4 + 8 + (int64_t)kMaxL * 8 + 32 + ((int64_t)4 << s->hash_bits) +

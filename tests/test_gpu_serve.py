@@ -89,9 +89,9 @@ def test_alone_equals_mix(setup, storage):
 
 def test_memory_bounded_admission(setup):
     dev, X, Q, ix = setup
-    # one slot keeps ~24.9 KB at d=64 (query, queue, visited table, outputs):
-    # a 75 KB pool admits three requests at a time
-    srv = rg.Server(ix, max_slots=1000, hbm_pool_bytes=75_000)
+    # with a 2^12-entry visited table one slot keeps ~24.9 KB at d=64 (query,
+    # queue, table, outputs): a 75 KB pool admits three requests at a time
+    srv = rg.Server(ix, max_slots=1000, hbm_pool_bytes=75_000, hash_bits=12)
     assert srv.slots() == 3
     n = 40
     res = run_mix(srv, Q, np.full(n, 10), np.full(n, 64))
@@ -105,3 +105,6 @@ def test_pool_too_small_is_rejected(setup):
     dev, X, Q, ix = setup
     with pytest.raises(rg.RGError):
         rg.Server(ix, hbm_pool_bytes=100)
+    for hb in (7, 14):
+        with pytest.raises(rg.RGError):
+            rg.Server(ix, hash_bits=hb)
