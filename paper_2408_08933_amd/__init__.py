@@ -139,9 +139,10 @@ class Index:
         return _stream(stream) if self.on_device else ctypes.c_void_p(None)
 
     def __del__(self):
-        if getattr(self, "h", None):
-            lib().rg_free(self.h)
-            self.h = None
+        h = getattr(self, "h", None)
+        if h and _lib is not None:   # at interpreter exit the library may already be gone
+            _lib.rg_free(h)
+        self.h = None
 
     def graph(self):
         off, idx = ctypes.c_void_p(), ctypes.c_void_p()
@@ -389,9 +390,10 @@ class Server:
         return dict(zip(("submitted", "admitted", "completed", "steps"), (x.value for x in v)))
 
     def close(self):
-        if getattr(self, "h", None):
-            lib().rg_server_destroy(self.h)
-            self.h = None
+        h = getattr(self, "h", None)
+        if h and _lib is not None:
+            _lib.rg_server_destroy(h)
+        self.h = None
 
     def __del__(self):
         self.close()
