@@ -450,7 +450,8 @@ int enhance_on_device(const float *X, int64_t n, int32_t d, const Lists &PJ, con
         });
         t_host += secs(th0, Clock::now());
         if (std::getenv("RG_LOG"))
-            std::fprintf(stderr, "[rg] enhancement searches %lld / %lld nodes\n", (long long)(x0 + cnt), (long long)n);
+            std::fprintf(stderr, "[rg] enhancement searches %lld / %lld nodes (host selection so far %.2f s)\n",
+                         (long long)(x0 + cnt), (long long)n, t_host);
         // buffer i is reused by batch b + 2, issued in the next iteration
     }
     (void)hipStreamSynchronize(gpu.stream);
@@ -615,6 +616,7 @@ int host_construct(const float *X, int64_t n, int32_t d, const uint32_t *knn, in
             E.deg[x] = acquire_sorted(X, d, c.data(), (int)c.size(), m_ce, false, E.row(x), kept[tid]);
         });
     }
+    const auto t1b = Clock::now();
     Lists CE;
     CE.init(n, capl);
     {
@@ -629,7 +631,9 @@ int host_construct(const float *X, int64_t n, int32_t d, const uint32_t *knn, in
         });
     }
     const auto t2 = Clock::now();
-    if (log) std::fprintf(stderr, "[rg] enhancement done in %.2f s\n", secs(t1, t2));
+    if (log)
+        std::fprintf(stderr, "[rg] enhancement done in %.2f s (searches and selections %.2f s, reverse updates %.2f s)\n",
+                     secs(t1, t2), secs(t1, t1b), secs(t1b, t2));
 
     // --- merge: final(x) = G_pj(x) u G'(x) -------------------------------
     std::vector<std::vector<uint32_t>> fin((size_t)n);

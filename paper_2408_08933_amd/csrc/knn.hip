@@ -7,8 +7,10 @@
 // Workgroup = 4 wavefronts, a 128-query x 128-base output tile per step,
 // each wavefront owning a 64 x 64 quarter as 4 x 4 MFMA blocks (64
 // accumulator registers).  Operands are staged through LDS in 32-wide
-// slices of the coordinate axis, stored coordinate-major with a 16-float pad
-// so that the MFMA operand reads are bank-conflict free.
+// slices of the coordinate axis, row-major with a 4-float pad (16-byte
+// writes and reads, conflict free for 16 lanes).  The contraction order is
+// free, so in the slice's k-step t lane l supplies coordinate 8*(l/16) + t:
+// each lane reads its 8 coordinates of a row with two 16-byte LDS loads.
 //
 // Top-K: every query row of the tile keeps, in global memory, a buffer of up
 // to CAP (score, id) pairs and in LDS an admission threshold (the K-th best
@@ -30,7 +32,7 @@ namespace {
 
 typedef float fx4 __attribute__((ext_vector_type(4)));
 
-constexpr int BQ = 128, BX = 128, KC = 32, LDS_LD = 128 + 16;
+constexpr int BQ = 128, BX = 128, KC = 32, KCP = KC + 4;
 constexpr int CAP = 512;        // per-row candidate buffer
 constexpr int CE = CAP / 64;    // pairs per lane when sorting a buffer
 
@@ -92,8 +94,8 @@ __device__ __forceinline__ int compact_row(float *bsc, uint32_t *bid, int c, int
 }
 
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k_knn(KnnArgs a) {
-    __shared__ float As[KC][LDS_LD];
-    __shared__ float Bs[KC][LDS_LD];
+    __shared__ __align__(16) float As[BQ * KCP];
+    __shared__ __align__(16) float Bs[BX * KCP];
     __shared__ float thr[BQ];
     __shared__ int cnt[BQ];
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
@@ -113,6 +115,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
     const int64_t xt0 = (int64_t)sp * a.xtiles_per_split;
     const int64_t xt1 = min(a.xtiles, xt0 + a.xtiles_per_split);
     const int lr = tid >> 3, lk = (tid & 7) * 4;
+    const int kq = (lane >> 4) * 8;  // this lane's coordinates within a slice
     // the next coordinate slice of the tile is loaded into registers while
     // the current one feeds the MFMAs
     float4 va[4], vb[4];
@@ -137,30 +140,27 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
 #pragma unroll
             for (int p = 0; p < 4; ++p) {
                 const int r = p * 32 + lr;
-                As[lk + 0][r] = va[p].x;
-                As[lk + 1][r] = va[p].y;
-                As[lk + 2][r] = va[p].z;
-                As[lk + 3][r] = va[p].w;
-                Bs[lk + 0][r] = vb[p].x;
-                Bs[lk + 1][r] = vb[p].y;
-                Bs[lk + 2][r] = vb[p].z;
-                Bs[lk + 3][r] = vb[p].w;
+                *reinterpret_cast<float4 *>(&As[r * KCP + lk]) = va[p];
+                *reinterpret_cast<float4 *>(&Bs[r * KCP + lk]) = vb[p];
             }
             __syncthreads();
             if (k0 + KC < a.d) load_slice(xt, k0 + KC);
-#pragma unroll
-            for (int ks = 0; ks < KC / 4; ++ks) {
-                const int kk = ks * 4 + (lane >> 4);
-                float af[4], bf[4];
-#pragma unroll
-                for (int i = 0; i < 4; ++i) af[i] = As[kk][wr * 64 + i * 16 + (lane & 15)];
-#pragma unroll
-                for (int j = 0; j < 4; ++j) bf[j] = Bs[kk][wc * 64 + j * 16 + (lane & 15)];
+#pragma unroll 1
+            for (int h = 0; h < 2; ++h) {
+                float4 af[4], bf[4];
 #pragma unroll
                 for (int i = 0; i < 4; ++i)
+                    af[i] = *reinterpret_cast<const float4 *>(&As[(wr * 64 + i * 16 + (lane & 15)) * KCP + kq + 4 * h]);
 #pragma unroll
-                    for (int j = 0; j < 4; ++j)
-                        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(af[i], bf[j], acc[i][j], 0, 0, 0);
+                for (int j = 0; j < 4; ++j)
+                    bf[j] = *reinterpret_cast<const float4 *>(&Bs[(wc * 64 + j * 16 + (lane & 15)) * KCP + kq + 4 * h]);
+#pragma unroll
+                for (int t = 0; t < 4; ++t)
+#pragma unroll
+                    for (int i = 0; i < 4; ++i)
+#pragma unroll
+                        for (int j = 0; j < 4; ++j)
+                            acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(af[i][t], bf[j][t], acc[i][j], 0, 0, 0);
             }
         }
         // filter: accumulator element r of block (i, j) is row 4*(lane/16)+r, column lane%16
