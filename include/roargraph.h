@@ -292,8 +292,10 @@ int rg_index_build_stats(const rg_index *idx, double *t_knn, double *t_project, 
 
 /* rg_index_storage_ptrs -- device pointers of the reduced-precision copies
  * (NULL until made by rg_index_set_storage): bf16 rows (pitch elements of
- * 2 bytes), e4m3 rows (pitch8 bytes) and their per-row scales.  The index
- * keeps ownership. */
+ * 2 bytes); e4m3 rows of pitch8 bytes, each holding the d codes, zeros up to
+ * a multiple of 4 bytes, the row's FP32 scale and zeros up to a multiple of
+ * 16 (the search reads the scale with the codes); and the scales again as an
+ * array of n floats.  The index keeps ownership. */
 int rg_index_storage_ptrs(const rg_index *idx, const void **bf16, const void **fp8,
                           const float **scales, int32_t *pitch8);
 

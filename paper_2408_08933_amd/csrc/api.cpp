@@ -140,7 +140,6 @@ SearchArgs search_args(const rg_index *ix, const float *queries, int64_t nq, int
     a.base = ix->d_base;
     a.base_bf16 = ix->d_bf16;
     a.base_fp8 = ix->d_fp8;
-    a.scale_fp8 = ix->d_scale;
     a.adj = ix->d_adj;
     a.adj_off = ix->d_adj_off;
     a.tomb = ix->d_tomb;
@@ -153,6 +152,7 @@ SearchArgs search_args(const rg_index *ix, const float *queries, int64_t nq, int
     a.d = ix->d;
     a.pitch = ix->pitch;
     a.pitch8 = ix->pitch8;
+    a.qpad = query_pad(ix->d, ix->pitch, ix->storage);
     a.ell = ix->ell;
     a.k = k;
     a.Leff = std::max(k, L);
@@ -771,7 +771,7 @@ int rg_index_set_storage(rg_index *ix, int32_t storage, void *stream) {
         if (rc) return rc;
     }
     if (storage == RG_STORE_FP8E4M3 && !ix->d_fp8) {
-        ix->pitch8 = round_up(ix->d, 64);
+        ix->pitch8 = fp8_pitch(ix->d);
         if (hipMalloc(&ix->d_fp8, (size_t)ix->n * ix->pitch8) != hipSuccess ||
             hipMalloc(&ix->d_scale, sizeof(float) * (size_t)ix->n) != hipSuccess) {
             if (ix->d_fp8) (void)hipFree(ix->d_fp8);

@@ -89,16 +89,27 @@ constexpr int shape_g(int st, int cls) {
     constexpr int g32[6] = {16, 16, 8, 16, 16, 32}, g16[6] = {8, 16, 8, 8, 16, 32}, g8[6] = {4, 8, 8, 8, 16, 32};
     return st == RG_STORE_FP32 ? g32[cls] : st == RG_STORE_BF16 ? g16[cls] : g8[cls];
 }
+// E4M3 rows also hold their scale after the codes (up to d + 7 bytes), so
+// each E4M3 shape covers the class's largest d plus 8 bytes.
 constexpr int shape_nch(int st, int cls) {
-    constexpr int n32[6] = {1, 2, 7, 4, 8, 8}, n16[6] = {1, 1, 4, 4, 4, 4}, n8[6] = {1, 1, 2, 2, 2, 2};
+    constexpr int n32[6] = {1, 2, 7, 4, 8, 8}, n16[6] = {1, 1, 4, 4, 4, 4}, n8[6] = {2, 2, 2, 3, 3, 3};
     return st == RG_STORE_FP32 ? n32[cls] : st == RG_STORE_BF16 ? n16[cls] : n8[cls];
 }
-constexpr int shape_r(int st) { return st == RG_STORE_FP32 ? 2 : st == RG_STORE_BF16 ? 2 : 4; }
+constexpr int shape_r(int st, int cls) { return st == RG_STORE_FP8E4M3 && cls <= 2 ? 4 : 2; }
 
-// Copy the query into LDS, zero padded to the row pitch.
-__device__ __forceinline__ void load_query(const float *q, int d, int pitch, float *qs) {
-    for (int i = lane_id(); i < pitch; i += 64) qs[i] = i < d ? q[i] : 0.f;
+// Copy the query into LDS, zero padded to qpad (every element a row chunk
+// can reach, so bytes past d meet a zero).
+__device__ __forceinline__ void load_query(const float *q, int d, int qpad, float *qs) {
+    for (int i = lane_id(); i < qpad; i += 64) qs[i] = i < d ? q[i] : 0.f;
     __syncthreads();
+}
+
+// Chunks of a stored row the search reads: the d elements, and for E4M3 rows
+// the scale that follows the codes.
+template <int ST>
+__device__ __forceinline__ int row_chunk_count(int d) {
+    if constexpr (ST == RG_STORE_FP8E4M3) return (((d + 3) & ~3) + 4 + 15) >> 4;
+    return (d + Fmt<ST>::EPC - 1) / Fmt<ST>::EPC;
 }
 
 template <int ST>
@@ -130,6 +141,8 @@ __device__ __forceinline__ float fma_chunk(const float *qs, int c, uint4 x, floa
             acc = fmaf(q.w, __uint_as_float(w[2 * i + 1] & 0xFFFF0000u), acc);
         }
     } else {
+        // bytes at and past d (the scale, padding) decode to finite values and
+        // meet zero query elements; the scale is taken separately
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
             // gfx950 converts OCP E4M3 pairs exactly (every code is a float)
@@ -147,9 +160,11 @@ __device__ __forceinline__ float fma_chunk(const float *qs, int c, uint4 x, floa
 
 // This lane's partial dot products with rows u[0..R) (kNone -> 0); all loads
 // are issued before the first multiply.
+// sc[r] receives the E4M3 row scale in the lane whose chunk holds it (0
+// elsewhere), so a group sum yields it.
 template <int ST, int G, int NCH, int R>
 __device__ __forceinline__ void dot_rows(const SearchArgs &a, const uint32_t (&u)[R], const float *qs, int nch,
-                                         float (&acc)[R]) {
+                                         float (&acc)[R], float (&sc)[R]) {
     const int j = lane_id() % G;
     uint4 raw[R][NCH];
 #pragma unroll
@@ -161,13 +176,22 @@ __device__ __forceinline__ void dot_rows(const SearchArgs &a, const uint32_t (&u
             raw[r][t] = (u[r] != kNone && c < nch) ? row[c] : make_uint4(0u, 0u, 0u, 0u);
         }
     }
+    const int s_off = (a.d + 3) & ~3, s_chunk = s_off >> 4, s_word = (s_off & 15) >> 2;
 #pragma unroll
     for (int r = 0; r < R; ++r) {
         acc[r] = 0.f;
+        sc[r] = 0.f;
 #pragma unroll
         for (int t = 0; t < NCH; ++t) {
             const int c = j + G * t;
             if (c < nch) acc[r] = fma_chunk<ST>(qs, c, raw[r][t], acc[r]);
+            if constexpr (ST == RG_STORE_FP8E4M3) {
+                if (c == s_chunk) {
+                    const uint32_t w = s_word == 0 ? raw[r][t].x : s_word == 1 ? raw[r][t].y
+                                     : s_word == 2 ? raw[r][t].z : raw[r][t].w;
+                    sc[r] = __uint_as_float(w);
+                }
+            }
         }
     }
 }
@@ -179,15 +203,12 @@ __device__ __forceinline__ float group_sum(float v) {
     return v;
 }
 
-// delta of this group's row u (uniform within the group)
+// delta of this group's row from its group-summed dot product (and, for
+// E4M3, the row's power-of-two scale: the product is exact)
 template <int ST>
-__device__ __forceinline__ float finish_delta(const SearchArgs &a, uint32_t u, float sum) {
-    if constexpr (ST == RG_STORE_FP8E4M3) {
-        const float s = u == kNone ? 1.f : a.scale_fp8[u];
-        return -(s * sum);
-    } else {
-        return -sum;
-    }
+__device__ __forceinline__ float finish_delta(float sum, float scale) {
+    if constexpr (ST == RG_STORE_FP8E4M3) return -(scale * sum);
+    return -sum;
 }
 
 // Score ids[0..cnt) (LDS) into dout[0..cnt) (LDS); R rows per group in flight.
@@ -203,15 +224,18 @@ __device__ __forceinline__ void score_batch(const SearchArgs &a, const float *qs
             const int sl = p + r * NG + g;
             u[r] = sl < cnt ? (ids[sl] & idmask) : kNone;
         }
-        float acc[R];
-        dot_rows<ST, G, NCH, R>(a, u, qs, nch, acc);
+        float acc[R], sc[R];
+        dot_rows<ST, G, NCH, R>(a, u, qs, nch, acc, sc);
 #pragma unroll
-        for (int r = 0; r < R; ++r) acc[r] = group_sum<G>(acc[r]);
+        for (int r = 0; r < R; ++r) {
+            acc[r] = group_sum<G>(acc[r]);
+            if constexpr (ST == RG_STORE_FP8E4M3) sc[r] = group_sum<G>(sc[r]);
+        }
         if (j == 0) {
 #pragma unroll
             for (int r = 0; r < R; ++r) {
                 const int sl = p + r * NG + g;
-                if (sl < cnt) dout[sl] = finish_delta<ST>(a, u[r], acc[r]);
+                if (sl < cnt) dout[sl] = finish_delta<ST>(acc[r], sc[r]);
             }
         }
     }
@@ -276,9 +300,9 @@ template <int ST, int CLS, class VIS>
 __device__ __forceinline__ void run_search(const SearchArgs &a, const Lds &s, VIS &vis,
                                            int &qn, int &ptr, uint32_t &hops, uint32_t &evals, int budget,
                                            bool &done) {
-    constexpr int G = shape_g(ST, CLS), NCH = shape_nch(ST, CLS), R = shape_r(ST);
+    constexpr int G = shape_g(ST, CLS), NCH = shape_nch(ST, CLS), R = shape_r(ST, CLS);
     const int lane = lane_id();
-    const int Leff = a.Leff, ell = a.ell, nch = (a.d + Fmt<ST>::EPC - 1) / Fmt<ST>::EPC;
+    const int Leff = a.Leff, ell = a.ell, nch = row_chunk_count<ST>(a.d);
     done = false;
     for (; budget > 0; --budget) {
         int sel = -1;
@@ -349,12 +373,13 @@ __device__ __forceinline__ void init_state(const SearchArgs &a, const Lds &s, VI
     const int lane = lane_id();
     vis.clear();
     const uint32_t u[1] = {lane < G ? a.entry : kNone};
-    float acc[1];
-    dot_rows<ST, G, NCH, 1>(a, u, s.qs, (a.d + Fmt<ST>::EPC - 1) / Fmt<ST>::EPC, acc);
+    float acc[1], sc[1];
+    dot_rows<ST, G, NCH, 1>(a, u, s.qs, row_chunk_count<ST>(a.d), acc, sc);
     acc[0] = group_sum<G>(acc[0]);
+    if constexpr (ST == RG_STORE_FP8E4M3) sc[0] = group_sum<G>(sc[0]);
     __syncthreads();
     if (lane == 0) {
-        s.qd[0] = finish_delta<ST>(a, a.entry, acc[0]);
+        s.qd[0] = finish_delta<ST>(acc[0], sc[0]);
         s.qi[0] = a.entry;
         vis.mark_entry(a.entry);
     }
@@ -447,9 +472,9 @@ template <int ST, int CLS>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(5))) void k_search(SearchArgs a) {
     extern __shared__ __align__(16) unsigned char smem[];
     const int64_t q = blockIdx.x;
-    const Lds s = carve(smem, a.Leff, a.pitch, a.cand);
+    const Lds s = carve(smem, a.Leff, a.qpad, a.cand);
     VisitLds vis{s.htab, a.hash_bits, 1 << a.hash_bits, 0};
-    load_query(a.queries + q * a.d, a.d, a.pitch, s.qs);
+    load_query(a.queries + q * a.d, a.d, a.qpad, s.qs);
     int qn, ptr;
     uint32_t hops, evals;
     bool done;
@@ -468,7 +493,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(5))) void k_
 template <int ST, int CLS>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void k_search_persistent(SearchArgs a) {
     extern __shared__ __align__(16) unsigned char smem[];
-    const Lds s = carve(smem, a.Leff, a.pitch, a.cand);
+    const Lds s = carve(smem, a.Leff, a.qpad, a.cand);
     VisitBitmap vis{a.bitmap + (size_t)blockIdx.x * a.bm_words, a.bm_words};
     const int lane = lane_id();
     for (;;) {
@@ -476,7 +501,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void k_
         if (lane == 0) q = (int)atomicAdd(a.work, 1u);
         q = __shfl(q, 0);
         if ((int64_t)q >= a.nq) break;
-        load_query(a.queries + (int64_t)q * a.d, a.d, a.pitch, s.qs);
+        load_query(a.queries + (int64_t)q * a.d, a.d, a.qpad, s.qs);
         int qn, ptr;
         uint32_t hops, evals;
         bool done;
@@ -497,10 +522,10 @@ __global__ __launch_bounds__(64) void k_serve_step(SlotArgs sa) {
     SearchArgs a = sa.s;
     a.k = sa.slot_k[slot];
     a.Leff = max(sa.slot_L[slot], a.k);
-    const Lds s = carve(smem, a.Leff, a.pitch, a.cand);
+    const Lds s = carve(smem, a.Leff, a.qpad, a.cand);
     const int lane = lane_id();
     const int H = 1 << a.hash_bits;
-    load_query(sa.slot_q + (size_t)slot * a.d, a.d, a.pitch, s.qs);
+    load_query(sa.slot_q + (size_t)slot * a.d, a.d, a.qpad, s.qs);
     int32_t *st = sa.slot_state + (size_t)slot * 8;
     float *gqd = sa.slot_qd + (size_t)slot * kMaxL;
     uint32_t *gqi = sa.slot_qi + (size_t)slot * kMaxL;
@@ -570,7 +595,7 @@ __global__ __launch_bounds__(64) void k_serve_admit(int32_t n, const int32_t *sl
 
 template <int ST, int CLS>
 int launch_one(const SearchArgs &a, hipStream_t stream) {
-    const size_t lds = search_lds_bytes(a.Leff, a.pitch, a.hash_bits, a.cand);
+    const size_t lds = search_lds_bytes(a.Leff, a.qpad, a.hash_bits, a.cand);
     hipLaunchKernelGGL((k_search<ST, CLS>), dim3((unsigned)a.nq), dim3(64), lds, stream, a);
     RG_HIP(hipGetLastError());
     return RG_OK;
@@ -578,7 +603,7 @@ int launch_one(const SearchArgs &a, hipStream_t stream) {
 
 template <int ST, int CLS>
 int launch_persistent(const SearchArgs &a, hipStream_t stream) {
-    const size_t lds = search_lds_bytes(a.Leff, a.pitch, 0, a.cand);
+    const size_t lds = search_lds_bytes(a.Leff, a.qpad, 0, a.cand);
     hipLaunchKernelGGL((k_search_persistent<ST, CLS>), dim3((unsigned)a.grid), dim3(64), lds, stream, a);
     RG_HIP(hipGetLastError());
     return RG_OK;
@@ -593,7 +618,7 @@ int occupancy_of(int Leff, int pitch, int cand, int *blocks_per_cu) {
 
 template <int ST, int CLS>
 int launch_step(const SlotArgs &sa, hipStream_t stream) {
-    const size_t lds = search_lds_bytes(kMaxL, sa.s.pitch, sa.s.hash_bits, sa.s.cand);
+    const size_t lds = search_lds_bytes(kMaxL, sa.s.qpad, sa.s.hash_bits, sa.s.cand);
     hipLaunchKernelGGL((k_serve_step<ST, CLS>), dim3((unsigned)sa.n_active), dim3(64), lds, stream, sa);
     RG_HIP(hipGetLastError());
     return RG_OK;
@@ -623,7 +648,7 @@ struct PersistentLaunch {
 template <int ST, int CLS>
 struct OccLaunch {
     static int run(const SearchArgs &a, hipStream_t) {
-        return occupancy_of<ST, CLS>(a.Leff, a.pitch, a.cand, a.occ_out);
+        return occupancy_of<ST, CLS>(a.Leff, a.qpad, a.cand, a.occ_out);
     }
 };
 template <int ST, int CLS>

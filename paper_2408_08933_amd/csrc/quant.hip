@@ -56,7 +56,9 @@ __device__ __forceinline__ uint32_t f32_to_e4m3(float y) {
     return sgn | code;
 }
 
-// one wavefront per row: scale = smallest 2^e with 448 * 2^e >= max|x|
+// one wavefront per row: scale = smallest 2^e with 448 * 2^e >= max|x|.
+// Row layout (pitch8 bytes): the d codes, zeros up to a multiple of 4, the
+// row's FP32 scale, zeros; the scale also goes to scales[r].
 __global__ __launch_bounds__(64) void k_quant_fp8(const float *src, int64_t n, int32_t d, int32_t pitch,
                                                   uint8_t *dst, int32_t pitch8, float *scales) {
     const int64_t r = blockIdx.x;
@@ -71,12 +73,16 @@ __global__ __launch_bounds__(64) void k_quant_fp8(const float *src, int64_t n, i
         e = ilogbf(amax) - 10;
         while (ldexpf(448.f, e) < amax) ++e;
     }
+    const float sc = ldexpf(1.f, e);
+    const int s_off = (d + 3) & ~3;
+    const uint32_t sb = __float_as_uint(sc);
     for (int c = lane; c < pitch8; c += 64) {
         uint32_t code = 0;
         if (c < d) code = f32_to_e4m3(ldexpf(x[c], -e));
+        else if (c >= s_off && c < s_off + 4) code = (sb >> (8 * (c - s_off))) & 0xFFu;
         dst[r * pitch8 + c] = (uint8_t)code;
     }
-    if (lane == 0) scales[r] = ldexpf(1.f, e);
+    if (lane == 0) scales[r] = sc;
 }
 
 // plain streaming copy (16 bytes per lane per step)

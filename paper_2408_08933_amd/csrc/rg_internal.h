@@ -3,6 +3,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cstdint>
 #include <string>
 #include <vector>
@@ -32,8 +33,7 @@ void set_error(const std::string &msg);
 struct SearchArgs {
     const float *base;          // fp32 rows, pitch floats
     const uint16_t *base_bf16;  // bf16 rows (pitch elements) or null
-    const uint8_t *base_fp8;    // e4m3 rows (pitch8 bytes) or null
-    const float *scale_fp8;     // per-row power-of-two scales
+    const uint8_t *base_fp8;    // e4m3 rows (pitch8 bytes: codes, the row's scale) or null
     const uint32_t *adj;        // ELL adjacency, n x ell, kNone padded; or CSR indices
     const int64_t *adj_off;     // CSR offsets (n + 1), or null for ELL
     const uint32_t *tomb;       // deleted-node bitmap (ceil(n/32) words), or null
@@ -44,6 +44,7 @@ struct SearchArgs {
     uint32_t *out_evals;        // nq or null
     int64_t nq;
     int32_t d, pitch, pitch8, ell;
+    int32_t qpad;               // floats of the query kept in LDS (zero padded): every element a chunk reaches
     int32_t k, Leff;
     int32_t cand;               // candidate-batch capacity (64 or 128; cand_capacity)
     int32_t hash_bits;
@@ -63,6 +64,13 @@ int launch_search_persistent(const SearchArgs &a, hipStream_t stream);
 int search_occupancy(const SearchArgs &a, int *blocks_per_cu);
 size_t search_lds_bytes(int Leff, int pitch, int hash_bits, int cand);
 int cand_capacity(int ell, bool csr);  // candidate-batch capacity for a graph layout
+// E4M3 row layout: d codes, zeros to a multiple of 4, the FP32 scale, zeros
+// to a multiple of 16 bytes
+inline int32_t fp8_pitch(int32_t d) { return (((d + 3) & ~3) + 4 + 15) & ~15; }
+// query floats a search of this storage form reads (the row's chunks)
+inline int32_t query_pad(int32_t d, int32_t pitch, int32_t storage) {
+    return storage == RG_STORE_FP8E4M3 ? std::max(pitch, fp8_pitch(d)) : pitch;
+}
 int default_hash_bits(int Leff);
 
 // Serving step: same per-query arithmetic as launch_search, resumable.

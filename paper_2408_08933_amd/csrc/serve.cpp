@@ -128,13 +128,13 @@ void rg_server::loop() {
         sa.s.base = ix->d_base;
         sa.s.base_bf16 = ix->d_bf16;
         sa.s.base_fp8 = ix->d_fp8;
-        sa.s.scale_fp8 = ix->d_scale;
         sa.s.adj = ix->d_adj;
         sa.s.adj_off = ix->d_adj_off;
         sa.s.tomb = ix->d_tomb;
         sa.s.d = d;
         sa.s.pitch = ix->pitch;
         sa.s.pitch8 = ix->pitch8;
+        sa.s.qpad = query_pad(d, ix->pitch, ix->storage);
         sa.s.ell = ix->ell;
         sa.s.cand = cand_capacity(ix->ell, ix->d_adj_off != nullptr);
         sa.s.hash_bits = hash_bits;

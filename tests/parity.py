@@ -25,7 +25,7 @@ CLASS_MAX_D = (64, 128, 224, 256, 512, 1024)
 SHAPES = {
     "fp32": (4, ((16, 1), (16, 2), (8, 7), (16, 4), (16, 8), (32, 8))),
     "bf16": (8, ((8, 1), (16, 1), (8, 4), (8, 4), (16, 4), (32, 4))),
-    "fp8": (16, ((4, 1), (8, 1), (8, 2), (8, 2), (16, 2), (32, 2))),
+    "fp8": (16, ((4, 2), (8, 2), (8, 2), (8, 3), (16, 3), (32, 3))),
 }
 
 

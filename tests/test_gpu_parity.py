@@ -336,8 +336,15 @@ def test_quantized_rows_match_oracle(dev, oracle_lib, c1):
     b16 = (bits.cpu().numpy()[:, :d].astype(np.uint16).astype(np.uint32) << 16).view(np.float32)
     assert np.array_equal(b16, oracle_lib.bf16(X))
     oc, os_, _ = oracle_lib.quant_fp8(X)
-    assert np.array_equal(codes.cpu().numpy()[:, :d], oc)
+    c = codes.cpu().numpy()
+    assert np.array_equal(c[:, :d], oc)
     assert np.array_equal(scales.cpu().numpy(), os_)
+    # each E4M3 row carries its scale after the codes (4-byte aligned); the
+    # rest of the row is zero
+    s_off = (d + 3) // 4 * 4
+    assert p8 == (s_off + 4 + 15) // 16 * 16
+    assert np.array_equal(c[:, s_off:s_off + 4].copy().view(np.float32)[:, 0], os_)
+    assert not c[:, d:s_off].any() and not c[:, s_off + 4:].any()
 
 
 @pytest.mark.parametrize("storage", ["bf16", "fp8"])
