@@ -364,6 +364,30 @@ def test_precision_search_parity(dev, oracle_lib, c1, storage):
         say(f"  {r}")
 
 
+@pytest.mark.parametrize("d", [7, 37, 129, 255, 700, 1024])
+def test_search_every_dimension_class(dev, oracle_lib, d):
+    # odd d, d just past a class limit, and the largest class, for all three
+    # storage forms (each form reads its rows in its own chunk shape)
+    rng = np.random.default_rng(d)
+    n = 3000
+    X = (rng.standard_normal((n, d)) * rng.uniform(0.2, 2.0, d)).astype(np.float32)
+    Q = rng.standard_normal((60, d)).astype(np.float32)
+    off, idx = datagen.random_graph(n, 12, seed=d)
+    ix = rg.rg_index_from_csr(T(X, dev), off, idx, 3)
+    for storage, st in (("fp32", rg.RG_STORE_FP32), ("bf16", rg.RG_STORE_BF16), ("fp8", rg.RG_STORE_FP8E4M3)):
+        rg.rg_index_set_storage(ix, st)
+        say(f"d={d} {storage} k=10 L=48")
+        ids, ds = rg.rg_search(ix, T(Q, dev), 10, 48)
+        torch.cuda.synchronize()
+        if storage == "fp32":
+            oi, od, _, _, gaps = oracle_lib.search(X, off, idx, 3, Q, 10, 48)
+        else:
+            Xq = oracle_lib.bf16(X) if storage == "bf16" else oracle_lib.quant_fp8(X)[2]
+            oi, od, _, _, gaps = oracle_lib.search_rerank(Xq, X, off, idx, 3, Q, 10, 48)
+        compare(rg.as_u32(ids), ds.cpu().numpy(), oi, od, gaps, Q, X, min_agreement=0.97, min_near_same=0.9,
+                label=f"d={d} {storage}", storage=storage)
+
+
 # ---------------------------------------------------------------------------
 # full-size shape: 1M x 200 rows on a random graph, sampled queries
 # ---------------------------------------------------------------------------
