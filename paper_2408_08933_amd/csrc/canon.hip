@@ -142,7 +142,104 @@ __global__ __launch_bounds__(64) void k_canon_search(CanonArgs a) {
     if (lane == 0) a.out_n[b] = qn;
 }
 
+// AcquireNeighbors (Algorithm 3, without the fill) for every searched node,
+// on the device: the candidates are the node's final queue without the node
+// itself, already ranked by (delta, id); a candidate is kept iff
+// delta(x, c) < delta(c, p) for every kept p (strict), until m are kept.
+// Lane r computes delta(c, kept_r) as the same sequential FP64 chain as the
+// host (exact float products, one rounding per addition), so every decision
+// is the host's.  The kept rows sit in LDS when they fit.
+struct SelectArgs {
+    const float *X;          // n x pitch
+    int32_t d, pitch;
+    const uint32_t *ids;     // count x L search output
+    const double *dists;
+    const int32_t *counts;
+    int32_t L, m, head_len, kept_in_lds;
+    int64_t x0;
+    uint32_t *sel_ids;       // count x m
+    double *sel_d;
+    int32_t *sel_n;
+    uint32_t *head;          // count x head_len: the first candidates
+    int32_t *head_n;         // candidates per node (without the node)
+};
+
+__global__ __launch_bounds__(64) void k_canon_select(SelectArgs a) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    float *K = reinterpret_cast<float *>(smem);  // m x pitch kept rows
+    const int lane = lane_id();
+    const int64_t b = blockIdx.x;
+    const uint32_t x = (uint32_t)(a.x0 + b);
+    const uint32_t *cid = a.ids + b * a.L;
+    const double *cdd = a.dists + b * a.L;
+    const int qn = a.counts[b];
+    int nr = 0, hn = 0;
+    uint32_t mine = kNone;  // lane r < nr: kept id r
+    for (int j = 0; j < qn; ++j) {
+        const uint32_t c = cid[j];
+        if (c == x) continue;
+        if (hn < a.head_len && lane == 0) a.head[b * a.head_len + hn] = c;
+        ++hn;
+        if (nr >= a.m) continue;
+        const double dxc = cdd[j];
+        bool lane_ok = true;
+        if (lane < nr) {
+            const float *pr = a.kept_in_lds ? K + (size_t)lane * a.pitch : a.X + (size_t)mine * a.pitch;
+            const float *cr = a.X + (size_t)c * a.pitch;
+            double s = 0.0;
+            for (int i = 0; i < a.d; ++i) s = fma((double)cr[i], (double)pr[i], s);
+            lane_ok = dxc < -s;
+        }
+        if (ballot64(!lane_ok) != 0) continue;
+        if (lane == nr) mine = c;
+        if (a.kept_in_lds)
+            for (int i = lane; i < a.pitch; i += 64) K[(size_t)nr * a.pitch + i] = a.X[(size_t)c * a.pitch + i];
+        if (lane == 0) {
+            a.sel_ids[b * a.m + nr] = c;
+            a.sel_d[b * a.m + nr] = dxc;
+        }
+        ++nr;
+        __syncthreads();
+    }
+    if (lane == 0) {
+        a.sel_n[b] = nr;
+        a.head_n[b] = hn;
+    }
+}
+
 }  // namespace
+
+int launch_canon_select(const float *X, int32_t d, int32_t pitch, const uint32_t *ids, const double *dists,
+                        const int32_t *counts, int32_t L, int64_t x0, int64_t count, int32_t m, uint32_t *sel_ids,
+                        double *sel_d, int32_t *sel_n, uint32_t *head, int32_t head_len, int32_t *head_n,
+                        hipStream_t stream) {
+    if (count == 0) return RG_OK;
+    if (m < 1 || L < 1) {
+        set_error("canon select: bad arguments");
+        return RG_EINVAL;
+    }
+    SelectArgs a{};
+    a.X = X;
+    a.d = d;
+    a.pitch = pitch;
+    a.ids = ids;
+    a.dists = dists;
+    a.counts = counts;
+    a.L = L;
+    a.m = m;
+    a.head_len = head_len;
+    a.x0 = x0;
+    a.sel_ids = sel_ids;
+    a.sel_d = sel_d;
+    a.sel_n = sel_n;
+    a.head = head;
+    a.head_n = head_n;
+    const size_t kept_bytes = (size_t)m * pitch * sizeof(float);
+    a.kept_in_lds = kept_bytes <= (48u << 10);
+    hipLaunchKernelGGL(k_canon_select, dim3((unsigned)count), dim3(64), a.kept_in_lds ? kept_bytes : 0, stream, a);
+    RG_HIP(hipGetLastError());
+    return RG_OK;
+}
 
 size_t canon_lds_bytes(int L, int pitch, int hash_bits) {
     return (size_t)pitch * 4 + (size_t)L * 12 + (size_t)kCand * 24 + ((size_t)4 << hash_bits);

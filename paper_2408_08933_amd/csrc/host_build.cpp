@@ -211,6 +211,66 @@ int acquire_sorted(const float *X, int d, const Cand *C, int nc, int m, bool fil
     return nr;
 }
 
+// Canonical distances between pairs of rows, remembered while one node's
+// reverse insertions are replayed (the same pairs recur from one insertion
+// to the next).  delta is symmetric bit for bit (the products commute, the
+// sum runs in increasing i), so a pair is keyed without order.  Forgetting
+// (a clear when the table fills) only costs recomputation.
+class PairCache {
+  public:
+    explicit PairCache(int bits = 16) : mask_((1u << bits) - 1u), key_((size_t)1 << bits, kFree),
+                                        val_((size_t)1 << bits, 0.0) {}
+    void clear() {
+        for (uint32_t h : used_) key_[h] = kFree;
+        used_.clear();
+    }
+    double get(const float *X, int d, uint32_t a, uint32_t b) {
+        const uint64_t k = a < b ? ((uint64_t)a << 32 | b) : ((uint64_t)b << 32 | a);
+        uint32_t h = (uint32_t)((k * 0x9E3779B97F4A7C15ull) >> 40) & mask_;
+        while (key_[h] != kFree) {
+            if (key_[h] == k) return val_[h];
+            h = (h + 1u) & mask_;
+        }
+        const double v = canon_dist(X + (int64_t)a * d, X + (int64_t)b * d, d);
+        if (used_.size() * 2 > mask_) clear();  // keep the load under one half
+        h = (uint32_t)((k * 0x9E3779B97F4A7C15ull) >> 40) & mask_;
+        while (key_[h] != kFree) h = (h + 1u) & mask_;
+        key_[h] = k;
+        val_[h] = v;
+        used_.push_back(h);
+        return v;
+    }
+
+  private:
+    static constexpr uint64_t kFree = ~0ull;
+    uint32_t mask_;
+    std::vector<uint64_t> key_;
+    std::vector<double> val_;
+    std::vector<uint32_t> used_;
+};
+
+// acquire_sorted with the candidate-to-kept distances taken from a cache.
+int acquire_sorted_cached(const float *X, int d, const Cand *C, int nc, int m, bool fill, Cand *res,
+                          std::vector<uint8_t> &kept, PairCache &pc) {
+    if (nc <= 0 || m <= 0) return 0;
+    kept.assign((size_t)nc, 0);
+    int nr = 0;
+    res[nr++] = C[0];
+    kept[0] = 1;
+    for (int j = 1; j < nc && nr < m; ++j) {
+        bool ok = true;
+        for (int r = 0; r < nr && ok; ++r) ok = C[j].d < pc.get(X, d, C[j].id, res[r].id);
+        if (ok) {
+            res[nr++] = C[j];
+            kept[j] = 1;
+        }
+    }
+    if (fill)
+        for (int j = 0; j < nc && nr < m; ++j)
+            if (!kept[j]) res[nr++] = C[j];
+    return nr;
+}
+
 // Fixed-capacity adjacency lists with their distances to the owner.
 struct Lists {
     int cap = 0;
@@ -241,7 +301,8 @@ void build_events(const Lists &sel, int64_t n, std::vector<int64_t> &off, std::v
 //   start: p's own assignment (is_assigned) or empty.
 void replay(const float *X, int d, int64_t p, bool is_assigned, const Cand *start, int nstart,
             const uint32_t *ev, int64_t nev, int m, bool fill, Cand *out, int32_t *outdeg,
-            std::vector<Cand> &cur, std::vector<Cand> &tmp, std::vector<uint8_t> &kept) {
+            std::vector<Cand> &cur, std::vector<Cand> &tmp, std::vector<uint8_t> &kept, PairCache &pc) {
+    pc.clear();
     cur.assign(start, start + nstart);
     const float *xp = X + p * d;
     for (int64_t e = 0; e < nev; ++e) {
@@ -257,7 +318,7 @@ void replay(const float *X, int d, int64_t p, bool is_assigned, const Cand *star
         if (fill && (int)cur.size() <= m) continue;  // with fill, <= m candidates are all kept
         std::sort(cur.begin(), cur.end(), cless);
         tmp.resize(cur.size());
-        const int nr = acquire_sorted(X, d, cur.data(), (int)cur.size(), m, fill, tmp.data(), kept);
+        const int nr = acquire_sorted_cached(X, d, cur.data(), (int)cur.size(), m, fill, tmp.data(), kept, pc);
         cur.assign(tmp.begin(), tmp.begin() + nr);
     }
     *outdeg = (int32_t)cur.size();
@@ -346,16 +407,15 @@ void lists_to_csr(const Lists &L, int64_t n, std::vector<int64_t> &off, std::vec
         for (int j = 0; j < L.deg[x]; ++j) idx[off[x] + j] = L.row(x)[j].id;
 }
 
-// Enhancement searches on the device (canonical FP64 distance, bit-identical
-// to the host searcher), then each node's own selection on host threads.
-// Double buffered: the device searches batch i+1 while the host selects for
-// batch i.
-int enhance_on_device(const float *X, int64_t n, int32_t d, const Lists &PJ, const std::vector<int64_t> &pjoff,
-                      const std::vector<uint32_t> &pjidx, uint32_t entry, int32_t L, int32_t m_ce, int threads,
-                      const GpuCtx &gpu, Lists &E, std::vector<uint32_t> &head, std::vector<int32_t> &head_n,
-                      double *t_search) {
-    (void)pjoff;
-    (void)pjidx;
+// Enhancement on the device: the searches of every node on G_pj and each
+// node's own selection (AcquireNeighbors without fill), both with the
+// canonical FP64 distance, so the lists are bit-identical to the host's.
+// Only the selections and the first kHead candidates come back.  Double
+// buffered: batch i+1 runs on the device while batch i is copied out.
+int enhance_on_device(const float *X, int64_t n, int32_t d, const Lists &PJ, uint32_t entry, int32_t L, int32_t m_ce,
+                      int threads, const GpuCtx &gpu, Lists &E, std::vector<uint32_t> &head,
+                      std::vector<int32_t> &head_n, double *t_search) {
+    (void)X;
     int32_t maxdeg = 1;
     for (int64_t x = 0; x < n; ++x) maxdeg = std::max<int32_t>(maxdeg, PJ.deg[x]);
     const int32_t ell = (maxdeg + 7) / 8 * 8;
@@ -363,56 +423,70 @@ int enhance_on_device(const float *X, int64_t n, int32_t d, const Lists &PJ, con
     for (int64_t x = 0; x < n; ++x)
         for (int j = 0; j < PJ.deg[x]; ++j) adj[x * ell + j] = PJ.row(x)[j].id;
     const int64_t B = std::min<int64_t>(n, 1 << 15);
-    uint32_t *d_adj = nullptr;
-    uint32_t *d_ids[2] = {nullptr, nullptr}, *h_ids[2] = {nullptr, nullptr};
-    double *d_d[2] = {nullptr, nullptr}, *h_d[2] = {nullptr, nullptr};
-    int32_t *d_n[2] = {nullptr, nullptr}, *h_n[2] = {nullptr, nullptr};
+    const int32_t m = std::max(1, m_ce);
+    uint32_t *d_adj = nullptr, *d_q = nullptr;
+    double *d_qd = nullptr;
+    int32_t *d_qn = nullptr;
+    uint32_t *d_sid[2] = {nullptr, nullptr}, *h_sid[2] = {nullptr, nullptr};
+    double *d_sd[2] = {nullptr, nullptr}, *h_sd[2] = {nullptr, nullptr};
+    int32_t *d_sn[2] = {nullptr, nullptr}, *h_sn[2] = {nullptr, nullptr};
+    uint32_t *d_hd[2] = {nullptr, nullptr}, *h_hd[2] = {nullptr, nullptr};
+    int32_t *d_hn[2] = {nullptr, nullptr}, *h_hn[2] = {nullptr, nullptr};
     hipEvent_t ev[2] = {nullptr, nullptr};
     auto release = [&]() {
-        if (d_adj) (void)hipFree(d_adj);
+        for (void *p : {(void *)d_adj, (void *)d_q, (void *)d_qd, (void *)d_qn})
+            if (p) (void)hipFree(p);
         for (int i = 0; i < 2; ++i) {
-            if (d_ids[i]) (void)hipFree(d_ids[i]);
-            if (d_d[i]) (void)hipFree(d_d[i]);
-            if (d_n[i]) (void)hipFree(d_n[i]);
-            if (h_ids[i]) (void)hipHostFree(h_ids[i]);
-            if (h_d[i]) (void)hipHostFree(h_d[i]);
-            if (h_n[i]) (void)hipHostFree(h_n[i]);
+            for (void *p : {(void *)d_sid[i], (void *)d_sd[i], (void *)d_sn[i], (void *)d_hd[i], (void *)d_hn[i]})
+                if (p) (void)hipFree(p);
+            for (void *p : {(void *)h_sid[i], (void *)h_sd[i], (void *)h_sn[i], (void *)h_hd[i], (void *)h_hn[i]})
+                if (p) (void)hipHostFree(p);
             if (ev[i]) (void)hipEventDestroy(ev[i]);
         }
     };
-    bool ok = hipMalloc(&d_adj, sizeof(uint32_t) * adj.size()) == hipSuccess;
+    bool ok = hipMalloc(&d_adj, sizeof(uint32_t) * adj.size()) == hipSuccess &&
+              hipMalloc(&d_q, sizeof(uint32_t) * B * L) == hipSuccess &&
+              hipMalloc(&d_qd, sizeof(double) * B * L) == hipSuccess &&
+              hipMalloc(&d_qn, sizeof(int32_t) * B) == hipSuccess;
     for (int i = 0; i < 2 && ok; ++i)
-        ok = hipMalloc(&d_ids[i], sizeof(uint32_t) * B * L) == hipSuccess &&
-             hipMalloc(&d_d[i], sizeof(double) * B * L) == hipSuccess &&
-             hipMalloc(&d_n[i], sizeof(int32_t) * B) == hipSuccess &&
-             hipHostMalloc(&h_ids[i], sizeof(uint32_t) * B * L, hipHostMallocDefault) == hipSuccess &&
-             hipHostMalloc(&h_d[i], sizeof(double) * B * L, hipHostMallocDefault) == hipSuccess &&
-             hipHostMalloc(&h_n[i], sizeof(int32_t) * B, hipHostMallocDefault) == hipSuccess &&
+        ok = hipMalloc(&d_sid[i], sizeof(uint32_t) * B * m) == hipSuccess &&
+             hipMalloc(&d_sd[i], sizeof(double) * B * m) == hipSuccess &&
+             hipMalloc(&d_sn[i], sizeof(int32_t) * B) == hipSuccess &&
+             hipMalloc(&d_hd[i], sizeof(uint32_t) * B * kHead) == hipSuccess &&
+             hipMalloc(&d_hn[i], sizeof(int32_t) * B) == hipSuccess &&
+             hipHostMalloc(&h_sid[i], sizeof(uint32_t) * B * m, hipHostMallocDefault) == hipSuccess &&
+             hipHostMalloc(&h_sd[i], sizeof(double) * B * m, hipHostMallocDefault) == hipSuccess &&
+             hipHostMalloc(&h_sn[i], sizeof(int32_t) * B, hipHostMallocDefault) == hipSuccess &&
+             hipHostMalloc(&h_hd[i], sizeof(uint32_t) * B * kHead, hipHostMallocDefault) == hipSuccess &&
+             hipHostMalloc(&h_hn[i], sizeof(int32_t) * B, hipHostMallocDefault) == hipSuccess &&
              hipEventCreateWithFlags(&ev[i], hipEventDisableTiming) == hipSuccess;
     if (!ok) {
         release();
         set_error("build: out of memory for enhancement searches");
         return RG_ENOMEM;
     }
-    std::vector<std::vector<Cand>> cc((size_t)threads);
-    std::vector<std::vector<uint8_t>> kept((size_t)threads);
     const auto tstart = Clock::now();
     double t_host = 0.0;
     int rc = RG_OK;
-    // issue the search of batch b into buffer b % 2
+    // search and select batch b on the device, copy its selections into buffer b % 2
     auto issue = [&](int64_t b) -> int {
         const int64_t x0 = b * B, cnt = std::min(B, n - x0);
         const int i = (int)(b & 1);
-        int r = launch_canon_search(gpu.X, d, gpu.pitch, d_adj, ell, entry, L, x0, cnt, d_ids[i], d_d[i], d_n[i],
-                                    gpu.stream);
+        int r = launch_canon_search(gpu.X, d, gpu.pitch, d_adj, ell, entry, L, x0, cnt, d_q, d_qd, d_qn, gpu.stream);
+        if (!r)
+            r = launch_canon_select(gpu.X, d, gpu.pitch, d_q, d_qd, d_qn, L, x0, cnt, m, d_sid[i], d_sd[i], d_sn[i],
+                                    d_hd[i], kHead, d_hn[i], gpu.stream);
         if (r) return r;
-        if (hipMemcpyAsync(h_ids[i], d_ids[i], sizeof(uint32_t) * cnt * L, hipMemcpyDeviceToHost, gpu.stream) !=
+        if (hipMemcpyAsync(h_sid[i], d_sid[i], sizeof(uint32_t) * cnt * m, hipMemcpyDeviceToHost, gpu.stream) !=
                 hipSuccess ||
-            hipMemcpyAsync(h_d[i], d_d[i], sizeof(double) * cnt * L, hipMemcpyDeviceToHost, gpu.stream) !=
+            hipMemcpyAsync(h_sd[i], d_sd[i], sizeof(double) * cnt * m, hipMemcpyDeviceToHost, gpu.stream) !=
                 hipSuccess ||
-            hipMemcpyAsync(h_n[i], d_n[i], sizeof(int32_t) * cnt, hipMemcpyDeviceToHost, gpu.stream) != hipSuccess ||
+            hipMemcpyAsync(h_sn[i], d_sn[i], sizeof(int32_t) * cnt, hipMemcpyDeviceToHost, gpu.stream) != hipSuccess ||
+            hipMemcpyAsync(h_hd[i], d_hd[i], sizeof(uint32_t) * cnt * kHead, hipMemcpyDeviceToHost, gpu.stream) !=
+                hipSuccess ||
+            hipMemcpyAsync(h_hn[i], d_hn[i], sizeof(int32_t) * cnt, hipMemcpyDeviceToHost, gpu.stream) != hipSuccess ||
             hipEventRecord(ev[i], gpu.stream) != hipSuccess) {
-            set_error("build: enhancement search on the device failed");
+            set_error("build: enhancement on the device failed");
             return RG_EDEVICE;
         }
         return RG_OK;
@@ -427,31 +501,24 @@ int enhance_on_device(const float *X, int64_t n, int32_t d, const Lists &PJ, con
         if (rc) break;
         const int i = (int)(b & 1);
         if (hipEventSynchronize(ev[i]) != hipSuccess) {
-            set_error("build: enhancement search on the device failed");
+            set_error("build: enhancement on the device failed");
             rc = RG_EDEVICE;
             break;
         }
         const auto th0 = Clock::now();
         const int64_t x0 = b * B, cnt = std::min(B, n - x0);
-        const uint32_t *hid = h_ids[i];
-        const double *hd = h_d[i];
-        const int32_t *hn = h_n[i];
-        parallel_for(cnt, threads, 16, [&](int64_t bb, int tid) {
+        parallel_for(cnt, threads, 256, [&](int64_t bb, int) {
             const int64_t x = x0 + bb;
-            auto &c = cc[tid];
-            c.clear();
-            for (int j = 0; j < hn[bb]; ++j) {
-                const uint32_t u = hid[bb * L + j];
-                if ((int64_t)u != x) c.push_back(Cand{hd[bb * L + j], u});
-            }
-            head_n[x] = (int32_t)c.size();
-            for (int j = 0; j < kHead && j < (int)c.size(); ++j) head[x * kHead + j] = c[j].id;
-            E.deg[x] = acquire_sorted(X, d, c.data(), (int)c.size(), m_ce, false, E.row(x), kept[tid]);
+            const int ns = std::min(h_sn[i][bb], m);
+            for (int j = 0; j < ns; ++j) E.row(x)[j] = Cand{h_sd[i][bb * m + j], h_sid[i][bb * m + j]};
+            E.deg[x] = ns;
+            head_n[x] = h_hn[i][bb];
+            const int nh = std::min(head_n[x], kHead);
+            for (int j = 0; j < nh; ++j) head[x * kHead + j] = h_hd[i][bb * kHead + j];
         });
         t_host += secs(th0, Clock::now());
         if (std::getenv("RG_LOG"))
-            std::fprintf(stderr, "[rg] enhancement searches %lld / %lld nodes (host selection so far %.2f s)\n",
-                         (long long)(x0 + cnt), (long long)n, t_host);
+            std::fprintf(stderr, "[rg] enhancement searches %lld / %lld nodes\n", (long long)(x0 + cnt), (long long)n);
         // buffer i is reused by batch b + 2, issued in the next iteration
     }
     (void)hipStreamSynchronize(gpu.stream);
@@ -538,10 +605,11 @@ int host_construct(const float *X, int64_t n, int32_t d, const uint32_t *knn, in
         build_events(F, n, eoff, esrc);
         std::vector<std::vector<Cand>> cur((size_t)threads), tmp((size_t)threads);
         std::vector<std::vector<uint8_t>> kept((size_t)threads);
+        std::vector<PairCache> pcs((size_t)threads);
         parallel_for(n, threads, 256, [&](int64_t p, int tid) {
             const bool piv = boff[p] != boff[p + 1];
             replay(X, d, p, piv, F.row(p), piv ? F.deg[p] : 0, esrc.data() + eoff[p], eoff[p + 1] - eoff[p], m_pj,
-                   true, PJ.row(p), &PJ.deg[p], cur[tid], tmp[tid], kept[tid]);
+                   true, PJ.row(p), &PJ.deg[p], cur[tid], tmp[tid], kept[tid], pcs[tid]);
         });
     }
     std::vector<int64_t> pjoff;
@@ -596,7 +664,7 @@ int host_construct(const float *X, int64_t n, int32_t d, const uint32_t *knn, in
     std::vector<uint32_t> head((size_t)n * kHead, kNone);
     std::vector<int32_t> head_n((size_t)n, 0);
     if (gpu) {
-        const int rc = enhance_on_device(X, n, d, PJ, pjoff, pjidx, entry, L, m_ce, threads, *gpu, E, head, head_n,
+        const int rc = enhance_on_device(X, n, d, PJ, entry, L, m_ce, threads, *gpu, E, head, head_n,
                                          &out->t_enhance_search);
         if (rc) return rc;
     } else {
@@ -625,9 +693,10 @@ int host_construct(const float *X, int64_t n, int32_t d, const uint32_t *knn, in
         build_events(E, n, eoff, esrc);
         std::vector<std::vector<Cand>> cur((size_t)threads), tmp((size_t)threads);
         std::vector<std::vector<uint8_t>> kept((size_t)threads);
+        std::vector<PairCache> pcs((size_t)threads);
         parallel_for(n, threads, 256, [&](int64_t p, int tid) {
             replay(X, d, p, true, E.row(p), E.deg[p], esrc.data() + eoff[p], eoff[p + 1] - eoff[p], m_ce, false,
-                   CE.row(p), &CE.deg[p], cur[tid], tmp[tid], kept[tid]);
+                   CE.row(p), &CE.deg[p], cur[tid], tmp[tid], kept[tid], pcs[tid]);
         });
     }
     const auto t2 = Clock::now();

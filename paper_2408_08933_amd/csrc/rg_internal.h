@@ -187,6 +187,13 @@ int host_insert(StageGraphs &sg, int32_t d, int32_t M, int32_t m_pj, int32_t L, 
 void host_canon_searches(const float *X, int32_t d, const int64_t *off, const uint32_t *idx, uint32_t entry,
                          int32_t L, int64_t x0, int64_t count, int threads, uint32_t *ids, int32_t *counts);
 
+// canon.hip: AcquireNeighbors without fill over each searched node's queue
+// (the enhancement's own selection), canonical FP64, on the device
+int launch_canon_select(const float *X, int32_t d, int32_t pitch, const uint32_t *ids, const double *dists,
+                        const int32_t *counts, int32_t L, int64_t x0, int64_t count, int32_t m, uint32_t *sel_ids,
+                        double *sel_d, int32_t *sel_n, uint32_t *head, int32_t head_len, int32_t *head_n,
+                        hipStream_t stream);
+
 // canon.hip: construction-time searches with the canonical FP64 distance
 int launch_canon_search(const float *X, int32_t d, int32_t pitch, const uint32_t *adj, int32_t ell,
                         uint32_t entry, int32_t L, int64_t x0, int64_t count, uint32_t *ids, double *dists,
