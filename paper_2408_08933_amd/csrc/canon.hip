@@ -164,9 +164,31 @@ struct SelectArgs {
     int32_t *head_n;         // candidates per node (without the node)
 };
 
+// delta(c, kept row r) for r in [r0, r0 + nk), nk <= KG, for this lane's
+// candidate row c: one pass over c, one sequential FP64 chain per kept row
+// (each pair's sum runs in increasing i, as on the host).  kr(t) gives the
+// kept row r0 + t (in LDS, or in device memory when the rows do not fit).
+constexpr int KG = 16;
+template <class KR>
+__device__ __forceinline__ void canon_against_kept(const float *crow, KR kr, int d, int nk, double (&acc)[KG]) {
+    const float *kp[KG];
+#pragma unroll
+    for (int t = 0; t < KG; ++t) {
+        acc[t] = 0.0;
+        kp[t] = t < nk ? kr(t) : kr(0);
+    }
+    for (int i = 0; i < d; ++i) {
+        const double ci = (double)crow[i];
+#pragma unroll
+        for (int t = 0; t < KG; ++t)
+            if (t < nk) acc[t] = fma(ci, (double)kp[t][i], acc[t]);
+    }
+}
+
 __global__ __launch_bounds__(64) void k_canon_select(SelectArgs a) {
     extern __shared__ __align__(16) unsigned char smem[];
-    float *K = reinterpret_cast<float *>(smem);  // m x pitch kept rows
+    uint32_t *kid = reinterpret_cast<uint32_t *>(smem);   // m kept ids
+    float *K = reinterpret_cast<float *>(smem) + ((a.m + 3) & ~3);  // m x pitch kept rows (if they fit)
     const int lane = lane_id();
     const int64_t b = blockIdx.x;
     const uint32_t x = (uint32_t)(a.x0 + b);
@@ -174,32 +196,58 @@ __global__ __launch_bounds__(64) void k_canon_select(SelectArgs a) {
     const double *cdd = a.dists + b * a.L;
     const int qn = a.counts[b];
     int nr = 0, hn = 0;
-    uint32_t mine = kNone;  // lane r < nr: kept id r
-    for (int j = 0; j < qn; ++j) {
-        const uint32_t c = cid[j];
-        if (c == x) continue;
-        if (hn < a.head_len && lane == 0) a.head[b * a.head_len + hn] = c;
-        ++hn;
+    auto kept_row = [&](int r) -> const float * {
+        return a.kept_in_lds ? K + (size_t)r * a.pitch : a.X + (size_t)kid[r] * a.pitch;
+    };
+    // 64 candidates at a time, one per lane, in rank order
+    for (int j0 = 0; j0 < qn; j0 += 64) {
+        const int j = j0 + lane;
+        const uint32_t c = j < qn ? cid[j] : kNone;
+        const bool valid = j < qn && c != x;
+        const uint64_t vm = ballot64(valid);
+        const int pos = hn + lanes_below(vm);
+        if (valid && pos < a.head_len) a.head[b * a.head_len + pos] = c;
+        hn += (int)__popcll(vm);
         if (nr >= a.m) continue;
-        const double dxc = cdd[j];
-        bool lane_ok = true;
-        if (lane < nr) {
-            const float *pr = a.kept_in_lds ? K + (size_t)lane * a.pitch : a.X + (size_t)mine * a.pitch;
-            const float *cr = a.X + (size_t)c * a.pitch;
-            double s = 0.0;
-            for (int i = 0; i < a.d; ++i) s = fma((double)cr[i], (double)pr[i], s);
-            lane_ok = dxc < -s;
+        const double dxc = valid ? cdd[j] : 0.0;
+        const float *crow = a.X + (size_t)(valid ? c : 0u) * a.pitch;
+        // rejected by a row kept before this batch?
+        bool alive = valid;
+        for (int r0 = 0; r0 < nr && ballot64(alive) != 0; r0 += KG) {
+            const int nk = min(KG, nr - r0);
+            if (alive) {
+                double acc[KG];
+                canon_against_kept(crow, [&](int t) { return kept_row(r0 + t); }, a.d, nk, acc);
+#pragma unroll
+                for (int t = 0; t < KG; ++t)
+                    if (t < nk && !(dxc < -acc[t])) alive = false;
+            }
         }
-        if (ballot64(!lane_ok) != 0) continue;
-        if (lane == nr) mine = c;
-        if (a.kept_in_lds)
-            for (int i = lane; i < a.pitch; i += 64) K[(size_t)nr * a.pitch + i] = a.X[(size_t)c * a.pitch + i];
-        if (lane == 0) {
-            a.sel_ids[b * a.m + nr] = c;
-            a.sel_d[b * a.m + nr] = dxc;
+        // in rank order: the lowest surviving candidate is kept, and the
+        // later survivors are checked against it
+        for (;;) {
+            const uint64_t am = ballot64(alive);
+            if (am == 0 || nr >= a.m) break;
+            const int js = (int)__builtin_ctzll(am);
+            const uint32_t cs = (uint32_t)__shfl((int)c, js);
+            const double ds = __shfl(dxc, js);
+            if (a.kept_in_lds)
+                for (int i = lane; i < a.pitch; i += 64) K[(size_t)nr * a.pitch + i] = a.X[(size_t)cs * a.pitch + i];
+            if (lane == 0) {
+                kid[nr] = cs;
+                a.sel_ids[b * a.m + nr] = cs;
+                a.sel_d[b * a.m + nr] = ds;
+            }
+            ++nr;
+            __syncthreads();
+            if (lane == js) alive = false;
+            if (alive) {
+                double acc[KG];
+                const int rn = nr - 1;
+                canon_against_kept(crow, [&](int t) { return kept_row(rn + t); }, a.d, 1, acc);
+                if (!(dxc < -acc[0])) alive = false;
+            }
         }
-        ++nr;
-        __syncthreads();
     }
     if (lane == 0) {
         a.sel_n[b] = nr;
@@ -234,9 +282,11 @@ int launch_canon_select(const float *X, int32_t d, int32_t pitch, const uint32_t
     a.sel_n = sel_n;
     a.head = head;
     a.head_n = head_n;
+    const size_t id_bytes = (size_t)((m + 3) & ~3) * sizeof(uint32_t);
     const size_t kept_bytes = (size_t)m * pitch * sizeof(float);
-    a.kept_in_lds = kept_bytes <= (48u << 10);
-    hipLaunchKernelGGL(k_canon_select, dim3((unsigned)count), dim3(64), a.kept_in_lds ? kept_bytes : 0, stream, a);
+    a.kept_in_lds = id_bytes + kept_bytes <= (48u << 10);
+    hipLaunchKernelGGL(k_canon_select, dim3((unsigned)count), dim3(64), id_bytes + (a.kept_in_lds ? kept_bytes : 0),
+                       stream, a);
     RG_HIP(hipGetLastError());
     return RG_OK;
 }

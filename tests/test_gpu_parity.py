@@ -202,6 +202,18 @@ def test_build_bit_exact_c1(c1, c1_built):
     assert c1_built.build_stats()["repairs"] == G.repairs
 
 
+def test_build_bit_exact_wide_lists(dev, oracle_lib):
+    # M = 128 at d = 200: the enhancement selection keeps up to 63 rows per
+    # node, more than fit in LDS, so the device reads them from HBM
+    g = datagen.Generator(2, n=3000, n_train=3000, n_test=10, d=200)
+    X, Tr = g.base(), g.train()
+    say("rg_build 3000 x 200, Nq=48, M=128, L=200")
+    ix = rg.rg_build(T(X, dev), T(Tr, dev), 48, 128, L_build=200)
+    G = oracle_lib.Graph(X, Tr, 48, 128, 200)
+    off, idx, entry = ix.graph()
+    assert entry == G.entry and np.array_equal(off, G.offsets) and np.array_equal(idx, G.indices)
+
+
 def test_build_stage_graphs_c1(oracle_lib, c1, c1_built):
     X, Tr, Q, G = c1
     b_off, b_idx, n_off, nout = c1_built.bipartite()
