@@ -315,7 +315,7 @@ int launch_canon_search(const float *X, int32_t d, int32_t pitch, const uint32_t
     a.pitch = pitch;
     a.ell = ell;
     a.L = L;
-    a.hash_bits = 13;
+    a.hash_bits = 11;  // 8 KB of LDS: fastest at L = 500 (the table size bounds work, not results)
     a.entry = entry;
     const size_t lds = canon_lds_bytes(L, pitch, a.hash_bits);
     hipLaunchKernelGGL(k_canon_search, dim3((unsigned)count), dim3(64), lds, stream, a);

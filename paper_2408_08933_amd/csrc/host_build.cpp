@@ -211,44 +211,6 @@ int acquire_sorted(const float *X, int d, const Cand *C, int nc, int m, bool fil
     return nr;
 }
 
-// Canonical distances between pairs of rows, remembered while one node's
-// reverse insertions are replayed (the same pairs recur from one insertion
-// to the next).  delta is symmetric bit for bit (the products commute, the
-// sum runs in increasing i), so a pair is keyed without order.  Forgetting
-// (a clear when the table fills) only costs recomputation.
-class PairCache {
-  public:
-    explicit PairCache(int bits = 16) : mask_((1u << bits) - 1u), key_((size_t)1 << bits, kFree),
-                                        val_((size_t)1 << bits, 0.0) {}
-    void clear() {
-        for (uint32_t h : used_) key_[h] = kFree;
-        used_.clear();
-    }
-    double get(const float *X, int d, uint32_t a, uint32_t b) {
-        const uint64_t k = a < b ? ((uint64_t)a << 32 | b) : ((uint64_t)b << 32 | a);
-        uint32_t h = (uint32_t)((k * 0x9E3779B97F4A7C15ull) >> 40) & mask_;
-        while (key_[h] != kFree) {
-            if (key_[h] == k) return val_[h];
-            h = (h + 1u) & mask_;
-        }
-        const double v = canon_dist(X + (int64_t)a * d, X + (int64_t)b * d, d);
-        if (used_.size() * 2 > mask_) clear();  // keep the load under one half
-        h = (uint32_t)((k * 0x9E3779B97F4A7C15ull) >> 40) & mask_;
-        while (key_[h] != kFree) h = (h + 1u) & mask_;
-        key_[h] = k;
-        val_[h] = v;
-        used_.push_back(h);
-        return v;
-    }
-
-  private:
-    static constexpr uint64_t kFree = ~0ull;
-    uint32_t mask_;
-    std::vector<uint64_t> key_;
-    std::vector<double> val_;
-    std::vector<uint32_t> used_;
-};
-
 // acquire_sorted with the candidate-to-kept distances taken from a cache.
 int acquire_sorted_cached(const float *X, int d, const Cand *C, int nc, int m, bool fill, Cand *res,
                           std::vector<uint8_t> &kept, PairCache &pc) {
@@ -898,6 +860,7 @@ int host_insert(StageGraphs &sg, int32_t d, int32_t M, int32_t m_pj, int32_t L, 
     Pool pool(hw_threads(threads));
     std::vector<std::vector<Cand>> tcand((size_t)pool.size()), tres((size_t)pool.size());
     std::vector<std::vector<uint8_t>> tkept((size_t)pool.size());
+
     std::vector<uint32_t> full;
     std::vector<uint8_t> keeps_v;
     for (int64_t i = 0; i < nv; ++i) {

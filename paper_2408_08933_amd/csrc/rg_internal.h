@@ -127,6 +127,47 @@ int launch_copy_probe(void *dst, const void *src, int64_t bytes, hipStream_t str
 // out-lists N_out(t) of the training queries without their pivot), its
 // base-to-base routing rows (row x = N_out(t) for each t in B(x)) with their
 // entry, and the projected graph G_pj (rows sorted by neighbour id).
+// canonical FP64 distance: -sum_i a_i b_i, exact products added in increasing i
+double canon_dist(const float *a, const float *b, int32_t d);
+
+// Canonical distances between pairs of base rows, remembered while one
+// node's reverse insertions are replayed (the same pairs recur from one
+// insertion to the next).  delta is symmetric bit for bit (the products commute, the
+// sum runs in increasing i), so a pair is keyed without order.  Forgetting
+// (a clear when the table fills) only costs recomputation.
+class PairCache {
+  public:
+    explicit PairCache(int bits = 16) : mask_((1u << bits) - 1u), key_((size_t)1 << bits, kFree),
+                                        val_((size_t)1 << bits, 0.0) {}
+    void clear() {
+        for (uint32_t h : used_) key_[h] = kFree;
+        used_.clear();
+    }
+    double get(const float *X, int d, uint32_t a, uint32_t b) {
+        const uint64_t k = a < b ? ((uint64_t)a << 32 | b) : ((uint64_t)b << 32 | a);
+        uint32_t h = (uint32_t)((k * 0x9E3779B97F4A7C15ull) >> 40) & mask_;
+        while (key_[h] != kFree) {
+            if (key_[h] == k) return val_[h];
+            h = (h + 1u) & mask_;
+        }
+        const double v = canon_dist(X + (int64_t)a * d, X + (int64_t)b * d, d);
+        if (used_.size() * 2 > mask_) clear();  // keep the load under one half
+        h = (uint32_t)((k * 0x9E3779B97F4A7C15ull) >> 40) & mask_;
+        while (key_[h] != kFree) h = (h + 1u) & mask_;
+        key_[h] = k;
+        val_[h] = v;
+        used_.push_back(h);
+        return v;
+    }
+
+  private:
+    static constexpr uint64_t kFree = ~0ull;
+    uint32_t mask_;
+    std::vector<uint64_t> key_;
+    std::vector<double> val_;
+    std::vector<uint32_t> used_;
+};
+
 // Insertion (updates through the saved bipartite graph) also needs the
 // vectors on the host, the ids appended to each N_out(t) since the build,
 // and, per base node, the queries whose N_out holds it.
