@@ -94,8 +94,11 @@ __device__ __forceinline__ int compact_row(float *bsc, uint32_t *bid, int c, int
 }
 
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k_knn(KnnArgs a) {
-    __shared__ __align__(16) float As[BQ * KCP];
-    __shared__ __align__(16) float Bs[BX * KCP];
+    // two LDS buffers per operand: the MFMAs read one slice while the next is
+    // stored into the other, one barrier per slice (73.7 KB per workgroup,
+    // two workgroups per CU)
+    __shared__ __align__(16) float As[2][BQ * KCP];
+    __shared__ __align__(16) float Bs[2][BX * KCP];
     __shared__ float thr[BQ];
     __shared__ int cnt[BQ];
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
@@ -116,8 +119,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
     const int64_t xt1 = min(a.xtiles, xt0 + a.xtiles_per_split);
     const int lr = tid >> 3, lk = (tid & 7) * 4;
     const int kq = (lane >> 4) * 8;  // this lane's coordinates within a slice
-    // the next coordinate slice of the tile is loaded into registers while
-    // the current one feeds the MFMAs
+    const int nsl = (a.d + KC - 1) / KC;
     float4 va[4], vb[4];
     auto load_slice = [&](int64_t xt, int k0) {
         const int64_t x0 = xt * BX;
@@ -127,33 +129,39 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
             vb[p] = ld4(a.X, a.n, a.ldx, a.d, x0 + p * 32 + lr, k0 + lk, vx);
         }
     };
+    auto store_slice = [&](int buf) {
+#pragma unroll
+        for (int p = 0; p < 4; ++p) {
+            const int r = p * 32 + lr;
+            *reinterpret_cast<float4 *>(&As[buf][r * KCP + lk]) = va[p];
+            *reinterpret_cast<float4 *>(&Bs[buf][r * KCP + lk]) = vb[p];
+        }
+    };
     for (int64_t xt = xt0; xt < xt1; ++xt) {
         const int64_t x0 = xt * BX;
         load_slice(xt, 0);
+        store_slice(0);
+        __syncthreads();
         fx4 acc[4][4];
 #pragma unroll
         for (int i = 0; i < 4; ++i)
 #pragma unroll
             for (int j = 0; j < 4; ++j) acc[i][j] = fx4{0.f, 0.f, 0.f, 0.f};
-        for (int k0 = 0; k0 < a.d; k0 += KC) {
-            __syncthreads();
-#pragma unroll
-            for (int p = 0; p < 4; ++p) {
-                const int r = p * 32 + lr;
-                *reinterpret_cast<float4 *>(&As[r * KCP + lk]) = va[p];
-                *reinterpret_cast<float4 *>(&Bs[r * KCP + lk]) = vb[p];
-            }
-            __syncthreads();
-            if (k0 + KC < a.d) load_slice(xt, k0 + KC);
+        for (int sl = 0; sl < nsl; ++sl) {
+            const int buf = sl & 1;
+            const bool more = sl + 1 < nsl;
+            if (more) load_slice(xt, (sl + 1) * KC);
 #pragma unroll 1
             for (int h = 0; h < 2; ++h) {
                 float4 af[4], bf[4];
 #pragma unroll
                 for (int i = 0; i < 4; ++i)
-                    af[i] = *reinterpret_cast<const float4 *>(&As[(wr * 64 + i * 16 + (lane & 15)) * KCP + kq + 4 * h]);
+                    af[i] = *reinterpret_cast<const float4 *>(
+                        &As[buf][(wr * 64 + i * 16 + (lane & 15)) * KCP + kq + 4 * h]);
 #pragma unroll
                 for (int j = 0; j < 4; ++j)
-                    bf[j] = *reinterpret_cast<const float4 *>(&Bs[(wc * 64 + j * 16 + (lane & 15)) * KCP + kq + 4 * h]);
+                    bf[j] = *reinterpret_cast<const float4 *>(
+                        &Bs[buf][(wc * 64 + j * 16 + (lane & 15)) * KCP + kq + 4 * h]);
 #pragma unroll
                 for (int t = 0; t < 4; ++t)
 #pragma unroll
@@ -162,6 +170,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
                         for (int j = 0; j < 4; ++j)
                             acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(af[i][t], bf[j][t], acc[i][j], 0, 0, 0);
             }
+            if (more) store_slice(buf ^ 1);
+            __syncthreads();
         }
         // filter: accumulator element r of block (i, j) is row 4*(lane/16)+r, column lane%16
 #pragma unroll
