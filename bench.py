@@ -151,7 +151,7 @@ def serve_run(rg, ix, Qh, gt, n_req, rate, seed=0, timeout=120.0):
             "recall": hit / max(tot, 1), "steps": st["steps"]}
 
 
-def serve_latency(rg, ix, Qh, gt, n_req=20000):
+def serve_latency(rg, ix, Qh, gt, n_req=100000):
     """Closed-loop capacity, then Poisson arrivals at 0.5, 0.8, 0.95 of it."""
     cap = serve_run(rg, ix, Qh, gt, n_req, None, seed=1)
     lam = cap["achieved_qps"]

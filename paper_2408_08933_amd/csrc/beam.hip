@@ -514,9 +514,10 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void k_
 }
 
 // One scheduler step of the serving loop: advance each listed slot by up to
-// hops_budget expansions, keeping its whole state in device memory.
+// hops_budget expansions, keeping its whole state in device memory.  Five
+// resident wavefronts per SIMD, as for k_search: the step is latency-bound.
 template <int ST, int CLS>
-__global__ __launch_bounds__(64) void k_serve_step(SlotArgs sa) {
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(5))) void k_serve_step(SlotArgs sa) {
     extern __shared__ __align__(16) unsigned char smem[];
     const int slot = sa.active[blockIdx.x];
     SearchArgs a = sa.s;

@@ -52,62 +52,107 @@ __device__ __forceinline__ int count_le(const int32_t *slb, int S, int i) {
 // the queue is not full) and are not already queued, then move queue
 // entries and survivors to their merged places, truncating at Leff.  The
 // result is the best Leff of queue u batch, whatever the batch order.
+// Survivors (entries that beat the last key of a full queue and are not
+// queued yet) at most this many are ordered by counting instead of sorting
+// the whole batch.
+constexpr int kRankByCount = 16;
+
 template <int E, typename K>
 __device__ __forceinline__ void merge_batch(const QueueLds<K> &s, int cnt, int Leff, int &qn, int &ptr) {
     const int lane = lane_id();
-    if (qn == Leff) {  // full queue: nothing to do unless some candidate beats the last entry
-        const K ld = s.qd[Leff - 1];
-        const uint32_t li = s.qi[Leff - 1] & ~kExpanded;
-        bool any = false;
-        for (int i = lane; i < cnt; i += 64) any |= kless(s.cd[i], s.ci[i], ld, li);
-        if (ballot64(any) == 0) return;
-    }
-    K k[E];
-    uint32_t id[E];
-#pragma unroll
-    for (int e = 0; e < E; ++e) {
-        const int i = lane * E + e;
-        k[e] = i < cnt ? s.cd[i] : (K)__builtin_inf();
-        id[e] = i < cnt ? s.ci[i] : kNone;
-    }
-    wave_sort<E, K>(k, id);
     const bool full = qn == Leff;
     const K lastd = full ? s.qd[Leff - 1] : (K)0;
     const uint32_t lasti = full ? (s.qi[Leff - 1] & ~kExpanded) : 0u;
-    int lb[E];
-    bool sv[E];
-    int mine = 0;
-#pragma unroll
-    for (int e = 0; e < E; ++e) {
-        sv[e] = id[e] != kNone && (!full || kless(k[e], id[e], lastd, lasti));
-        lb[e] = 0;
-        if (sv[e]) {
-            lb[e] = lower_bound_q(s.qd, s.qi, qn, k[e], id[e]);
-            if (lb[e] < qn && (s.qi[lb[e]] & ~kExpanded) == id[e]) sv[e] = false;  // already queued
+    int total = 0;
+    bool sorted = false;
+    if constexpr (E == 1) {
+        // one candidate per lane: find the survivors and their queue ranks
+        K kc = (K)__builtin_inf();
+        uint32_t ic = kNone;
+        bool sv = false;
+        int lbc = 0;
+        if (lane < cnt) {
+            kc = s.cd[lane];
+            ic = s.ci[lane];
+            sv = ic != kNone && (!full || kless(kc, ic, lastd, lasti));
         }
-        mine += sv[e] ? 1 : 0;
-    }
-    // order-preserving compaction: exclusive prefix of per-lane counts
-    int incl = mine;
-#pragma unroll
-    for (int o = 1; o < 64; o <<= 1) {
-        const int t = __shfl_up(incl, o);
-        if (lane >= o) incl += t;
-    }
-    const int total = __shfl(incl, 63);
-    int w = incl - mine;
-    __syncthreads();
-#pragma unroll
-    for (int e = 0; e < E; ++e) {
-        if (sv[e]) {
-            s.sd[w] = k[e];
-            s.si[w] = id[e];
-            s.slb[w] = lb[e];
-            ++w;
+        if (sv) {
+            lbc = lower_bound_q(s.qd, s.qi, qn, kc, ic);
+            if (lbc < qn && (s.qi[lbc] & ~kExpanded) == ic) sv = false;  // already queued
         }
+        const uint64_t m = ballot64(sv);
+        total = (int)__popcll(m);
+        if (total == 0) return;
+        if (total <= kRankByCount) {
+            // survivor order = number of survivors that precede it
+            __syncthreads();
+            if (sv) {
+                s.sd[lanes_below(m)] = kc;
+                s.si[lanes_below(m)] = ic;
+            }
+            __syncthreads();
+            int rank = 0;
+            if (sv)
+                for (int t = 0; t < total; ++t) rank += kless(s.sd[t], s.si[t], kc, ic) ? 1 : 0;
+            __syncthreads();
+            if (sv) {
+                s.sd[rank] = kc;
+                s.si[rank] = ic;
+                s.slb[rank] = lbc;
+            }
+            __syncthreads();
+            sorted = true;
+        }
+    } else if (full) {  // nothing to do unless some candidate beats the last entry
+        bool any = false;
+        for (int i = lane; i < cnt; i += 64) any |= kless(s.cd[i], s.ci[i], lastd, lasti);
+        if (ballot64(any) == 0) return;
     }
-    __syncthreads();
-    if (total == 0) return;
+    if (!sorted) {
+        K k[E];
+        uint32_t id[E];
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+            const int i = lane * E + e;
+            k[e] = i < cnt ? s.cd[i] : (K)__builtin_inf();
+            id[e] = i < cnt ? s.ci[i] : kNone;
+        }
+        wave_sort<E, K>(k, id);
+        int lb[E];
+        bool sv[E];
+        int mine = 0;
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+            sv[e] = id[e] != kNone && (!full || kless(k[e], id[e], lastd, lasti));
+            lb[e] = 0;
+            if (sv[e]) {
+                lb[e] = lower_bound_q(s.qd, s.qi, qn, k[e], id[e]);
+                if (lb[e] < qn && (s.qi[lb[e]] & ~kExpanded) == id[e]) sv[e] = false;  // already queued
+            }
+            mine += sv[e] ? 1 : 0;
+        }
+        // order-preserving compaction: exclusive prefix of per-lane counts
+        int incl = mine;
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+            const int t = __shfl_up(incl, o);
+            if (lane >= o) incl += t;
+        }
+        total = __shfl(incl, 63);
+        int w = incl - mine;
+        __syncthreads();
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+            if (sv[e]) {
+                s.sd[w] = k[e];
+                s.si[w] = id[e];
+                s.slb[w] = lb[e];
+                ++w;
+            }
+        }
+        __syncthreads();
+        if (total == 0) return;
+    }
     const int lbmin = s.slb[0];
     // entries of the queue that move, and their new places
     constexpr int R = kMaxL / 64;
