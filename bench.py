@@ -166,8 +166,9 @@ def serve_latency(rg, ix, Qh, gt, n_req=100000):
 
 
 def storage_rows(rg, ix, st, n, d, pitch):
-    """The device's reduced-precision rows, decoded to FP32 on the host
-    (BF16: exact widening; FP8: code value times the row scale)."""
+    """A function pick -> the device's reduced-precision rows `pick`,
+    decoded to FP32 on the host (BF16: exact widening; FP8: code value times
+    the row scale).  The whole stored array is copied once."""
     import ctypes
     import torch
     hip = ctypes.CDLL("libamdhip64.so")
@@ -175,20 +176,23 @@ def storage_rows(rg, ix, st, n, d, pitch):
     if st == rg.RG_STORE_BF16:
         h = np.empty((n, pitch), np.uint16)
         assert hip.hipMemcpy(ctypes.c_void_p(h.ctypes.data), ctypes.c_void_p(pb), ctypes.c_size_t(h.nbytes), 2) == 0
-        return torch.from_numpy(h[:, :d].copy()).view(torch.bfloat16).float().numpy()
+        return lambda pick: torch.from_numpy(h[pick, :d].copy()).view(torch.bfloat16).float().numpy()
     h = np.empty((n, p8), np.uint8)
     sc = np.empty(n, np.float32)
     assert hip.hipMemcpy(ctypes.c_void_p(h.ctypes.data), ctypes.c_void_p(pf), ctypes.c_size_t(h.nbytes), 2) == 0
     assert hip.hipMemcpy(ctypes.c_void_p(sc.ctypes.data), ctypes.c_void_p(ps), ctypes.c_size_t(sc.nbytes), 2) == 0
-    v = torch.from_numpy(h[:, :d].copy()).view(torch.float8_e4m3fn).float().numpy()
-    return v * sc[:, None]
+    return lambda pick: (torch.from_numpy(h[pick, :d].copy()).view(torch.float8_e4m3fn).float().numpy()
+                         * sc[pick][..., None])
 
 
 def distance_errors(Xh, Qh, ids, ds, rows=None, nq=1000, n_rand=100, seed=3):
     """Errors against FP64, in units of |q| * max|x|: the returned distances
-    (after the FP32 rerank for reduced storage) and, for reduced storage, the
-    search-phase score on the stored rows for sampled (query, row) pairs."""
-    xmax = float(np.sqrt((Xh.astype(np.float64) ** 2).sum(1)).max())
+    (after the FP32 rerank for reduced storage) and, for reduced storage
+    (rows = storage_rows(...)), the search-phase score on the stored rows for
+    sampled (query, row) pairs."""
+    xmax = 0.0
+    for a0 in range(0, Xh.shape[0], 1 << 20):
+        xmax = max(xmax, float(np.sqrt((Xh[a0:a0 + (1 << 20)].astype(np.float64) ** 2).sum(1)).max()))
     Q64 = Qh[:nq].astype(np.float64)
     scale = np.linalg.norm(Q64, axis=1) * xmax
     a = ids[:nq].astype(np.int64)
@@ -198,7 +202,7 @@ def distance_errors(Xh, Qh, ids, ds, rows=None, nq=1000, n_rand=100, seed=3):
         rng = np.random.default_rng(seed)
         pick = np.concatenate([a, rng.integers(0, Xh.shape[0], (nq, n_rand))], axis=1)
         e64 = -np.einsum("qkd,qd->qk", Xh[pick].astype(np.float64), Q64)
-        eq = -np.einsum("qkd,qd->qk", rows[pick].astype(np.float64), Q64)
+        eq = -np.einsum("qkd,qd->qk", rows(pick).astype(np.float64), Q64)
         rel = np.abs(eq - e64) / scale[:, None]
         out.update({"score_max": float(rel.max()), "score_mean": float(rel.mean())})
     return out
@@ -347,6 +351,88 @@ def ablation(rg, torch, dev, n):
     return out
 
 
+# Storage forms measured per workload: the configuration's own form next to
+# plain FP32 (the 10M x 200 serving workload is plain FP32; the reduced forms
+# are added there for comparison).
+WORKLOAD_FORMS = {3: ("fp32", "bf16"), 4: ("fp32", "bf16", "fp8"), 5: ("fp32", "fp8")}
+
+
+def workload_run(rg, torch, dev, wid, train_frac, steps, serve_req):
+    """The method end to end on another workload shape (not the headline
+    line): build from |T| = train_frac |X| training queries, graph checks,
+    then per storage form QPS at recall@10 = 0.90 (and recall@100 for the
+    CLIP-like shape, which asks for k = 100), the recall of the reduced form
+    at the FP32 operating L, distance errors against FP64 and serving
+    latency at three Poisson rates."""
+    import datagen
+    w = datagen.WORKLOADS[wid]
+    nt = int(round(train_frac * w.n_train))
+    g = datagen.Generator(wid, n=w.n, n_train=nt, n_test=w.n_test)
+    log(f"workload {w.name}: n={w.n} d={w.d} train={nt} test={w.n_test} Nq={w.Nq} M={w.M}")
+    t = time.time()
+    Xh, Th, Qh = g.base(), g.train(), g.test()
+    log(f"data generated in {time.time() - t:.1f} s")
+    X = torch.from_numpy(Xh).to(dev)
+    Q = torch.from_numpy(Qh).to(dev)
+    Tr = torch.from_numpy(Th).to(dev)
+    del Th
+    t = time.time()
+    ix = rg.rg_build(X, Tr, w.Nq, w.M, L_build=500)
+    torch.cuda.synchronize()
+    bstats = ix.build_stats()
+    bstats["wall_s"] = time.time() - t
+    del Tr
+    torch.cuda.empty_cache()
+    log(f"build: {bstats}")
+    off, idx, entry = ix.graph()
+    bstats["checks"] = graph_checks(off, idx, entry, w.M)
+    log(f"graph checks: {bstats['checks']}")
+    del off, idx
+    gt100 = rg.as_u32(rg.rg_knn(Q, X, 100)[0])
+    info = ix.info()
+    nq = Q.shape[0]
+    out = {"workload": w.name, "n_base": w.n, "d": w.d, "n_train": nt, "n_test": int(nq), "Nq": w.Nq, "M": w.M,
+           "L_build": 500, "metric_space": "cosine" if w.normalize else "inner product", "build": bstats,
+           "forms": {}, "data": "synthetic"}
+    L32 = {}
+    for name in WORKLOAD_FORMS[wid]:
+        st = {"fp32": rg.RG_STORE_FP32, "bf16": rg.RG_STORE_BF16, "fp8": rg.RG_STORE_FP8E4M3}[name]
+        rg.rg_index_set_storage(ix, st)
+        f = {}
+        for k, grid in ((10, L_GRID), (100, [L for L in L_GRID if L >= 100])):
+            if k == 100 and wid != 3:
+                continue
+            log(f"{name} sweep, k={k}")
+            L, curve = sweep(rg, torch, ix, Q, gt100[:, :k], k, grid, 0.90)
+            if L is None:
+                L = grid[-1]
+            wall, lm = time_search(rg, torch, ix, Q, k, L, steps, 2)
+            f[f"k{k}"] = {"L": L, f"recall_at_{k}": dict(curve)[L], "qps": nq * steps / wall,
+                          "ms_per_launch": float(np.mean(lm)), "curve": [[a, b] for a, b in curve]}
+            if name == "fp32":
+                L32[k] = L
+            else:
+                ids, _ = rg.rg_search(ix, Q, k, L32[k])
+                torch.cuda.synchronize()
+                f[f"k{k}"]["recall_at_fp32_L"] = {"L": L32[k], "recall": recall_at(rg.as_u32(ids), gt100, k)}
+            log(f"  {name} k={k}: {f[f'k{k}']}")
+        ids, ds = rg.rg_search(ix, Q, 10, f["k10"]["L"])
+        torch.cuda.synchronize()
+        rows = None if st == rg.RG_STORE_FP32 else storage_rows(rg, ix, st, w.n, w.d, info["pitch"])
+        f["dist_err_vs_fp64"] = distance_errors(Xh, Qh, rg.as_u32(ids), ds.cpu().numpy(), rows=rows)
+        del rows
+        log(f"  {name} distance error: {f['dist_err_vs_fp64']}")
+        if wid in (4, 5) and serve_req:
+            log(f"serving {name}")
+            f["serving"] = serve_latency(rg, ix, Qh, gt100, n_req=serve_req)
+        out["forms"][name] = f
+    rg.rg_index_set_storage(ix, rg.RG_STORE_FP32)
+    base = out["forms"]["fp32"]["k10"]["qps"]
+    for name, f in out["forms"].items():
+        f["qps_vs_fp32_at_recall_0.90"] = f["k10"]["qps"] / base
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -360,6 +446,11 @@ def main():
     ap.add_argument("--copy-probe", action="store_true", help="run a 1 GiB plain copy kernel (traffic calibration)")
     ap.add_argument("--ablation", action="store_true",
                     help="instead of the benchmark: G_bi / G_pj / RoarGraph, |T| = 0.1/0.5/1 |X|, ID queries")
+    ap.add_argument("--workload", type=int, choices=(3, 4, 5), default=None,
+                    help="instead of the benchmark: the method end to end on the CLIP-like 2M x 512 (3), "
+                         "10M x 200 serving (4) or 8M x 512 FP8 serving (5) shape")
+    ap.add_argument("--train-frac", type=float, default=1.0, help="|T| / |X| for --workload")
+    ap.add_argument("--serve-requests", type=int, default=100000, help="requests per serving run (--workload)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: this build runs on exactly one GPU; --gpus N > 1 is not supported", file=sys.stderr)
@@ -375,6 +466,10 @@ def main():
     w = datagen.WORKLOADS[2]
     if args.ablation:
         print(json.dumps({"ablation": ablation(rg, torch, dev, args.n or w.n)}), flush=True)
+        return
+    if args.workload:
+        r = workload_run(rg, torch, dev, args.workload, args.train_frac, 10, args.serve_requests)
+        print(json.dumps({"workload_run": r}), flush=True)
         return
     n = args.n or w.n
     g = datagen.Generator(2, n=n, n_train=n, n_test=w.n_test)

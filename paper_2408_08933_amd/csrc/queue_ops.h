@@ -52,10 +52,10 @@ __device__ __forceinline__ int count_le(const int32_t *slb, int S, int i) {
 // the queue is not full) and are not already queued, then move queue
 // entries and survivors to their merged places, truncating at Leff.  The
 // result is the best Leff of queue u batch, whatever the batch order.
-// Survivors (entries that beat the last key of a full queue and are not
-// queued yet) at most this many are ordered by counting instead of sorting
-// the whole batch.
-constexpr int kRankByCount = 16;
+// When at most this many candidates survive (they beat the last key of a
+// full queue and are not queued yet), they are ordered by counting the
+// survivors ahead of each one instead of sorting the whole batch.
+constexpr int kRankByCount = 32;
 
 template <int E, typename K>
 __device__ __forceinline__ void merge_batch(const QueueLds<K> &s, int cnt, int Leff, int &qn, int &ptr) {
