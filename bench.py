@@ -387,6 +387,7 @@ def workload_run(rg, torch, dev, wid, train_frac, steps, serve_req):
     off, idx, entry = ix.graph()
     bstats["checks"] = graph_checks(off, idx, entry, w.M)
     log(f"graph checks: {bstats['checks']}")
+    avg_deg = float(np.diff(off).mean())
     del off, idx
     gt100 = rg.as_u32(rg.rg_knn(Q, X, 100)[0])
     info = ix.info()
@@ -407,10 +408,27 @@ def workload_run(rg, torch, dev, wid, train_frac, steps, serve_req):
             if L is None:
                 L = grid[-1]
             wall, lm = time_search(rg, torch, ix, Q, k, L, steps, 2)
+            bpr = {"fp32": 4.0 * w.d, "bf16": 2.0 * w.d, "fp8": w.d + 4.0}[name]
+            b, vm, hm = algorithmic_bytes(rg, torch, ix, Q, k, L, w.d, bpr, avg_deg)
+            if name != "fp32":
+                b += nq * max(L, k) * 4.0 * w.d   # the FP32 rerank of the final queue
             f[f"k{k}"] = {"L": L, f"recall_at_{k}": dict(curve)[L], "qps": nq * steps / wall,
-                          "ms_per_launch": float(np.mean(lm)), "curve": [[a, b] for a, b in curve]}
+                          "ms_per_launch": float(np.mean(lm)), "mean_visits": vm, "mean_hops": hm,
+                          "algorithmic_GBps": b / (np.mean(lm) * 1e-3) / 1e9,
+                          "curve": [[a, b] for a, b in curve]}
             if name == "fp32":
                 L32[k] = L
+                # the LDS visited table in place of the HBM bitmap, at the same L
+                # (the bitmap costs n/8 bytes per query to clear)
+                f[f"k{k}"]["lds_table_ms_per_launch"] = {}
+                for hb in (10, 11):
+                    rg.rg_search(ix, Q, k, L, hash_bits=hb)
+                    torch.cuda.synchronize()
+                    t0 = time.perf_counter()
+                    for _ in range(steps):
+                        rg.rg_search(ix, Q, k, L, hash_bits=hb)
+                    torch.cuda.synchronize()
+                    f[f"k{k}"]["lds_table_ms_per_launch"][hb] = (time.perf_counter() - t0) / steps * 1e3
             else:
                 ids, _ = rg.rg_search(ix, Q, k, L32[k])
                 torch.cuda.synchronize()

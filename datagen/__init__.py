@@ -24,7 +24,12 @@ Real text and image embeddings have an intrinsic dimension far below d;
 both modalities live in one shared semantic subspace:
   * U = a random orthonormal d x r basis (r = 32), shared by both sets;
   * latent centres c_j ~ N(0, I_r), independent sets for base and queries;
-  * h = c_z + 0.5 g_r, point = (U h + 0.6 g_d) / sqrt(r), g ~ N(0, I).
+  * h = c_z + 0.5 g_r, point = (U h + a g_d) / sqrt(r), g ~ N(0, I), with
+    a = 0.6 at d = 200 and a = 0.375 at d = 512: the off-subspace noise has
+    the same norm (about 1.5 / sqrt(r) of the point) at both widths, next to
+    a subspace part of norm about 1.1.  At a = 0.6 and d = 512 the noise
+    would be twice the signal, and normalised rows would be nearly random
+    directions with no usable neighbour structure.
 
 For both laws a query is s (.) point' + G u, with point' from the query
 mixture, u a fixed random unit vector (the "modality gap", norm G) and s a
@@ -70,11 +75,11 @@ WORKLOADS = {
     2: Workload("t2i-like-d200", 2, 200, 1_000_000, 1_000_000, 10_000, 256, 256, 1.5, False, (0.5, 1.5), 100, 64,
                 latent=32),
     3: Workload("clip-like-d512", 3, 512, 2_000_000, 2_000_000, 10_000, 1024, 1024, 0.8, True, None, 100, 64,
-                latent=32),
+                latent=32, ambient_noise=0.375),
     4: Workload("serve-d200-10M", 4, 200, 10_000_000, 10_000_000, 10_000, 1024, 1024, 1.5, False, (0.5, 1.5), 100,
                 64, latent=32),
     5: Workload("serve-fp8-d512-8M", 5, 512, 8_000_000, 8_000_000, 10_000, 1024, 1024, 0.8, True, None, 100, 64,
-                latent=32),
+                latent=32, ambient_noise=0.375),
 }
 
 

@@ -479,7 +479,9 @@ int enhance_on_device(const float *X, int64_t n, int32_t d, const Lists &PJ, uin
             for (int j = 0; j < nh; ++j) head[x * kHead + j] = h_hd[i][bb * kHead + j];
         });
         t_host += secs(th0, Clock::now());
-        if (std::getenv("RG_LOG"))
+        // about ten progress lines per build
+        const int64_t step = std::max<int64_t>(cnt, (n / 10 + cnt - 1) / cnt * cnt);
+        if (std::getenv("RG_LOG") && ((x0 + cnt) % step == 0 || x0 + cnt == n))
             std::fprintf(stderr, "[rg] enhancement searches %lld / %lld nodes\n", (long long)(x0 + cnt), (long long)n);
         // buffer i is reused by batch b + 2, issued in the next iteration
     }
@@ -700,6 +702,10 @@ int host_construct(const float *X, int64_t n, int32_t d, const uint32_t *knn, in
         };
         bfs();
         Searcher s;
+        // order[0 .. first_free) are all full; rows only grow, so the first
+        // node of `order` with a free slot never moves back
+        size_t first_free = 0;
+        int64_t searches = 0;
         for (int64_t u = 0; u < n; ++u) {
             if (seen[u]) continue;
             // first node of u's enhancement candidates (queue order) with a free
@@ -711,14 +717,17 @@ int host_construct(const float *X, int64_t n, int32_t d, const uint32_t *knn, in
             }
             if (r < 0 && head_n[u] > kHead) {  // rare: the stored head is full, search again
                 if (s.stamp.empty()) s.init(n, L);
+                ++searches;
                 const int qn = s.run(X, d, pjoff.data(), pjidx.data(), entry, X + u * d, L);
                 for (int j = 0; j < qn && r < 0; ++j) {
                     const uint32_t c = s.qi[j];
                     if ((int64_t)c != u && seen[c] && (int)fin[c].size() < M) r = c;
                 }
             }
-            for (size_t j = 0; j < order.size() && r < 0; ++j)
-                if ((int)fin[order[j]].size() < M) r = order[j];
+            if (r < 0) {
+                while (first_free < order.size() && (int)fin[order[first_free]].size() >= M) ++first_free;
+                if (first_free < order.size()) r = order[first_free];
+            }
             if (r < 0) {
                 set_error("build: reachability repair found no node with a free slot");
                 return RG_EINTERNAL;
@@ -729,6 +738,9 @@ int host_construct(const float *X, int64_t n, int32_t d, const uint32_t *knn, in
             order.push_back((uint32_t)u);
             bfs();
         }
+        if (log && repairs)
+            std::fprintf(stderr, "[rg] repair: %lld edges, %lld nodes searched again (stored head full)\n",
+                         (long long)repairs, (long long)searches);
     }
 
     // --- CSR, rows sorted by id ------------------------------------------
@@ -961,16 +973,15 @@ int host_insert(StageGraphs &sg, int32_t d, int32_t M, int32_t m_pj, int32_t L, 
             }
         };
         bfs();
+        size_t first_free = 0;  // order[0 .. first_free) are full, and rows only grow
         for (int64_t u = 0; u < N; ++u) {
             if (seen[u]) continue;
-            int64_t r = -1;
-            for (size_t j = 0; j < order.size() && r < 0; ++j)
-                if ((int64_t)rows[order[j]].size() < M) r = order[j];
-            if (r < 0) {
+            while (first_free < order.size() && (int64_t)rows[order[first_free]].size() >= M) ++first_free;
+            if (first_free == order.size()) {
                 set_error("insert: no node with a free slot");
                 return RG_EINTERNAL;
             }
-            auto &rr = rows[r];
+            auto &rr = rows[order[first_free]];
             rr.insert(std::upper_bound(rr.begin(), rr.end(), (uint32_t)u), (uint32_t)u);
             seen[u] = 1;
             order.push_back((uint32_t)u);

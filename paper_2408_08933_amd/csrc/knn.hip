@@ -10,7 +10,9 @@
 // slices of the coordinate axis, row-major with a 4-float pad (16-byte
 // writes and reads, conflict free for 16 lanes).  The contraction order is
 // free, so in the slice's k-step t lane l supplies coordinate 8*(l/16) + t:
-// each lane reads its 8 coordinates of a row with two 16-byte LDS loads.
+// each lane reads its 8 coordinates of a row with two 16-byte LDS loads.  A
+// last slice shorter than 32 is stored permuted so that its data meet the
+// first k-steps, and only ceil(rem / 4) k-steps run on it.
 //
 // Top-K: every query row of the tile keeps, in global memory, a buffer of up
 // to CAP (score, id) pairs and in LDS an admission threshold (the K-th best
@@ -129,30 +131,59 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
             vb[p] = ld4(a.X, a.n, a.ldx, a.d, x0 + p * 32 + lr, k0 + lk, vx);
         }
     };
-    auto store_slice = [&](int buf) {
+    // A partial last slice is stored permuted: coordinate c at position
+    // 8 (c % 4) + c / 4, where k-step s of lane group g reads 8 g + s, so
+    // step s meets coordinates 4 s .. 4 s + 3 and the steps past the data
+    // can be skipped.
+    auto store_slice = [&](int buf, bool tail) {
 #pragma unroll
         for (int p = 0; p < 4; ++p) {
             const int r = p * 32 + lr;
-            *reinterpret_cast<float4 *>(&As[buf][r * KCP + lk]) = va[p];
-            *reinterpret_cast<float4 *>(&Bs[buf][r * KCP + lk]) = vb[p];
+            if (!tail) {
+                *reinterpret_cast<float4 *>(&As[buf][r * KCP + lk]) = va[p];
+                *reinterpret_cast<float4 *>(&Bs[buf][r * KCP + lk]) = vb[p];
+            } else {
+                float *pa = &As[buf][r * KCP + (lk >> 2)], *pb = &Bs[buf][r * KCP + (lk >> 2)];
+                pa[0] = va[p].x;
+                pa[8] = va[p].y;
+                pa[16] = va[p].z;
+                pa[24] = va[p].w;
+                pb[0] = vb[p].x;
+                pb[8] = vb[p].y;
+                pb[16] = vb[p].z;
+                pb[24] = vb[p].w;
+            }
         }
     };
+    // The slices of consecutive tiles form one pipeline: the buffer parity
+    // runs on across tiles, and the next tile's first slice is loaded while
+    // the current tile's last slice is multiplied.
+    int gsl = 0;
+    if (xt0 < xt1) {
+        load_slice(xt0, 0);
+        store_slice(0, KC > a.d);
+    }
+    __syncthreads();
     for (int64_t xt = xt0; xt < xt1; ++xt) {
         const int64_t x0 = xt * BX;
-        load_slice(xt, 0);
-        store_slice(0);
-        __syncthreads();
         fx4 acc[4][4];
 #pragma unroll
         for (int i = 0; i < 4; ++i)
 #pragma unroll
             for (int j = 0; j < 4; ++j) acc[i][j] = fx4{0.f, 0.f, 0.f, 0.f};
-        for (int sl = 0; sl < nsl; ++sl) {
-            const int buf = sl & 1;
-            const bool more = sl + 1 < nsl;
-            if (more) load_slice(xt, (sl + 1) * KC);
+        for (int sl = 0; sl < nsl; ++sl, ++gsl) {
+            const int buf = gsl & 1;
+            // the slice stored next: (xt, sl + 1), else the next tile's first
+            const bool more = sl + 1 < nsl || xt + 1 < xt1;
+            const bool more_tail = sl + 1 < nsl ? (sl + 2) * KC > a.d : KC > a.d;
+            if (sl + 1 < nsl)
+                load_slice(xt, (sl + 1) * KC);
+            else if (xt + 1 < xt1)
+                load_slice(xt + 1, 0);
+            // k-steps of this slice: 8, or ceil(rem / 4) for a partial last one
+            const int ns = (sl + 1) * KC <= a.d ? 8 : (a.d - sl * KC + 3) >> 2;
 #pragma unroll 1
-            for (int h = 0; h < 2; ++h) {
+            for (int h = 0; h < 2 && 4 * h < ns; ++h) {
                 float4 af[4], bf[4];
 #pragma unroll
                 for (int i = 0; i < 4; ++i)
@@ -163,14 +194,16 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
                     bf[j] = *reinterpret_cast<const float4 *>(
                         &Bs[buf][(wc * 64 + j * 16 + (lane & 15)) * KCP + kq + 4 * h]);
 #pragma unroll
-                for (int t = 0; t < 4; ++t)
+                for (int t = 0; t < 4; ++t) {
+                    if (4 * h + t >= ns) break;
 #pragma unroll
                     for (int i = 0; i < 4; ++i)
 #pragma unroll
                         for (int j = 0; j < 4; ++j)
                             acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(af[i][t], bf[j][t], acc[i][j], 0, 0, 0);
+                }
             }
-            if (more) store_slice(buf ^ 1);
+            if (more) store_slice(buf ^ 1, more_tail);
             __syncthreads();
         }
         // filter: accumulator element r of block (i, j) is row 4*(lane/16)+r, column lane%16

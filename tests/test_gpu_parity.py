@@ -45,8 +45,10 @@ def c1(oracle_lib):
 # ---------------------------------------------------------------------------
 # kNN
 # ---------------------------------------------------------------------------
+# d = 33 and 95 leave a last coordinate slice of 1 and 31 (slices are 32 wide)
 @pytest.mark.parametrize("nq,n,d,K", [(300, 3000, 64, 48), (257, 1999, 200, 40), (130, 700, 37, 33),
-                                      (5, 128, 16, 128), (1000, 10000, 512, 112)])
+                                      (5, 128, 16, 128), (1000, 10000, 512, 112), (64, 2000, 33, 20),
+                                      (70, 1500, 95, 30)])
 def test_knn_candidates_are_fp32_topk(dev, nq, n, d, K):
     say(f"knn_candidates nq={nq} n={n} d={d} K={K}")
     rng = np.random.default_rng(nq + n + d)
