@@ -214,13 +214,13 @@ int knn_exact(const float *Qdev, int64_t nq, const float *Xdev, int64_t n, int32
     const double u32 = std::ldexp(1.0, -24), u64 = std::ldexp(1.0, -53);
     const double g32 = (d + 1) * u32 / (1.0 - (d + 1) * u32);
     const double g64 = (d + 1) * u64 / (1.0 - (d + 1) * u64);
-    double xmax = 0.0;
-    for (int64_t i = 0; i < n; ++i) {
+    std::vector<double> norm2((size_t)n);
+    par_rows(n, threads, [&](int64_t i) {
         double s = 0.0;
         for (int j = 0; j < d; ++j) s += (double)Xhost[i * d + j] * (double)Xhost[i * d + j];
-        xmax = std::max(xmax, std::sqrt(s));
-    }
-    xmax *= 1.0 + 1e-12;
+        norm2[i] = s;
+    });
+    double xmax = std::sqrt(*std::max_element(norm2.begin(), norm2.end())) * (1.0 + 1e-12);
 
     std::vector<int64_t> rows((size_t)nq);
     for (int64_t i = 0; i < nq; ++i) rows[i] = i;
@@ -245,41 +245,28 @@ int knn_exact(const float *Qdev, int64_t nq, const float *Xdev, int64_t n, int32
         rc = launch_knn_candidates(qd, m, d, Xdev, n, d, d, K, cid.as<uint32_t>(), csc.as<float>(), st);
         if (rc) return rc;
         if (std::getenv("RG_LOG")) std::fprintf(stderr, "[rg] knn candidates: %lld rows, K=%d\n", (long long)m, K);
-        std::vector<uint32_t> hid((size_t)m * K);
-        std::vector<float> hsc((size_t)m * K);
-        RG_HIP(hipMemcpyAsync(hid.data(), cid.p, sizeof(uint32_t) * hid.size(), hipMemcpyDeviceToHost, st));
-        RG_HIP(hipMemcpyAsync(hsc.data(), csc.p, sizeof(float) * hsc.size(), hipMemcpyDeviceToHost, st));
-        RG_HIP(hipStreamSynchronize(st));
+        // canonical FP64 rescoring, ordering and certification on the device;
+        // only each row's k results and its flag come back
+        DevBuf oid, od, okb;
+        rc = oid.alloc(sizeof(uint32_t) * (size_t)m * k);
+        if (!rc && d_out) rc = od.alloc(sizeof(double) * (size_t)m * k);
+        if (!rc) rc = okb.alloc((size_t)m);
+        if (rc) return rc;
+        rc = launch_knn_certify(qd, m, d, Xdev, n, d, d, cid.as<uint32_t>(), csc.as<float>(), K, k, g32 + g64, xmax,
+                                oid.as<uint32_t>(), d_out ? od.as<double>() : nullptr, okb.as<uint8_t>(), st);
+        if (rc) return rc;
+        std::vector<uint32_t> hid((size_t)m * k);
+        std::vector<double> hd(d_out ? (size_t)m * k : 0);
         std::vector<uint8_t> ok((size_t)m, 0);
+        RG_HIP(hipMemcpyAsync(hid.data(), oid.p, sizeof(uint32_t) * hid.size(), hipMemcpyDeviceToHost, st));
+        if (d_out) RG_HIP(hipMemcpyAsync(hd.data(), od.p, sizeof(double) * hd.size(), hipMemcpyDeviceToHost, st));
+        RG_HIP(hipMemcpyAsync(ok.data(), okb.p, ok.size(), hipMemcpyDeviceToHost, st));
+        RG_HIP(hipStreamSynchronize(st));
         par_rows(m, threads, [&](int64_t i) {
+            if (!ok[i]) return;
             const int64_t q = rows[i];
-            const float *t = Qhost + q * d;
-            struct C {
-                double d;
-                uint32_t id;
-            };
-            std::vector<C> c;
-            c.reserve((size_t)K);
-            for (int j = 0; j < K; ++j) {
-                const uint32_t id = hid[i * K + j];
-                if (id != kNone) c.push_back(C{canon_dist(t, Xhost + (int64_t)id * d, d), id});
-            }
-            std::sort(c.begin(), c.end(), [](const C &a, const C &b) { return a.d < b.d || (a.d == b.d && a.id < b.id); });
-            bool certified = (int64_t)K >= n;
-            if (!certified && (int)c.size() >= k) {
-                double tn = 0.0;
-                for (int j = 0; j < d; ++j) tn += (double)t[j] * (double)t[j];
-                const double tau = (g32 + g64) * std::sqrt(tn) * (1.0 + 1e-12) * xmax;
-                const double sigma = (double)hsc[i * K + K - 1];
-                const double sk = -c[k - 1].d;
-                certified = sigma + tau < sk;
-            }
-            if (!certified) return;
-            ok[i] = 1;
-            for (int j = 0; j < k && j < (int)c.size(); ++j) {
-                (*ids_out)[q * k + j] = c[j].id;
-                if (d_out) (*d_out)[q * k + j] = c[j].d;
-            }
+            std::memcpy(&(*ids_out)[q * k], &hid[i * k], sizeof(uint32_t) * k);
+            if (d_out) std::memcpy(&(*d_out)[q * k], &hd[i * k], sizeof(double) * k);
         });
         std::vector<int64_t> fail;
         for (int64_t i = 0; i < m; ++i)

@@ -293,6 +293,90 @@ __global__ __launch_bounds__(64) void k_knn_merge(const float *sc, const uint32_
     }
 }
 
+// Certification of the exact k nearest rows from the FP32 candidates (one
+// wavefront per query row).  Each lane rescores its candidates with the
+// canonical distance delta = -sum_i q_i x_i, a chain of FP64 fused
+// multiply-adds in increasing i (the products of floats are exact in FP64,
+// so every step rounds like a plain FP64 add and the value equals the host's
+// sum bit for bit), the wave sorts (delta, id) ascending, and the row is
+// certified when the K-th candidate's FP32 score plus the error bound of
+// both sums is below the k-th canonical score: no row outside the candidate
+// list can then be among the k nearest.
+constexpr int CERT_E = 4;  // candidates per lane (K <= 256)
+
+struct CertArgs {
+    const float *Q;
+    const float *X;
+    const uint32_t *cid;  // m x K, FP32 score descending
+    const float *csc;
+    uint32_t *out_id;  // m x k
+    double *out_d;     // m x k or null
+    uint8_t *ok;       // m
+    int64_t m, n, ldq, ldx;
+    int32_t d, K, k;
+    double gsum, xmax;  // FP32 + FP64 summation bound factor, max row norm
+};
+
+__device__ __forceinline__ double canon_dot(const float *qs, const float *row, int d) {
+    double s = 0.0;
+    for (int i = 0; i < d; ++i) s = fma((double)qs[i], (double)row[i], s);
+    return s;
+}
+
+__global__ __launch_bounds__(64) void k_knn_certify(CertArgs a) {
+    extern __shared__ float qs[];
+    const int64_t r = blockIdx.x;
+    const int lane = lane_id();
+    const float *q = a.Q + r * a.ldq;
+    for (int i = lane; i < a.d; i += 64) qs[i] = q[i];
+    __syncthreads();
+    // candidate c = lane + 64 e (the sort takes any placement)
+    double key[CERT_E];
+    uint32_t id[CERT_E];
+    int valid = 0;
+#pragma unroll
+    for (int e = 0; e < CERT_E; ++e) {
+        const int c = lane + 64 * e;
+        key[e] = __builtin_inf();
+        id[e] = kNone;
+        if (c < a.K) {
+            const uint32_t u = a.cid[r * a.K + c];
+            if (u != kNone) {
+                id[e] = u;
+                key[e] = -canon_dot(qs, a.X + (int64_t)u * a.ldx, a.d);
+                ++valid;
+            }
+        }
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) valid += __shfl_xor(valid, o);
+    wave_sort<CERT_E, double>(key, id);
+    bool certified = (int64_t)a.K >= a.n;
+    if (!certified && valid >= a.k) {
+        double tn = 0.0;
+        for (int i = 0; i < a.d; ++i) tn = fma((double)qs[i], (double)qs[i], tn);
+        const double tau = a.gsum * sqrt(tn) * (1.0 + 1e-12) * a.xmax;
+        const double sigma = (double)a.csc[r * a.K + a.K - 1];
+        const int src = (a.k - 1) / CERT_E, se = (a.k - 1) % CERT_E;
+        double kth = 0.0;
+#pragma unroll
+        for (int e = 0; e < CERT_E; ++e)
+            if (e == se) kth = key[e];
+        kth = __shfl(kth, src);
+        certified = sigma + tau < -kth;
+    }
+    if (lane == 0) a.ok[r] = certified ? 1 : 0;
+    if (!certified) return;
+#pragma unroll
+    for (int e = 0; e < CERT_E; ++e) {
+        const int j = lane * CERT_E + e;
+        if (j < a.k) {
+            a.out_id[r * a.k + j] = j < valid ? id[e] : kNone;
+            if (a.out_d) a.out_d[r * a.k + j] = j < valid ? key[e] : __builtin_inf();
+        }
+    }
+}
+
 }  // namespace
 
 int launch_knn_candidates(const float *Q, int64_t nq, int32_t ldq, const float *X, int64_t n, int32_t ldx,
@@ -383,6 +467,36 @@ int launch_knn_candidates(const float *Q, int64_t nq, int32_t ldq, const float *
         return RG_EDEVICE;
     }
     cleanup();
+    return RG_OK;
+}
+
+int launch_knn_certify(const float *Q, int64_t m, int64_t ldq, const float *X, int64_t n, int64_t ldx, int32_t d,
+                       const uint32_t *cid, const float *csc, int32_t K, int32_t k, double gsum, double xmax,
+                       uint32_t *out_id, double *out_d, uint8_t *ok, hipStream_t stream) {
+    if (K < k || K > 64 * CERT_E || k < 1 || d < 1 || d > 16384) {
+        set_error("knn certify: bad candidate count or dimension");
+        return RG_EINVAL;
+    }
+    if (m == 0) return RG_OK;
+    CertArgs a{};
+    a.Q = Q;
+    a.X = X;
+    a.cid = cid;
+    a.csc = csc;
+    a.out_id = out_id;
+    a.out_d = out_d;
+    a.ok = ok;
+    a.m = m;
+    a.n = n;
+    a.ldq = ldq;
+    a.ldx = ldx;
+    a.d = d;
+    a.K = K;
+    a.k = k;
+    a.gsum = gsum;
+    a.xmax = xmax;
+    hipLaunchKernelGGL(k_knn_certify, dim3((unsigned)m), dim3(64), sizeof(float) * (size_t)d, stream, a);
+    RG_HIP(hipGetLastError());
     return RG_OK;
 }
 

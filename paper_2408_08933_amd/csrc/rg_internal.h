@@ -110,6 +110,11 @@ int launch_serve_admit(int32_t n, const int32_t *slots, const float *q, const in
 int launch_knn_candidates(const float *Q, int64_t nq, int32_t ldq, const float *X, int64_t n,
                           int32_t ldx, int32_t d, int32_t K, uint32_t *ids, float *scores,
                           hipStream_t stream);
+// Canonical FP64 rescoring, sort and certification of m rows of K FP32
+// candidates (see knn.hip); ok[i] = 1 where row i's k results are exact.
+int launch_knn_certify(const float *Q, int64_t m, int64_t ldq, const float *X, int64_t n, int64_t ldx, int32_t d,
+                       const uint32_t *cid, const float *csc, int32_t K, int32_t k, double gsum, double xmax,
+                       uint32_t *out_id, double *out_d, uint8_t *ok, hipStream_t stream);
 
 // quant.hip
 int launch_pad_rows(const float *src, int64_t n, int32_t d, float *dst, int32_t pitch,
