@@ -471,7 +471,7 @@ def main():
     ap.add_argument("--serve-requests", type=int, default=100000, help="requests per serving run (--workload)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py: this build runs on exactly one GPU; --gpus N > 1 is not supported", file=sys.stderr)
+        print("bench.py runs on exactly one GPU; --gpus N > 1 is not supported", file=sys.stderr)
         sys.exit(2)
 
     import torch

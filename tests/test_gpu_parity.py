@@ -85,6 +85,38 @@ def test_knn_exact_matches_oracle(dev, oracle_lib, c1, nq, k):
     assert np.array_equal(ds.cpu().numpy(), od.astype(np.float32))
 
 
+def test_knn_certification_retries_on_ties(dev, oracle_lib):
+    # 40 identical rows nearest to every query: the first candidate list
+    # (k + 16 = 26) ends inside the tie, so certification fails and the rows
+    # are retried with 52 candidates, which reach past it.  The exact answer
+    # is the k lowest ids of the tied rows.
+    rng = np.random.default_rng(11)
+    n, d, k = 3000, 24, 10
+    X = rng.standard_normal((n, d)).astype(np.float32) * 0.1
+    v = rng.standard_normal(d).astype(np.float32)
+    tied = np.sort(rng.choice(n, 40, replace=False))
+    X[tied] = v
+    Q = (v[None, :] + 0.01 * rng.standard_normal((50, d))).astype(np.float32)
+    say("rg_knn with a 40-row tie, k=10")
+    ids, ds = rg.rg_knn(T(Q, dev), T(X, dev), k)
+    torch.cuda.synchronize()
+    oi, od = oracle_lib.knn(X, Q, k)
+    assert np.array_equal(rg.as_u32(ids), oi)
+    assert (rg.as_u32(ids) == tied[:k]).all()
+    assert np.array_equal(ds.cpu().numpy(), od.astype(np.float32))
+
+
+def test_knn_uncertifiable_tie_is_an_error(dev):
+    # a tie of 300 rows cannot be resolved with at most 256 candidates
+    rng = np.random.default_rng(12)
+    X = rng.standard_normal((2000, 16)).astype(np.float32) * 0.1
+    X[:300] = 1.0
+    Q = np.ones((4, 16), np.float32)
+    with pytest.raises(rg.RGError):
+        rg.rg_knn(T(Q, dev), T(X, dev), 10)
+        torch.cuda.synchronize()
+
+
 def test_knn_rejects_bad_k(dev):
     X = torch.zeros((10, 4), device=dev)
     with pytest.raises(rg.RGError):
