@@ -866,22 +866,22 @@ int host_insert(StageGraphs &sg, int32_t d, int32_t M, int32_t m_pj, int32_t L, 
         }
         return -1;
     };
-    std::vector<uint32_t> qs;
-    std::vector<Cand> cand, res((size_t)std::max(M, std::max(m_pj, 1)));
-    std::vector<uint8_t> kept;
     Pool pool(hw_threads(threads));
     std::vector<std::vector<Cand>> tcand((size_t)pool.size()), tres((size_t)pool.size());
     std::vector<std::vector<uint8_t>> tkept((size_t)pool.size());
+    std::vector<std::vector<uint32_t>> tqs((size_t)pool.size());
+    for (auto &r : tres) r.resize((size_t)std::max(M, std::max(m_pj, 1)));
 
-    std::vector<uint32_t> full;
-    std::vector<uint8_t> keeps_v;
-    for (int64_t i = 0; i < nv; ++i) {
-        const int64_t v = n0 + i;
-        const float *xv = X + v * d;
+    // v's bridge query q (the training query nearest v among those joined to
+    // the first queue node that has any) and v's own list: AcquireNeighbors
+    // over N_out(q) and the rows already linked to q, else over the queue.
+    // Both read only data fixed at the call's start, except nout_add[q],
+    // which grows when an earlier row of this call had the same q.
+    auto bridge = [&](int64_t i, std::vector<uint32_t> &qs) -> int64_t {
+        const float *xv = X + (n0 + i) * d;
         const uint32_t *queue = queue_ids + i * L;
-        const int qn = queue_n[i];
         int64_t q = -1;
-        for (int j = 0; j < qn && q < 0; ++j) {
+        for (int j = 0; j < queue_n[i] && q < 0; ++j) {
             joined(queue[j], qs);
             double best = INFINITY;
             for (uint32_t t : qs) {
@@ -892,12 +892,18 @@ int host_insert(StageGraphs &sg, int32_t d, int32_t M, int32_t m_pj, int32_t L, 
                 }
             }
         }
+        return q;
+    };
+    auto own_list = [&](int64_t i, int64_t q, std::vector<Cand> &cand, std::vector<Cand> &res,
+                        std::vector<uint8_t> &kept, std::vector<uint32_t> &sel) {
+        const float *xv = X + (n0 + i) * d;
+        const uint32_t *queue = queue_ids + i * L;
         cand.clear();
         if (q >= 0) {
             for (int64_t j = 0; j < q1; ++j) cand.push_back(Cand{0.0, sg.nout[q * q1 + j]});
             for (uint32_t u : sg.nout_add[q]) cand.push_back(Cand{0.0, u});
         } else {
-            for (int j = 0; j < qn; ++j) cand.push_back(Cand{0.0, queue[j]});
+            for (int j = 0; j < queue_n[i]; ++j) cand.push_back(Cand{0.0, queue[j]});
         }
         for (Cand &c : cand) c.d = canon_dist(xv, X + (int64_t)c.id * d, d);
         std::sort(cand.begin(), cand.end(), cless);
@@ -905,8 +911,29 @@ int host_insert(StageGraphs &sg, int32_t d, int32_t M, int32_t m_pj, int32_t L, 
                    cand.end());
         const int nc = (int)std::min<int64_t>((int64_t)cand.size(), L);
         const int ns = acquire_sorted(X, d, cand.data(), nc, m_pj, true, res.data(), kept);
-        std::vector<uint32_t> sel((size_t)ns);
+        sel.resize((size_t)ns);
         for (int j = 0; j < ns; ++j) sel[j] = res[j].id;
+    };
+    // all rows' bridges and lists in parallel, as of the call's start
+    std::vector<int64_t> qv((size_t)nv);
+    std::vector<std::vector<uint32_t>> selv((size_t)nv);
+    pool.run((int)nv, [&](int i, int tid) {
+        qv[i] = bridge(i, tqs[tid]);
+        own_list(i, qv[i], tcand[tid], tres[tid], tkept[tid], selv[i]);
+    });
+    std::vector<uint8_t> q_used(sg.nout_add.size(), 0);
+
+    std::vector<uint32_t> full;
+    std::vector<uint8_t> keeps_v;
+    for (int64_t i = 0; i < nv; ++i) {
+        const int64_t v = n0 + i;
+        const float *xv = X + v * d;
+        const uint32_t *queue = queue_ids + i * L;
+        const int qn = queue_n[i];
+        const int64_t q = qv[i];
+        std::vector<uint32_t> &sel = selv[i];
+        if (q >= 0 && q_used[q]) own_list(i, q, tcand[0], tres[0], tkept[0], sel);  // q gained rows in this call
+        if (q >= 0) q_used[q] = 1;
         rows[v] = sel;
         std::sort(rows[v].begin(), rows[v].end());
         // each selected row is reconsidered on its own (rows are disjoint, so

@@ -164,6 +164,30 @@ def test_insert_bit_exact_with_oracle(oracle_lib, batches):
     assert [nout[n_off[t]:n_off[t + 1]].tolist() for t in range(len(st.nout))] == st.nout
 
 
+def test_insert_rows_sharing_a_bridge_query(oracle_lib):
+    # near-copies of a few vectors in one call share their bridge training
+    # query, so each later copy's own list must see the copies linked before
+    from oracle.updates import Updatable
+    gen = datagen.Generator(1, n=1200, n_train=1200, n_test=40)
+    X, T, Q = gen.base(), gen.train(), gen.test()
+    Nq, M, L = 16, 16, 100
+    G = oracle_lib.Graph(X, T, Nq, M, L)
+    knn, _ = oracle_lib.knn(X, T, Nq)
+    ix = rg.rg_build_from_knn(X, knn, Nq, M, L_build=L, keep_stages=True, train_host=T)
+    st = Updatable.from_graph(G, X, T)
+    rng = np.random.default_rng(5)
+    V = (np.repeat(Q[:4], 12, axis=0) + 1e-3 * rng.standard_normal((48, X.shape[1]))).astype(np.float32)
+    ix.insert(V, L=64)
+    st.insert(V, L=64)
+    off, idx, entry = ix.graph()
+    o2, i2 = st.csr()
+    assert np.array_equal(off, o2) and np.array_equal(idx, i2)
+    _, _, n_off, nout = ix.bipartite()
+    lists = [nout[n_off[t]:n_off[t + 1]].tolist() for t in range(len(st.nout))]
+    assert lists == st.nout
+    assert max(sum(1 for u in r if u >= 1200) for r in lists) >= 2   # some query gained several new rows
+
+
 def test_insert_needs_stages_and_training_queries(oracle_lib):
     gen = datagen.Generator(1, n=300, n_train=300, n_test=10)
     X, T = gen.base(), gen.train()
