@@ -243,9 +243,11 @@ int rg_index_set_storage(rg_index *idx, int32_t storage, void *stream);
  * a neighbour enters the queue if the queue is not full or it beats the last
  * entry.  With reduced-precision storage the final L_eff queue is rescored
  * against the FP32 rows and the best k are returned.  FP32 storage keeps an
- * exact visited bitmap per resident query in device memory; BF16 / FP8 keep
- * a 2^10-entry visited table in LDS that forgets and rescores (the results
- * are the same; evals counts the rescoring).  Asynchronous on stream.
+ * exact visited bitmap per resident query in device memory while n/8 bytes
+ * stay below 5% of a query's expected row bytes (40 L_eff rows of 4d
+ * bytes); otherwise, and for BF16 / FP8, a 2^10-entry visited table in LDS
+ * that forgets and rescores (the results are the same; evals counts the
+ * rescoring).  Asynchronous on stream.
  * Errors: RG_EINVAL, RG_EDEVICE.
  */
 int rg_search(const rg_index *idx, const float *queries, int64_t nq, int32_t k, int32_t L,
@@ -256,9 +258,10 @@ int rg_search(const rg_index *idx, const float *queries, int64_t nq, int32_t k, 
  * preprocessing step of construction and the ground truth of recall@k.
  *   queries device nq x d; base device n x d; ids/dists device nq x k.
  * The GPU computes FP32 scores with MFMA and keeps k + slack candidates per
- * query; the host rescores them in FP64 and certifies that no other base row
- * can be closer (the FP32 error bound is smaller than the margin); rows that
- * fail are recomputed with more candidates.  ids are in (delta, id) order and
+ * query, then rescores them in canonical FP64 and certifies that no other
+ * base row can be closer (the FP32 error bound is smaller than the margin);
+ * rows that fail are recomputed with more candidates (error RG_EINTERNAL if
+ * 256 do not suffice, e.g. more than 256 tied rows).  ids are in (delta, id) order and
  * dists hold the FP64 delta rounded to float.  Synchronous.
  * Errors: RG_EINVAL (k < 1, k > n, k > 224, n >= 2^31), RG_ENOMEM,
  * RG_EDEVICE, RG_EINTERNAL (certification failed with 256 candidates).

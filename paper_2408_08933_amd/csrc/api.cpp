@@ -807,7 +807,18 @@ int rg_search(const rg_index *ix, const float *queries, int64_t nq, int32_t k, i
         a.hash_bits = kReducedHashBits;
         return launch_search(a, st);
     }
-    // FP32 rows, bandwidth bound: persistent grid: as many resident workgroups as the chip holds, each
+    // FP32 rows, bandwidth bound.  The persistent kernel's exact visited
+    // bitmap costs about n/8 bytes per query (the clear, then the lines its
+    // atomics dirty); the LDS table costs the rows it forgets and rescores.
+    // Measured: the bitmap is faster at 1M x 200 (L = 183) and 8M x 512
+    // (L = 500), the table at 10M x 200 (L = 439, by 28%).  The bitmap is
+    // used while n/8 stays below 5% of a query's expected row bytes (about
+    // 40 L rows of 4d bytes).
+    if ((double)ix->n / 8.0 > 0.05 * 40.0 * std::max(L, k) * 4.0 * ix->d) {
+        a.hash_bits = kReducedHashBits;
+        return launch_search(a, st);
+    }
+    // persistent grid: as many resident workgroups as the chip holds, each
     // with its own visited bitmap (bounded to 8 GiB in total)
     int per_cu = 0, cus = 0;
     int rc = search_occupancy(a, &per_cu);
