@@ -245,7 +245,8 @@ int rg_index_set_storage(rg_index *idx, int32_t storage, void *stream);
  * against the FP32 rows and the best k are returned.  FP32 storage keeps an
  * exact visited bitmap per resident query in device memory while n/8 bytes
  * stay below 5% of a query's expected row bytes (40 L_eff rows of 4d
- * bytes); otherwise, and for BF16 / FP8, a 2^10-entry visited table in LDS
+ * bytes) or the graph is held as CSR (rows over 128 ids);
+ * otherwise, and for BF16 / FP8, a 2^10-entry visited table in LDS
  * that forgets and rescores (the results are the same; evals counts the
  * rescoring).  Asynchronous on stream.
  * Errors: RG_EINVAL, RG_EDEVICE.

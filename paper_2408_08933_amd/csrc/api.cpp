@@ -813,8 +813,11 @@ int rg_search(const rg_index *ix, const float *queries, int64_t nq, int32_t k, i
     // Measured: the bitmap is faster at 1M x 200 (L = 183) and 8M x 512
     // (L = 500), the table at 10M x 200 (L = 439, by 28%).  The bitmap is
     // used while n/8 stays below 5% of a query's expected row bytes (about
-    // 40 L rows of 4d bytes).
-    if ((double)ix->n / 8.0 > 0.05 * 40.0 * std::max(L, k) * 4.0 * ix->d) {
+    // 40 L_eff rows of 4d bytes, as measured on these indexes: the graph's
+    // mean degree says little, the expanded nodes being its dense part), and
+    // always for CSR graphs, whose wide rows would overflow the table at
+    // every expansion.
+    if (!ix->d_adj_off && (double)ix->n / 8.0 > 0.05 * 40.0 * std::max(L, k) * 4.0 * ix->d) {
         a.hash_bits = kReducedHashBits;
         return launch_search(a, st);
     }

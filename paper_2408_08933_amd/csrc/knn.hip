@@ -123,8 +123,20 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
     const int kq = (lane >> 4) * 8;  // this lane's coordinates within a slice
     const int nsl = (a.d + KC - 1) / KC;
     float4 va[4], vb[4];
+    // interior tiles and full slices load without bounds checks
+    const bool q_in = vq && q0 + BQ <= a.nq;
+    const float *qrow = a.Q + (q0 + lr) * (int64_t)a.ldq + lk;
     auto load_slice = [&](int64_t xt, int k0) {
         const int64_t x0 = xt * BX;
+        if (q_in && vx && x0 + BX <= a.n && k0 + KC <= a.d) {
+            const float *xrow = a.X + (x0 + lr) * (int64_t)a.ldx + lk + k0;
+#pragma unroll
+            for (int p = 0; p < 4; ++p) {
+                va[p] = *reinterpret_cast<const float4 *>(qrow + (int64_t)p * 32 * a.ldq + k0);
+                vb[p] = *reinterpret_cast<const float4 *>(xrow + (int64_t)p * 32 * a.ldx);
+            }
+            return;
+        }
 #pragma unroll
         for (int p = 0; p < 4; ++p) {
             va[p] = ld4(a.Q, a.nq, a.ldq, a.d, q0 + p * 32 + lr, k0 + lk, vq);
