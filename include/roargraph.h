@@ -330,7 +330,8 @@ const char *rg_last_error(void);
 /* depend on what else is in flight.                                       */
 /* ---------------------------------------------------------------------- */
 typedef struct {
-    int32_t max_slots;        /* concurrent requests on the device (>= 1) */
+    int32_t max_slots;        /* concurrent requests on the device; 0 => twice the
+                                 serving-step workgroups the device holds at once */
     int64_t hbm_pool_bytes;   /* bound on slot state bytes; 0 => no bound beyond max_slots */
     int32_t hops_per_step;    /* expansions per slot per step; 0 => 32 */
     int32_t max_L;            /* largest L_eff accepted (<= 512); 0 => 512 */

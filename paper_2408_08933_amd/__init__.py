@@ -337,7 +337,7 @@ def rg_load(path: str, stream=None) -> Index:
 class Server:
     """Continuous-batching search server over an Index (rg_server_*)."""
 
-    def __init__(self, index: Index, max_slots=1024, hbm_pool_bytes=0, hops_per_step=32, max_L=512, hash_bits=0):
+    def __init__(self, index: Index, max_slots=0, hbm_pool_bytes=0, hops_per_step=32, max_L=512, hash_bits=0):
         self.index = index
         lim = rg_server_limits(max_slots, hbm_pool_bytes, hops_per_step, max_L, hash_bits)
         h = ctypes.c_void_p()

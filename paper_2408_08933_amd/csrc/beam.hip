@@ -656,6 +656,14 @@ template <int ST, int CLS>
 struct StepLaunch {
     static int run(const SlotArgs &a, hipStream_t s) { return launch_step<ST, CLS>(a, s); }
 };
+template <int ST, int CLS>
+struct StepOcc {
+    static int run(const SlotArgs &a, hipStream_t) {
+        const size_t lds = search_lds_bytes(kMaxL, a.s.qpad, a.s.hash_bits, a.s.cand);
+        RG_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(a.s.occ_out, k_serve_step<ST, CLS>, 64, lds));
+        return RG_OK;
+    }
+};
 
 }  // namespace
 
@@ -719,6 +727,17 @@ int launch_serve_step(const SlotArgs &sa, hipStream_t stream) {
     case RG_STORE_FP32: return dispatch_dim<StepLaunch, RG_STORE_FP32>(sa.s.d, sa, stream);
     case RG_STORE_BF16: return dispatch_dim<StepLaunch, RG_STORE_BF16>(sa.s.d, sa, stream);
     case RG_STORE_FP8E4M3: return dispatch_dim<StepLaunch, RG_STORE_FP8E4M3>(sa.s.d, sa, stream);
+    default: set_error("serve: unknown storage"); return RG_EINVAL;
+    }
+}
+
+int serve_step_occupancy(const SlotArgs &a, int *blocks_per_cu) {
+    SlotArgs b = a;
+    b.s.occ_out = blocks_per_cu;
+    switch (a.s.storage) {
+    case RG_STORE_FP32: return dispatch_dim<StepOcc, RG_STORE_FP32>(a.s.d, b, nullptr);
+    case RG_STORE_BF16: return dispatch_dim<StepOcc, RG_STORE_BF16>(a.s.d, b, nullptr);
+    case RG_STORE_FP8E4M3: return dispatch_dim<StepOcc, RG_STORE_FP8E4M3>(a.s.d, b, nullptr);
     default: set_error("serve: unknown storage"); return RG_EINVAL;
     }
 }

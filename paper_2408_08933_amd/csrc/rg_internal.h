@@ -101,6 +101,8 @@ struct ServeRecord {
     float d[kMaxL];
 };
 int launch_serve_step(const SlotArgs &a, hipStream_t stream);
+// workgroups of the serving step kernel one CU holds at once for these arguments
+int serve_step_occupancy(const SlotArgs &a, int *blocks_per_cu);
 // Scatter n admitted requests (compact arrays) into their slots and reset their state.
 int launch_serve_admit(int32_t n, const int32_t *slots, const float *q, const int32_t *k, const int32_t *L,
                        int32_t d, float *slot_q, int32_t *slot_k, int32_t *slot_L, int32_t *slot_state,

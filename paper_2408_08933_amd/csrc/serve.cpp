@@ -218,7 +218,10 @@ int rg_server_create(const rg_index *ix, const rg_server_limits *lim, rg_server 
     *out = nullptr;
     rg_server_limits l{};
     if (lim) l = *lim;
-    if (l.max_slots < 1) l.max_slots = 1024;
+    if (l.max_slots < 0) {
+        set_error("rg_server_create: max_slots must be >= 0");
+        return RG_EINVAL;
+    }
     if (l.hops_per_step <= 0) l.hops_per_step = 32;
     if (l.max_L <= 0 || l.max_L > kMaxL) l.max_L = kMaxL;
     if (l.hash_bits == 0) l.hash_bits = serve_hash_bits(ix->storage);
@@ -226,6 +229,25 @@ int rg_server_create(const rg_index *ix, const rg_server_limits *lim, rg_server 
         (1 << l.hash_bits) < 2 * cand_capacity(ix->ell, ix->d_adj_off != nullptr) + 2) {
         set_error("rg_server_create: hash_bits out of range");
         return RG_EINVAL;
+    }
+    if (l.max_slots == 0) {
+        // twice the step workgroups the device holds at once, so each step
+        // runs whole waves of workgroups
+        SlotArgs sa{};
+        sa.s.d = ix->d;
+        sa.s.qpad = query_pad(ix->d, ix->pitch, ix->storage);
+        sa.s.cand = cand_capacity(ix->ell, ix->d_adj_off != nullptr);
+        sa.s.hash_bits = l.hash_bits;
+        sa.s.storage = ix->storage;
+        int per_cu = 0, cus = 0;
+        (void)hipSetDevice(ix->device);
+        const int rc = serve_step_occupancy(sa, &per_cu);
+        if (rc) return rc;
+        if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, ix->device) != hipSuccess) {
+            set_error("rg_server_create: device query failed");
+            return RG_EDEVICE;
+        }
+        l.max_slots = 2 * std::max(1, per_cu) * std::max(1, cus);
     }
     rg_server *s = new rg_server();
     s->ix = ix;

@@ -101,6 +101,23 @@ def test_memory_bounded_admission(setup):
         assert np.array_equal(res[i]["ids"], ai)
 
 
+def test_automatic_slot_count(setup):
+    # max_slots = 0: twice the step workgroups the device holds at once
+    dev, X, Q, ix = setup
+    cus = torch.cuda.get_device_properties(0).multi_processor_count
+    srv = rg.Server(ix, max_slots=0, hops_per_step=8)
+    slots = srv.slots()
+    assert slots >= 2 * cus and slots % (2 * cus) == 0
+    n = 30
+    res = run_mix(srv, Q, np.full(n, 10), np.full(n, 64))
+    srv.close()
+    for i in range(n):
+        ai, ad = alone(dev, ix, Q[i % len(Q)], 10, 64)
+        assert np.array_equal(res[i]["ids"], ai)
+    with pytest.raises(rg.RGError):
+        rg.Server(ix, max_slots=-1)
+
+
 def test_pool_too_small_is_rejected(setup):
     dev, X, Q, ix = setup
     with pytest.raises(rg.RGError):
