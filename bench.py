@@ -122,7 +122,9 @@ def serve_run(rg, ix, Qh, gt, n_req, rate, seed=0, timeout=120.0):
     ks = rng.choice([1, 10, 100], n_req).astype(np.int32)
     Ls = rng.choice([32, 128, 512], n_req).astype(np.int32)
     arrive = np.cumsum(rng.exponential(1.0 / rate, n_req)) if rate else np.zeros(n_req)
-    srv = rg.Server(ix, max_slots=0, hops_per_step=32)   # slots: twice the resident step workgroups
+    # 4096 slots: the automatic count (twice the resident step workgroups,
+    # up to 9,728) serves more requests closed-loop but queues at high load
+    srv = rg.Server(ix, max_slots=4096, hops_per_step=32)
     done = {}
     i = 0
     t0 = srv.now()
