@@ -154,7 +154,9 @@ def serve_run(rg, ix, Qh, gt, n_req, rate, seed=0, timeout=120.0):
 
 
 def serve_latency(rg, ix, Qh, gt, n_req=100000):
-    """Closed-loop capacity, then Poisson arrivals at 0.5, 0.8, 0.95 of it."""
+    """Closed-loop capacity, then Poisson arrivals at 0.5, 0.8, 0.95 of it
+    (after a short unmeasured run: a process's first serving run is slower)."""
+    serve_run(rg, ix, Qh, gt, 5000, None, seed=3)
     cap = serve_run(rg, ix, Qh, gt, n_req, None, seed=1)
     lam = cap["achieved_qps"]
     out = {"k_mix": [1, 10, 100], "L_mix": [32, 128, 512], "capacity_qps": lam, "capacity_recall": cap["recall"],

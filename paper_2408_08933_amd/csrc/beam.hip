@@ -15,9 +15,9 @@
 // row (ELL, one id per lane; or a CSR row of any length, 128 ids at a time),
 // filter through the visited set, gather the
 // new neighbours' rows (G lanes per row, 16-byte loads, R rows per group in
-// flight), reduce the FP32 dot products inside each G-lane group with xor
-// shuffles, sort the batch in registers, and merge the entries that beat the
-// queue's last key.  The search stops when every queue entry is expanded.
+// flight), reduce the FP32 dot products inside each G-lane group (DPP lane
+// moves), order the survivors, and merge the entries that beat the queue's
+// last key.  The search stops when every queue entry is expanded.
 //
 // Rows are read in 16-byte chunks of EPC elements (4 FP32, 8 BF16 or 16
 // E4M3 values).  Lane j of a group accumulates, with fused multiply-adds in
@@ -196,10 +196,25 @@ __device__ __forceinline__ void dot_rows(const SearchArgs &a, const uint32_t (&u
     }
 }
 
+// lane l reads lane l + n of its 16-lane row (row shift left) or lane
+// l ^ 2 / l ^ 1 (quad permutes); lanes past the row read 0
+template <int CTRL>
+__device__ __forceinline__ float dpp_read(float v) {
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, true));
+}
+
+// Sum of the G lanes of each group, valid in the group's first lane.  The
+// steps are those of an xor butterfly with the largest offset first, as
+// seen from the first lane, so the value is the butterfly's bit for bit;
+// inside a 16-lane row they use DPP (no LDS round trip), across rows
+// (G = 32) a shuffle.
 template <int G>
 __device__ __forceinline__ float group_sum(float v) {
-#pragma unroll
-    for (int o = G / 2; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    if constexpr (G >= 32) v += __shfl_down(v, 16);
+    if constexpr (G >= 16) v += dpp_read<0x108>(v);  // row_shl:8: lane + 8
+    if constexpr (G >= 8) v += dpp_read<0x104>(v);   // row_shl:4: lane + 4
+    if constexpr (G >= 4) v += dpp_read<0x4E>(v);    // quad_perm [2,3,0,1]: lane ^ 2
+    if constexpr (G >= 2) v += dpp_read<0xB1>(v);    // quad_perm [1,0,3,2]: lane ^ 1
     return v;
 }
 
