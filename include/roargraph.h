@@ -351,7 +351,9 @@ typedef struct {
 } rg_result;
 
 /* rg_server_create -- start a server (and its scheduler thread) on idx.
- * idx must outlive the server.  Errors: RG_EINVAL, RG_ENOMEM, RG_EDEVICE. */
+ * lim may be NULL (every limit at its default).  idx must outlive the
+ * server.  Errors: RG_EINVAL (e.g. max_slots < 0, hash_bits out of range, a
+ * pool smaller than one slot), RG_ENOMEM, RG_EDEVICE. */
 int rg_server_create(const rg_index *idx, const rg_server_limits *lim, rg_server **out);
 
 /* rg_server_submit -- queue one request; query_host is d floats (copied).
