@@ -410,6 +410,30 @@ def test_precision_search_parity(dev, oracle_lib, c1, storage):
         say(f"  {r}")
 
 
+def test_fp32_search_on_the_lds_table_path(dev, oracle_lib):
+    # n/8 bytes of bitmap per query (2,500) above 5% of the expected row
+    # bytes (40 L rows of 4d bytes: 1,280 at d = 16, L = 10): rg_search runs
+    # FP32 rows on the LDS-table kernel; same results as the exact 2^15
+    # table, and the oracle's within the FP32 tolerance
+    rng = np.random.default_rng(21)
+    n, d = 20000, 16
+    X = rng.standard_normal((n, d)).astype(np.float32)
+    Q = rng.standard_normal((80, d)).astype(np.float32)
+    off, idx = datagen.random_graph(n, 100, seed=21)
+    ix = rg.rg_index_from_csr(T(X, dev), off, idx, 0)
+    say("fp32 LDS-table path n=20000 d=16 degree 100 k=10 L=10")
+    a = rg.rg_search(ix, T(Q, dev), 10, 10, stats=True)
+    b = rg.rg_search(ix, T(Q, dev), 10, 10, stats=True, hash_bits=15)
+    torch.cuda.synchronize()
+    assert torch.equal(a[0], b[0]) and torch.equal(a[1], b[1]) and torch.equal(a[2], b[2])
+    # ~100 new rows per expansion overflow the 2^10 table, which forgets and
+    # rescores: only the LDS-table kernel counts more evaluations
+    assert (a[3] >= b[3]).all() and (a[3] > b[3]).any()
+    oi, od, _, _, gaps = oracle_lib.search(X, off, idx, 0, Q, 10, 10)
+    compare(rg.as_u32(a[0]), a[1].cpu().numpy(), oi, od, gaps, Q, X, min_agreement=0.97, min_near_same=0.9,
+            label="fp32 LDS-table path")
+
+
 @pytest.mark.parametrize("d", [7, 37, 129, 255, 700, 1024])
 def test_search_every_dimension_class(dev, oracle_lib, d):
     # odd d, d just past a class limit, and the largest class, for all three
