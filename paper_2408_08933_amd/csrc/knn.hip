@@ -391,12 +391,11 @@ __global__ __launch_bounds__(64) void k_knn_certify(CertArgs a) {
 
 }  // namespace
 
-int launch_knn_candidates(const float *Q, int64_t nq, int32_t ldq, const float *X, int64_t n, int32_t ldx,
-                          int32_t d, int32_t K, uint32_t *ids, float *scores, hipStream_t stream) {
-    if (K < 1 || K > CAP - BX || K > CAP / 2) {
-        set_error("knn: K must be in [1, 256]");
-        return RG_EINVAL;
-    }
+namespace {
+
+// Candidates of query rows [0, nq) of Q (one launch series, one split policy).
+int knn_range(const float *Q, int64_t nq, int32_t ldq, const float *X, int64_t n, int32_t ldx, int32_t d,
+              int32_t K, uint32_t *ids, float *scores, hipStream_t stream) {
     if (nq == 0) return RG_OK;
     const int64_t qtiles = (nq + BQ - 1) / BQ;
     const int64_t xtiles = (n + BX - 1) / BX;
@@ -480,6 +479,35 @@ int launch_knn_candidates(const float *Q, int64_t nq, int32_t ldq, const float *
     }
     cleanup();
     return RG_OK;
+}
+
+}  // namespace
+
+int launch_knn_candidates(const float *Q, int64_t nq, int32_t ldq, const float *X, int64_t n, int32_t ldx,
+                          int32_t d, int32_t K, uint32_t *ids, float *scores, hipStream_t stream) {
+    if (K < 1 || K > CAP - BX || K > CAP / 2) {
+        set_error("knn: K must be in [1, 256]");
+        return RG_EINVAL;
+    }
+    // Each workgroup sweeps the base for one 128-row query tile.  When the
+    // tiles leave a thin last wave of workgroups (under half the device), its
+    // tiles run with the base split across workgroups instead, so the chip
+    // is not mostly idle for a whole sweep (same candidates).
+    int per_cu = 0, cus = 0, dev = 0;
+    RG_HIP(hipGetDevice(&dev));
+    RG_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+    RG_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_knn, 256, 0));
+    const int64_t resident = (int64_t)std::max(1, per_cu) * std::max(1, cus);
+    const int64_t qtiles = (nq + BQ - 1) / BQ;
+    const int64_t rem = qtiles % resident;
+    if (qtiles > resident && rem != 0 && rem < resident / 2) {
+        const int64_t nq_main = (qtiles - rem) * BQ;
+        const int rc = knn_range(Q, nq_main, ldq, X, n, ldx, d, K, ids, scores, stream);
+        if (rc) return rc;
+        return knn_range(Q + nq_main * ldq, nq - nq_main, ldq, X, n, ldx, d, K, ids + nq_main * K,
+                         scores + nq_main * K, stream);
+    }
+    return knn_range(Q, nq, ldq, X, n, ldx, d, K, ids, scores, stream);
 }
 
 int launch_knn_certify(const float *Q, int64_t m, int64_t ldq, const float *X, int64_t n, int64_t ldx, int32_t d,
