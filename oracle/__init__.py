@@ -56,6 +56,7 @@ def _load():
         "or_quant_fp8": (None, [P, i64, i32, P, P, P]),
         "or_recall": (f64, [P, i32, P, i32, i64, i32]),
         "or_build": (P, [P, i64, i32, P, i64, i32, i32, i32, i32, i32]),
+        "or_repair": (i64, [i64, i32, u32, P, P, P, P, i64]),
         "or_graph_n": (i64, [P]),
         "or_graph_entry": (u32, [P]),
         "or_graph_repairs": (i64, [P]),
@@ -169,6 +170,29 @@ def search_rerank(Xq, X, offsets, indices, entry, Q, k, L):
     _load().or_search_rerank(_p(Xq), _p(X), X.shape[0], X.shape[1], _p(off), _p(idx), int(entry),
                              _p(Q), nq, int(k), int(L), _p(ids), _p(ds), _p(hops), _p(ev), _p(gaps))
     return ids, ds, hops, ev, gaps
+
+
+def repair(rows, M, entry, cand):
+    """Reachability repair of a graph given as lists of out-neighbours, with
+    each node's enhancement candidates `cand` (lists); returns the repaired
+    rows (sorted by id, repair edges appended) and the number of edges added."""
+    n = len(rows)
+    a = np.zeros((n, M), np.uint32)
+    deg = np.zeros(n, np.int32)
+    for x, r in enumerate(rows):
+        assert len(r) <= M
+        a[x, :len(r)] = r
+        deg[x] = len(r)
+    stride = max(1, max((len(c) for c in cand), default=1))
+    cx = np.zeros((n, stride), np.uint32)
+    cn = np.zeros(n, np.int32)
+    for x, c in enumerate(cand):
+        cx[x, :len(c)] = c
+        cn[x] = len(c)
+    added = _load().or_repair(n, int(M), int(entry), _p(a), _p(deg), _p(cx), _p(cn), stride)
+    if added < 0:
+        raise RuntimeError("repair: no reached node has a free slot")
+    return [a[x, :deg[x]].tolist() for x in range(n)], int(added)
 
 
 def bf16(x):

@@ -624,6 +624,70 @@ static void reverse_insert(const float *X, int32_t d, adjl *g, uint32_t p, uint3
     g->deg[p] = or_acquire(X, d, p, tmp, c, m, fill, g->a + (int64_t)p * g->cap);
 }
 
+/* ------------------------------------------------------------------------ */
+/* Reachability repair (the paper's claim that the enhancement connects the */
+/* graph, Sec. 4.2.4, is not guaranteed by Algorithm 1; this is the reading  */
+/* used for it).  rows is n x M with deg[x] entries in row x.  Each row is   */
+/* first sorted by id, so the breadth-first search from the entry visits a   */
+/* node's neighbours in ascending id.  Then every node u still unreached, in */
+/* ascending id, gets one in-edge r -> u: r is the first node of u's         */
+/* enhancement candidates cx[u] (stride cx_stride, cx_n[u] entries) that is  */
+/* reached and has a free slot (degree < M); failing that, the first reached */
+/* node in breadth-first order with a free slot.  The search then continues  */
+/* from u.  Returns the number of edges added, or -1 if no node has a free   */
+/* slot.                                                                      */
+/* ------------------------------------------------------------------------ */
+int64_t or_repair(int64_t n, int32_t M, uint32_t entry, uint32_t *rows, int32_t *deg, const uint32_t *cx,
+                  const int32_t *cx_n, int64_t cx_stride)
+{
+    for (int64_t x = 0; x < n; ++x)
+        qsort(rows + x * M, (size_t)deg[x], sizeof(uint32_t), u32_cmp);
+    uint8_t *seen = (uint8_t *)calloc((size_t)n, 1);
+    uint32_t *order = (uint32_t *)malloc(sizeof(uint32_t) * (size_t)n);
+    int64_t head = 0, tail = 0, repairs = 0;
+    seen[entry] = 1;
+    order[tail++] = entry;
+    for (int64_t u = -1; u < n; ++u) {
+        if (u >= 0) {
+            if (seen[u])
+                continue;
+            uint32_t r = OR_NONE;
+            for (int32_t j = 0; j < cx_n[u]; ++j) {
+                uint32_t c = cx[u * cx_stride + j];
+                if (seen[c] && deg[c] < M) {
+                    r = c;
+                    break;
+                }
+            }
+            for (int64_t j = 0; r == OR_NONE && j < tail; ++j)
+                if (deg[order[j]] < M)
+                    r = order[j];
+            if (r == OR_NONE) {
+                free(seen);
+                free(order);
+                return -1;
+            }
+            rows[(int64_t)r * M + deg[r]++] = (uint32_t)u;
+            ++repairs;
+            seen[u] = 1;
+            order[tail++] = (uint32_t)u;
+        }
+        while (head < tail) {
+            uint32_t v = order[head++];
+            for (int32_t j = 0; j < deg[v]; ++j) {
+                uint32_t w2 = rows[(int64_t)v * M + j];
+                if (!seen[w2]) {
+                    seen[w2] = 1;
+                    order[tail++] = w2;
+                }
+            }
+        }
+    }
+    free(seen);
+    free(order);
+    return repairs;
+}
+
 or_graph *or_build(const float *X, int64_t n, int32_t d, const float *T, int64_t nt, int32_t Nq,
                    int32_t M, int32_t L, int32_t m_pj, int32_t m_ce)
 {
@@ -800,59 +864,13 @@ or_graph *or_build(const float *X, int64_t n, int32_t d, const float *T, int64_t
     adj_free(&ce);
     free(tmp);
 
-    /* Reachability repair: BFS from the entry, visiting each node's        */
-    /* neighbours in ascending id; each node still unreached, in ascending   */
-    /* id, gets one in-edge from the first node of its enhancement list with */
-    /* a free slot (else the first reached node in BFS order with a free     */
-    /* slot), and the BFS is extended from it.                               */
-    for (int64_t x = 0; x < n; ++x)
-        qsort(fin.a + x * M, (size_t)fin.deg[x], sizeof(uint32_t), u32_cmp);
-    {
-        uint8_t *seen = (uint8_t *)calloc((size_t)n, 1);
-        uint32_t *order = (uint32_t *)malloc(sizeof(uint32_t) * (size_t)n);
-        int64_t head = 0, tail = 0;
-        seen[G->entry] = 1;
-        order[tail++] = G->entry;
+    /* Reachability repair (or_repair above, a function of its own so that  */
+    /* it can be pinned on a hand-made graph).                               */
+    G->repairs = or_repair(n, M, G->entry, fin.a, fin.deg, G->cx, G->cx_n, L);
+    if (G->repairs < 0) { /* cannot happen while the degree budget holds */
         G->repairs = 0;
-        for (int64_t u = -1; u < n; ++u) {
-            if (u >= 0) {
-                if (seen[u])
-                    continue;
-                uint32_t r = OR_NONE;
-                for (int32_t j = 0; j < G->cx_n[u]; ++j) {
-                    uint32_t c = G->cx[u * L + j];
-                    if (seen[c] && fin.deg[c] < M) {
-                        r = c;
-                        break;
-                    }
-                }
-                for (int64_t j = 0; r == OR_NONE && j < tail; ++j)
-                    if (fin.deg[order[j]] < M)
-                        r = order[j];
-                if (r == OR_NONE) { /* cannot happen while the degree budget holds */
-                    free(seen);
-                    free(order);
-                    adj_free(&fin);
-                    return G; /* off == NULL marks failure */
-                }
-                fin.a[(int64_t)r * M + fin.deg[r]++] = (uint32_t)u;
-                G->repairs++;
-                seen[u] = 1;
-                order[tail++] = (uint32_t)u;
-            }
-            while (head < tail) {
-                uint32_t v = order[head++];
-                for (int32_t j = 0; j < fin.deg[v]; ++j) {
-                    uint32_t w2 = fin.a[(int64_t)v * M + j];
-                    if (!seen[w2]) {
-                        seen[w2] = 1;
-                        order[tail++] = w2;
-                    }
-                }
-            }
-        }
-        free(seen);
-        free(order);
+        adj_free(&fin);
+        return G; /* off == NULL marks failure */
     }
     adj_to_csr(&fin, n, 1, &G->off, &G->idx);
     adj_free(&fin);

@@ -141,6 +141,45 @@ def test_build_hand_worked_five_points(oracle_lib):
     assert list(G.pivot) == [0, 3]
 
 
+def test_projection_cutoff_hand_worked(oracle_lib):
+    # overlapping bridge lists beyond L: distinct count before each list,
+    # rank by distance to the pivot, truncate to L (Algorithm 2)
+    g = json.load(open(os.path.join(GOLDEN, "projection_cutoff.json")))
+    b = g["base"]
+    X = np.array([[r * c for c in unit2(a)] for a, r in zip(b["angles_deg"], b["norms"])], np.float32)
+    T = np.array([unit2(a) for a in g["train_angles_deg"]], np.float32)
+    G = oracle_lib.Graph(X, T, g["Nq"], g["M"], g["L"])
+    assert G.pivot.tolist() == g["pivot"]
+    assert G.nout.tolist() == g["nout"]
+    assert [r.tolist() for r in G.rows("pj")] == g["pj_rows"]
+
+
+def test_repair_fallback_hand_worked(oracle_lib):
+    g = json.load(open(os.path.join(GOLDEN, "repair_fallback.json")))
+    rows, added = oracle_lib.repair(g["rows"], g["M"], g["entry"], g["candidates"])
+    assert rows == g["repaired_rows"]
+    assert added == g["repairs"]
+
+
+def test_repair_reaches_everything_on_random_graphs(oracle_lib):
+    # invariant: after the repair every node is reachable and no row exceeds M
+    rng = np.random.default_rng(11)
+    for trial in range(20):
+        n, M = 40, 4
+        rows = [sorted(set(rng.integers(0, n, size=int(rng.integers(0, 3))).tolist()) - {x}) for x in range(n)]
+        cand = [rng.permutation(n)[:5].tolist() for _ in range(n)]
+        out, _ = oracle_lib.repair(rows, M, 0, cand)
+        assert max(len(r) for r in out) <= M
+        seen, todo = {0}, [0]
+        while todo:
+            v = todo.pop()
+            for w in out[v]:
+                if w not in seen:
+                    seen.add(w)
+                    todo.append(w)
+        assert len(seen) == n
+
+
 def test_bipartite_routing_hand_worked(oracle_lib):
     # greedy routing on G_bi through query nodes (Sec. 4.2.1), by hand
     g = json.load(open(os.path.join(GOLDEN, "projection_5pt.json")))
@@ -371,6 +410,34 @@ def test_rerank_search_with_exact_storage_equals_plain(oracle_lib, small_graph):
     a = oracle_lib.search(X, G.offsets, G.indices, G.entry, Q[:40], 10, 32)
     b = oracle_lib.search_rerank(X, X, G.offsets, G.indices, G.entry, Q[:40], 10, 32)
     assert (a[0] == b[0]).all() and (a[1] == b[1]).all() and (a[2] == b[2]).all()
+
+
+def test_rerank_hand_worked(oracle_lib):
+    g = json.load(open(os.path.join(GOLDEN, "rerank_hand.json")))
+    X = np.array(g["X"], np.float32)
+    Xq = np.array(g["Xq"], np.float32)
+    off, idx = _complete(len(X))
+    q = np.array([g["query"]], np.float32)
+    for k, e in g["expect"].items():
+        ids, ds, _, _, _ = oracle_lib.search_rerank(Xq, X, off, idx, g["entry"], q, int(k), g["L"])
+        assert ids[0].tolist() == e["ids"] and ds[0].tolist() == e["dists"]
+
+
+def test_rerank_complete_graph_equals_brute_force_on_fp32_rows(oracle_lib):
+    # with L >= n on a complete graph the final queue holds every row, so the
+    # rerank must return the exact kNN on X whatever the stored rows are
+    rng = np.random.default_rng(5)
+    X = rng.standard_normal((50, 6)).astype(np.float32)
+    Xq = rng.standard_normal((50, 6)).astype(np.float32)   # unrelated stored rows
+    Q = rng.standard_normal((20, 6)).astype(np.float32)
+    off, idx = _complete(50)
+    gt, gd = oracle_lib.knn(X, Q, 7)
+    ids, ds, _, ev, _ = oracle_lib.search_rerank(Xq, X, off, idx, 3, Q, 7, 50)
+    assert (ids == gt).all() and (ds == gd).all()
+    assert (ev == 50).all()
+    # on the stored rows alone the answer differs
+    ids_q, _ = oracle_lib.knn(Xq, Q, 7)
+    assert (ids_q != gt).any()
 
 
 # --------------------------------------------------------------------------
