@@ -49,6 +49,9 @@ def _load():
         "or_acquire": (i32, [P, i32, u32, P, i32, i32, i32, P]),
         "or_search": (None, [P, i64, i32, P, P, u32, P, i64, i32, i32, P, P, P, P, P]),
         "or_search_rerank": (None, [P, P, i64, i32, P, P, u32, P, i64, i32, i32, P, P, P, P, P]),
+        "or_search_perturbed": (None, [P, i64, i32, P, P, u32, P, i64, i32, i32, f64, ctypes.c_uint64, P, P, P, P]),
+        "or_search_rerank_perturbed": (None, [P, P, i64, i32, P, P, u32, P, i64, i32, i32, f64, ctypes.c_uint64,
+                                              P, P, P, P]),
         "or_bf16": (ctypes.c_float, [ctypes.c_float]),
         "or_quant_bf16": (None, [P, i64, P]),
         "or_e4m3_value": (f64, [ctypes.c_uint8]),
@@ -139,7 +142,9 @@ def acquire(X, x, C, m, fill):
 
 
 def search(X, offsets, indices, entry, Q, k, L, with_stats=True):
-    """Beam search; returns ids, FP64 distances, hops, evals, decision gaps."""
+    """Beam search; returns ids, FP64 distances, hops, evals and each query's
+    decision margin: the smallest (delta_b - delta_a) / (S_a + S_b), with
+    S = sum_i |q_i x_i|, over the pairs whose order decides the search."""
     X, Q = _f32(X), _f32(Q)
     off = np.ascontiguousarray(offsets, dtype=np.int64)
     idx = np.ascontiguousarray(indices, dtype=np.uint32)
@@ -193,6 +198,31 @@ def repair(rows, M, entry, cand):
     if added < 0:
         raise RuntimeError("repair: no reached node has a free slot")
     return [a[x, :deg[x]].tolist() for x in range(n)], int(added)
+
+
+def search_perturbed(X, offsets, indices, entry, Q, k, L, eps, seed, Xq=None):
+    """The search (or, with Xq, the search over Xq and the rerank on X) with
+    every distance moved by eps * sign * S(q, x), sign in {-1, 0, +1} drawn
+    per node from the seed; returns ids, distances, hops, evals."""
+    X, Q = _f32(X), _f32(Q)
+    off = np.ascontiguousarray(offsets, dtype=np.int64)
+    idx = np.ascontiguousarray(indices, dtype=np.uint32)
+    if idx.size == 0:
+        idx = np.zeros(1, np.uint32)
+    nq = Q.shape[0]
+    ids = np.empty((nq, k), np.uint32)
+    ds = np.empty((nq, k), np.float64)
+    hops = np.empty(nq, np.uint32)
+    ev = np.empty(nq, np.uint32)
+    if Xq is None:
+        _load().or_search_perturbed(_p(X), X.shape[0], X.shape[1], _p(off), _p(idx), int(entry), _p(Q), nq,
+                                    int(k), int(L), float(eps), int(seed), _p(ids), _p(ds), _p(hops), _p(ev))
+    else:
+        Xq = _f32(Xq)
+        _load().or_search_rerank_perturbed(_p(Xq), _p(X), X.shape[0], X.shape[1], _p(off), _p(idx), int(entry),
+                                           _p(Q), nq, int(k), int(L), float(eps), int(seed), _p(ids), _p(ds),
+                                           _p(hops), _p(ev))
+    return ids, ds, hops, ev
 
 
 def bf16(x):

@@ -221,18 +221,31 @@ int32_t or_acquire(const float *X, int32_t d, uint32_t x, const uint32_t *C,
 /* entry v: every out-neighbour u of v not seen before gets its distance     */
 /* computed and enters Q if Q is not full or (delta,u) beats Q's last entry. */
 /* Stop when every entry of Q is expanded.  Returns Q[0..k) (padded).        */
+/* (Sec. 4.3: beam search from the medoid with queue length L.)              */
 /*                                                                            */
-/* gap (optional) receives the smallest margin of any comparison that        */
-/* decided the trajectory: next-best vs best unexpanded at each selection,   */
-/* candidate vs the last entry at each decision on a full queue, the entry   */
-/* evicted vs its successor, and entries k-1 vs k at the end.  A search      */
-/* whose distances are each perturbed by less than gap/2 makes the same      */
-/* decisions.                                                                 */
+/* gap (optional) receives the decision margin of the search, for checking   */
+/* an implementation whose distances carry rounding errors.  Each distance   */
+/* delta(q,x) comes with its scale S(q,x) = sum_i |q_i x_i|.  For two nodes  */
+/* a before b in (delta, id) order the pair's margin is                      */
+/*     (delta_b - delta_a) / (S_a + S_b)                                      */
+/* (+inf when both scales are 0, where both distances are exactly 0).  The   */
+/* search's margin is the smallest pair margin over every comparison that    */
+/* decides its course:                                                        */
+/*   - selection: the expanded entry against every other unexpanded entry;   */
+/*   - each expansion: every entry of the queue it leaves against every node  */
+/*     it dropped (candidates rejected and entries evicted), since the new   */
+/*     queue is the best L of the old queue and the new candidates;          */
+/*   - the end: each of the first k entries against each later entry.        */
+/* A search whose distances each err by at most g * S(q,x), with g below     */
+/* the margin, orders every such pair as this one does, so it expands the    */
+/* same nodes in the same order and returns the same k ids.                  */
 /* ------------------------------------------------------------------------ */
 typedef struct {
-    double *qd;
+    double *qd, *qs; /* queue: distance and its scale */
     uint32_t *qi;
     uint8_t *qx;
+    double *od, *os; /* nodes dropped during one expansion */
+    int32_t nout, capout;
     uint8_t *vis;
     uint32_t *touched;
     int64_t ntouched, captouched;
@@ -241,8 +254,13 @@ typedef struct {
 static void ws_init(search_ws *w, int64_t n, int32_t Leff)
 {
     w->qd = (double *)malloc(sizeof(double) * (size_t)(Leff + 1));
+    w->qs = (double *)malloc(sizeof(double) * (size_t)(Leff + 1));
     w->qi = (uint32_t *)malloc(sizeof(uint32_t) * (size_t)(Leff + 1));
     w->qx = (uint8_t *)malloc((size_t)(Leff + 1));
+    w->capout = 64;
+    w->od = (double *)malloc(sizeof(double) * (size_t)w->capout);
+    w->os = (double *)malloc(sizeof(double) * (size_t)w->capout);
+    w->nout = 0;
     w->vis = (uint8_t *)calloc((size_t)n, 1);
     w->captouched = 1024;
     w->touched = (uint32_t *)malloc(sizeof(uint32_t) * (size_t)w->captouched);
@@ -252,8 +270,11 @@ static void ws_init(search_ws *w, int64_t n, int32_t Leff)
 static void ws_free(search_ws *w)
 {
     free(w->qd);
+    free(w->qs);
     free(w->qi);
     free(w->qx);
+    free(w->od);
+    free(w->os);
     free(w->vis);
     free(w->touched);
 }
@@ -268,6 +289,18 @@ static void ws_mark(search_ws *w, uint32_t u)
     w->touched[w->ntouched++] = u;
 }
 
+static void ws_drop(search_ws *w, double d, double sc)
+{
+    if (w->nout == w->capout) {
+        w->capout *= 2;
+        w->od = (double *)realloc(w->od, sizeof(double) * (size_t)w->capout);
+        w->os = (double *)realloc(w->os, sizeof(double) * (size_t)w->capout);
+    }
+    w->od[w->nout] = d;
+    w->os[w->nout] = sc;
+    w->nout++;
+}
+
 static void ws_reset(search_ws *w)
 {
     for (int64_t i = 0; i < w->ntouched; ++i)
@@ -275,16 +308,84 @@ static void ws_reset(search_ws *w)
     w->ntouched = 0;
 }
 
+/* delta(q,x) and its scale sum_i |q_i x_i|, both summed in increasing i */
+static double dist_scale(const float *q, const float *x, int32_t d, double *scale)
+{
+    double s = 0.0, a = 0.0;
+    for (int32_t i = 0; i < d; ++i) {
+        double p = (double)q[i] * (double)x[i];
+        s += p;
+        a += fabs(p);
+    }
+    *scale = a;
+    return -s;
+}
+
+/* margin of the pair (a before b) */
+static double pair_margin(double da, double sa, double db, double sb)
+{
+    double den = sa + sb;
+    if (den == 0.0)
+        return INFINITY;
+    return (db - da) / den;
+}
+
+/* smallest margin between every node of the sorted list (d, s)[0..na) and
+ * every node of (d2, s2)[0..nb), all of which come after it; g is the
+ * current minimum, returned lowered.  smax bounds the first list's scales:
+ * walking it from its end, the distances fall, so once even the largest
+ * scale cannot bring a pair under g the rest cannot either. */
+static double cross_margin(const double *d, const double *sc, int32_t na, const double *d2,
+                           const double *s2, int32_t nb, double g)
+{
+    double smax = 0.0;
+    for (int32_t i = 0; i < na; ++i)
+        if (sc[i] > smax)
+            smax = sc[i];
+    for (int32_t j = 0; j < nb; ++j) {
+        for (int32_t i = na - 1; i >= 0; --i) {
+            double t = pair_margin(d[i], sc[i], d2[j], s2[j]);
+            if (t < g)
+                g = t;
+            double bound = smax + s2[j] > 0.0 ? (d2[j] - d[i]) / (smax + s2[j]) : INFINITY;
+            if (bound >= g)
+                break;
+        }
+    }
+    return g;
+}
+
+/* Perturbation used to explain a search run with rounding errors: node x's */
+/* distance is moved by eps * sign(x) * S(q,x), sign in {-1, 0, +1} drawn   */
+/* from the splitmix64 mix of (seed, x).  eps = 0 leaves it unchanged.      */
+static double perturb_sign(uint64_t seed, uint32_t x)
+{
+    uint64_t z = seed * 0x9E3779B97F4A7C15ull + (uint64_t)x + 1;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    z ^= z >> 31;
+    return (double)(int)(z % 3) - 1.0;
+}
+
+static double node_dist(const float *q, const float *X, int32_t d, uint32_t x, double eps, uint64_t seed,
+                        double *scale)
+{
+    double dd = dist_scale(q, X + (int64_t)x * d, d, scale);
+    if (eps != 0.0)
+        dd += eps * perturb_sign(seed, x) * *scale;
+    return dd;
+}
+
 /* returns the number of queue entries (<= Leff); qd/qi hold the queue */
 static int32_t search_core(search_ws *w, const float *X, int32_t d, const int64_t *off,
                            const uint32_t *idx, uint32_t entry, const float *q, int32_t Leff,
-                           uint32_t *hops, uint32_t *evals, double *gap)
+                           uint32_t *hops, uint32_t *evals, double *gap, double eps, uint64_t seed)
 {
     double g = INFINITY;
     int32_t qn = 0;
     uint32_t h = 0, ev = 0;
     ws_mark(w, entry);
-    w->qd[0] = or_dist(q, X + (int64_t)entry * d, d);
+    w->qd[0] = node_dist(q, X, d, entry, eps, seed, &w->qs[0]);
     w->qi[0] = entry;
     w->qx[0] = 0;
     qn = 1;
@@ -295,51 +396,55 @@ static int32_t search_core(search_ws *w, const float *X, int32_t d, const int64_
             ++i;
         if (i == qn)
             break;
-        /* margin of this selection against the next unexpanded entry */
-        for (int32_t j = i + 1; j < qn; ++j)
-            if (!w->qx[j]) {
-                double t = w->qd[j] - w->qd[i];
+        if (gap) { /* the selection against every other unexpanded entry */
+            double smax = 0.0;
+            for (int32_t j = i + 1; j < qn; ++j)
+                if (w->qs[j] > smax)
+                    smax = w->qs[j];
+            for (int32_t j = i + 1; j < qn; ++j) {
+                if (w->qx[j])
+                    continue;
+                double t = pair_margin(w->qd[i], w->qs[i], w->qd[j], w->qs[j]);
                 if (t < g)
                     g = t;
-                break;
+                if (w->qs[i] + smax > 0.0 && (w->qd[j] - w->qd[i]) / (w->qs[i] + smax) >= g)
+                    break;
             }
+        }
         w->qx[i] = 1;
         uint32_t v = w->qi[i];
         ++h;
+        w->nout = 0;
         for (int64_t e = off[v]; e < off[v + 1]; ++e) {
             uint32_t u = idx[e];
             if (w->vis[u])
                 continue;
             ws_mark(w, u);
-            double du = or_dist(q, X + (int64_t)u * d, d);
+            double su;
+            double du = node_dist(q, X, d, u, eps, seed, &su);
             ++ev;
             if (qn == Leff) {
-                double last = w->qd[Leff - 1];
-                if (!before(du, u, last, w->qi[Leff - 1])) {
-                    double t = du - last;
-                    if (t < g)
-                        g = t;
+                if (!before(du, u, w->qd[Leff - 1], w->qi[Leff - 1])) {
+                    ws_drop(w, du, su); /* rejected */
                     continue;
                 }
-                /* admitted: the old last entry is evicted */
-                double nxt = du;
-                if (Leff >= 2 && w->qd[Leff - 2] > nxt)
-                    nxt = w->qd[Leff - 2];
-                double t = last - nxt;
-                if (t < g)
-                    g = t;
+                ws_drop(w, w->qd[Leff - 1], w->qs[Leff - 1]); /* evicted */
             }
             int32_t pos = qn < Leff ? qn++ : Leff - 1;
             while (pos > 0 && before(du, u, w->qd[pos - 1], w->qi[pos - 1])) {
                 w->qd[pos] = w->qd[pos - 1];
+                w->qs[pos] = w->qs[pos - 1];
                 w->qi[pos] = w->qi[pos - 1];
                 w->qx[pos] = w->qx[pos - 1];
                 --pos;
             }
             w->qd[pos] = du;
+            w->qs[pos] = su;
             w->qi[pos] = u;
             w->qx[pos] = 0;
         }
+        if (gap && w->nout) /* the queue kept against everything dropped */
+            g = cross_margin(w->qd, w->qs, qn, w->od, w->os, w->nout, g);
     }
     if (hops)
         *hops = h;
@@ -350,9 +455,10 @@ static int32_t search_core(search_ws *w, const float *X, int32_t d, const int64_
     return qn;
 }
 
-void or_search(const float *X, int64_t n, int32_t d, const int64_t *off, const uint32_t *idx,
-               uint32_t entry, const float *Q, int64_t nq, int32_t k, int32_t L, uint32_t *ids,
-               double *dists, uint32_t *hops, uint32_t *evals, double *gaps)
+static void search_batch(const float *X, int64_t n, int32_t d, const int64_t *off, const uint32_t *idx,
+                         uint32_t entry, const float *Q, int64_t nq, int32_t k, int32_t L, uint32_t *ids,
+                         double *dists, uint32_t *hops, uint32_t *evals, double *gaps, double eps,
+                         uint64_t seed)
 {
     int32_t Leff = L > k ? L : k;
 #pragma omp parallel
@@ -361,14 +467,12 @@ void or_search(const float *X, int64_t n, int32_t d, const int64_t *off, const u
         ws_init(&w, n, Leff);
 #pragma omp for schedule(dynamic, 4)
         for (int64_t qq = 0; qq < nq; ++qq) {
-            double g;
+            double g = INFINITY;
             int32_t qn = search_core(&w, X, d, off, idx, entry, Q + qq * d, Leff,
-                                     hops ? hops + qq : NULL, evals ? evals + qq : NULL, &g);
-            if (qn > k) {
-                double t = w.qd[k] - w.qd[k - 1];
-                if (t < g)
-                    g = t;
-            }
+                                     hops ? hops + qq : NULL, evals ? evals + qq : NULL,
+                                     gaps ? &g : NULL, eps, seed);
+            if (gaps && qn > k) /* the first k against the rest */
+                g = cross_margin(w.qd, w.qs, k, w.qd + k, w.qs + k, qn - k, g);
             if (gaps)
                 gaps[qq] = g;
             for (int32_t j = 0; j < k; ++j) {
@@ -379,6 +483,23 @@ void or_search(const float *X, int64_t n, int32_t d, const int64_t *off, const u
         }
         ws_free(&w);
     }
+}
+
+void or_search(const float *X, int64_t n, int32_t d, const int64_t *off, const uint32_t *idx,
+               uint32_t entry, const float *Q, int64_t nq, int32_t k, int32_t L, uint32_t *ids,
+               double *dists, uint32_t *hops, uint32_t *evals, double *gaps)
+{
+    search_batch(X, n, d, off, idx, entry, Q, nq, k, L, ids, dists, hops, evals, gaps, 0.0, 0);
+}
+
+/* The same search with every distance moved by eps * sign * S (see        */
+/* perturb_sign): used to show that a result differing from the plain one   */
+/* is what some distance errors within eps * S produce.                      */
+void or_search_perturbed(const float *X, int64_t n, int32_t d, const int64_t *off, const uint32_t *idx,
+                         uint32_t entry, const float *Q, int64_t nq, int32_t k, int32_t L, double eps,
+                         uint64_t seed, uint32_t *ids, double *dists, uint32_t *hops, uint32_t *evals)
+{
+    search_batch(X, n, d, off, idx, entry, Q, nq, k, L, ids, dists, hops, evals, NULL, eps, seed);
 }
 
 /* ------------------------------------------------------------------------ */
@@ -493,33 +614,55 @@ void or_quant_fp8(const float *X, int64_t n, int32_t d, uint8_t *codes, float *s
 
 /* Search over the reduced-precision rows Xq (given dequantised, exact as    */
 /* float), then rescore every entry of the final queue against the FP32 rows */
-/* X with the canonical distance, order by (delta, id) and keep k.           */
-void or_search_rerank(const float *Xq, const float *X, int64_t n, int32_t d, const int64_t *off,
-                      const uint32_t *idx, uint32_t entry, const float *Q, int64_t nq, int32_t k,
-                      int32_t L, uint32_t *ids, double *dists, uint32_t *hops, uint32_t *evals,
-                      double *gaps)
+/* X with the canonical distance, order by (delta, id) and keep k.  The      */
+/* margin covers the search on Xq and, with scales taken on X, the first k   */
+/* of the rescored queue against the rest.                                   */
+typedef struct {
+    double d, s;
+    uint32_t id;
+} rr_t;
+
+static int rr_cmp(const void *pa, const void *pb)
+{
+    const rr_t *a = (const rr_t *)pa, *b = (const rr_t *)pb;
+    if (a->d < b->d)
+        return -1;
+    if (a->d > b->d)
+        return 1;
+    return a->id < b->id ? -1 : (a->id > b->id ? 1 : 0);
+}
+
+static void rerank_batch(const float *Xq, const float *X, int64_t n, int32_t d, const int64_t *off,
+                         const uint32_t *idx, uint32_t entry, const float *Q, int64_t nq, int32_t k,
+                         int32_t L, uint32_t *ids, double *dists, uint32_t *hops, uint32_t *evals,
+                         double *gaps, double eps, uint64_t seed)
 {
     int32_t Leff = L > k ? L : k;
 #pragma omp parallel
     {
         search_ws w;
         ws_init(&w, n, Leff);
-        pair_t *pr = (pair_t *)malloc(sizeof(pair_t) * (size_t)Leff);
+        rr_t *pr = (rr_t *)malloc(sizeof(rr_t) * (size_t)Leff);
+        double *rd = (double *)malloc(sizeof(double) * (size_t)Leff);
+        double *rs = (double *)malloc(sizeof(double) * (size_t)Leff);
 #pragma omp for schedule(dynamic, 4)
         for (int64_t qq = 0; qq < nq; ++qq) {
-            double g;
+            double g = INFINITY;
             const float *q = Q + qq * d;
             int32_t qn = search_core(&w, Xq, d, off, idx, entry, q, Leff,
-                                     hops ? hops + qq : NULL, evals ? evals + qq : NULL, &g);
+                                     hops ? hops + qq : NULL, evals ? evals + qq : NULL,
+                                     gaps ? &g : NULL, eps, seed);
             for (int32_t j = 0; j < qn; ++j) {
                 pr[j].id = w.qi[j];
-                pr[j].d = or_dist(q, X + (int64_t)w.qi[j] * d, d);
+                pr[j].d = node_dist(q, X, d, w.qi[j], eps, seed ^ 0x5DEECE66Dull, &pr[j].s);
             }
-            qsort(pr, (size_t)qn, sizeof(pair_t), pair_cmp);
-            if (qn > k) {
-                double t = pr[k].d - pr[k - 1].d;
-                if (t < g)
-                    g = t;
+            qsort(pr, (size_t)qn, sizeof(rr_t), rr_cmp);
+            if (gaps && qn > k) {
+                for (int32_t j = 0; j < qn; ++j) {
+                    rd[j] = pr[j].d;
+                    rs[j] = pr[j].s;
+                }
+                g = cross_margin(rd, rs, k, rd + k, rs + k, qn - k, g);
             }
             if (gaps)
                 gaps[qq] = g;
@@ -530,8 +673,26 @@ void or_search_rerank(const float *Xq, const float *X, int64_t n, int32_t d, con
             ws_reset(&w);
         }
         free(pr);
+        free(rd);
+        free(rs);
         ws_free(&w);
     }
+}
+
+void or_search_rerank(const float *Xq, const float *X, int64_t n, int32_t d, const int64_t *off,
+                      const uint32_t *idx, uint32_t entry, const float *Q, int64_t nq, int32_t k,
+                      int32_t L, uint32_t *ids, double *dists, uint32_t *hops, uint32_t *evals,
+                      double *gaps)
+{
+    rerank_batch(Xq, X, n, d, off, idx, entry, Q, nq, k, L, ids, dists, hops, evals, gaps, 0.0, 0);
+}
+
+void or_search_rerank_perturbed(const float *Xq, const float *X, int64_t n, int32_t d, const int64_t *off,
+                                const uint32_t *idx, uint32_t entry, const float *Q, int64_t nq, int32_t k,
+                                int32_t L, double eps, uint64_t seed, uint32_t *ids, double *dists,
+                                uint32_t *hops, uint32_t *evals)
+{
+    rerank_batch(Xq, X, n, d, off, idx, entry, Q, nq, k, L, ids, dists, hops, evals, NULL, eps, seed);
 }
 
 /* ------------------------------------------------------------------------ */
@@ -813,7 +974,7 @@ or_graph *or_build(const float *X, int64_t n, int32_t d, const float *T, int64_t
 #pragma omp for schedule(dynamic, 8)
         for (int64_t x = 0; x < n; ++x) {
             int32_t qn = search_core(&w, X, d, G->pj_off, G->pj_idx, G->entry, X + x * d, L,
-                                     NULL, NULL, NULL);
+                                     NULL, NULL, NULL, 0.0, 0);
             int32_t c = 0;
             for (int32_t j = 0; j < qn; ++j)
                 if (w.qi[j] != (uint32_t)x)

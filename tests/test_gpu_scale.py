@@ -10,7 +10,7 @@ import numpy as np
 import pytest
 
 import datagen
-from parity import NONE, compare
+from parity import NONE, compare, oracle_explainer
 
 pytestmark = pytest.mark.gpu
 
@@ -44,8 +44,8 @@ def test_clip_like_2m_d512_bf16(dev, oracle_lib):
         ids, ds = rg.rg_search(ix, torch.from_numpy(Q).to(dev), k, L)
         torch.cuda.synchronize()
         oi, od, _, _, gaps = oracle_lib.search_rerank(Xq, X, off, idx, 0, Q, k, L)
-        compare(rg.as_u32(ids), ds.cpu().numpy(), oi, od, gaps, Q, X, min_agreement=0.97, min_near_same=0.9,
-                label=f"2M d512 bf16 k={k} L={L}", storage="bf16")
+        compare(rg.as_u32(ids), ds.cpu().numpy(), oi, od, gaps, Q, X, label=f"2M d512 bf16 k={k} L={L}",
+                storage="bf16", explain=oracle_explainer(oracle_lib, X, off, idx, 0, Q, k, L, Xq=Xq))
 
 
 def test_t2i_like_10m_d200_fp32(dev, oracle_lib):
@@ -59,8 +59,8 @@ def test_t2i_like_10m_d200_fp32(dev, oracle_lib):
         ids, ds = rg.rg_search(ix, torch.from_numpy(Q).to(dev), k, L)
         torch.cuda.synchronize()
         oi, od, _, _, gaps = oracle_lib.search(X, off, idx, 0, Q, k, L)
-        compare(rg.as_u32(ids), ds.cpu().numpy(), oi, od, gaps, Q, X, min_agreement=0.97, min_near_same=0.9,
-                label=f"10M d200 k={k} L={L}")
+        compare(rg.as_u32(ids), ds.cpu().numpy(), oi, od, gaps, Q, X, label=f"10M d200 k={k} L={L}",
+                explain=oracle_explainer(oracle_lib, X, off, idx, 0, Q, k, L))
 
 
 def test_fp8_8m_d512_properties(dev, oracle_lib):
@@ -71,7 +71,6 @@ def test_fp8_8m_d512_properties(dev, oracle_lib):
     Xt = torch.from_numpy(X).to(dev)
     ix = rg.rg_index_from_csr(Xt, off, idx, 0)
     Qt = torch.from_numpy(Q).to(dev)
-    ref_ids = None
     rg.rg_index_set_storage(ix, rg.RG_STORE_FP8E4M3)
     # codes and scales of sampled rows equal the oracle's quantiser
     _, pf, ps, p8 = ix.storage_ptrs()
@@ -97,7 +96,6 @@ def test_fp8_8m_d512_properties(dev, oracle_lib):
     exact = -np.einsum("qkd,qd->qk", X[a.astype(np.int64)].astype(np.float64), Q.astype(np.float64))
     tol = 1e-5 * np.linalg.norm(Q, axis=1)[:, None] * np.linalg.norm(X[rows], axis=1).max() * 1.5
     assert (np.abs(dd - exact) <= tol).all()
-    del ref_ids
 
 
 def test_fp8_500k_d512_oracle_parity(dev, oracle_lib):
@@ -115,5 +113,5 @@ def test_fp8_500k_d512_oracle_parity(dev, oracle_lib):
         ids, ds = rg.rg_search(ix, torch.from_numpy(Q).to(dev), k, L)
         torch.cuda.synchronize()
         oi, od, _, _, gaps = oracle_lib.search_rerank(Xq, X, off, idx, 0, Q, k, L)
-        compare(rg.as_u32(ids), ds.cpu().numpy(), oi, od, gaps, Q, X, min_agreement=0.97, min_near_same=0.9,
-                label=f"500k d512 fp8 k={k} L={L}", storage="fp8")
+        compare(rg.as_u32(ids), ds.cpu().numpy(), oi, od, gaps, Q, X, label=f"500k d512 fp8 k={k} L={L}",
+                storage="fp8", explain=oracle_explainer(oracle_lib, X, off, idx, 0, Q, k, L, Xq=Xq))

@@ -8,7 +8,7 @@ import numpy as np
 import pytest
 
 import datagen
-from parity import NONE, compare
+from parity import NONE, compare, oracle_explainer
 
 pytestmark = pytest.mark.gpu
 
@@ -64,8 +64,8 @@ def test_search_after_insert(setup, oracle_lib):
         ids, ds = rg.rg_search(ix, T(Q, dev), k, L)
         torch.cuda.synchronize()
         oi, od, _, _, gaps = oracle_lib.search(st.X, off, idx, st.entry, Q, k, L)
-        compare(rg.as_u32(ids), ds.cpu().numpy(), oi, od, gaps, Q, st.X, min_agreement=0.97, min_near_same=0.9,
-                label=f"after insert k={k} L={L}")
+        compare(rg.as_u32(ids), ds.cpu().numpy(), oi, od, gaps, Q, st.X, label=f"after insert k={k} L={L}",
+                explain=oracle_explainer(oracle_lib, st.X, off, idx, st.entry, Q, k, L))
     # new rows are found: each inserted row searched for itself comes back first
     V = st.X[4000:]
     ids, _ = rg.rg_search(ix, T(V, dev), 1, 64)
@@ -88,9 +88,10 @@ def test_insert_with_bf16_storage(setup, oracle_lib):
         say("bf16 search after insert k=10 L=64")
         ids, ds = rg.rg_search(ix, T(Q, dev), 10, 64)
         torch.cuda.synchronize()
-        oi, od, _, _, gaps = oracle_lib.search_rerank(oracle_lib.bf16(st.X), st.X, off, idx, st.entry, Q, 10, 64)
-        compare(rg.as_u32(ids), ds.cpu().numpy(), oi, od, gaps, Q, st.X, min_agreement=0.97, min_near_same=0.9,
-                label="bf16 after insert", storage="bf16")
+        Xq = oracle_lib.bf16(st.X)
+        oi, od, _, _, gaps = oracle_lib.search_rerank(Xq, st.X, off, idx, st.entry, Q, 10, 64)
+        compare(rg.as_u32(ids), ds.cpu().numpy(), oi, od, gaps, Q, st.X, label="bf16 after insert", storage="bf16",
+                explain=oracle_explainer(oracle_lib, st.X, off, idx, st.entry, Q, 10, 64, Xq=Xq))
     finally:
         rg.rg_index_set_storage(ix, rg.RG_STORE_FP32)
 

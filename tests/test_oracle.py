@@ -306,14 +306,20 @@ def test_search_path_graph_by_hand(oracle_lib):
     off = np.array([0, 1, 3, 5, 7, 8], np.int64)
     idx = np.array(sum(rows, []), np.uint32)
     # q = +1 prefers larger x.  L=1 from entry 0: 0 -> 1 -> 2 -> 3 -> 4.
+    # Node i holds x = i + 1; the scale of a pair is |q x| = x.
+    # Each expansion evicts the old entry: margins (delta_old - delta_new) /
+    # (S_new + S_old) = 1/3, 1/5, 1/7, 1/9; the smallest is 1/9.
     ids, ds, hops, ev, gaps = oracle_lib.search(X, off, idx, 0, np.array([[1]], np.float32), 1, 1)
     assert ids[0, 0] == 4 and ds[0, 0] == -5.0 and hops[0] == 5 and ev[0] == 5
+    assert gaps[0] == pytest.approx(1 / 9, rel=1e-15)
     # q = -1 prefers smaller x: from entry 2 with L=2: expand 2 (sees 1, 3),
-    # queue [1, 2]; expand 1 (sees 0), queue [0, 1]; expand 0; done.
+    # queue [1, 2] and 3 rejected: margins (4-2)/(2+4), (4-3)/(3+4) = 1/7;
+    # expand 1 (sees 0), queue [0, 1] and 2 evicted: (3-1)/4, (3-2)/5;
+    # expand 0; done.  Smallest: 1/7.
     ids, ds, hops, ev, gaps = oracle_lib.search(X, off, idx, 2, np.array([[-1]], np.float32), 2, 2)
     assert list(ids[0]) == [0, 1] and list(ds[0]) == [1.0, 2.0]
     assert hops[0] == 3 and ev[0] == 4
-    assert gaps[0] == 1.0
+    assert gaps[0] == pytest.approx(1 / 7, rel=1e-15)
 
 
 def test_search_single_node_and_padding(oracle_lib):
@@ -323,6 +329,56 @@ def test_search_single_node_and_padding(oracle_lib):
     assert ids[0, 0] == 0 and ds[0, 0] == -2.0
     assert ids[0, 1] == oracle_lib.NONE and math.isinf(ds[0, 2])
     assert hops[0] == 1 and ev[0] == 1
+
+
+def test_search_margin_is_sound_under_perturbation(oracle_lib, small_graph):
+    # The margin promises that distances perturbed by less than margin * S
+    # (S = sum |q_i x_i|) leave every decision unchanged.  Perturb each
+    # coordinate of X by a relative 0.4 * margin with random sign, which
+    # moves every distance by at most 0.4 * margin * S (plus float rounding,
+    # 2^-24 relative, kept far below by skipping tiny margins): the search
+    # must expand the same nodes and return the same ids.
+    X, T, Q, G = small_graph
+    rng = np.random.default_rng(17)
+    checked = 0
+    for L, k in ((16, 10), (48, 10), (32, 32)):
+        ids, ds, hops, ev, gaps = oracle_lib.search(X, G.offsets, G.indices, G.entry, Q[:24], k, L)
+        for q in range(24):
+            g = float(gaps[q])
+            if not (1e-5 < g < np.inf):
+                continue
+            eps = 0.4 * g
+            Xp = (X.astype(np.float64) * (1.0 + eps * rng.choice([-1.0, 1.0], size=X.shape))).astype(np.float32)
+            i2, _, h2, e2, _ = oracle_lib.search(Xp, G.offsets, G.indices, G.entry, Q[q:q + 1], k, L)
+            assert set(i2[0].tolist()) == set(ids[q].tolist()) and h2[0] == hops[q] and e2[0] == ev[q]
+            checked += 1
+    assert checked >= 20
+
+
+def test_perturbed_search(oracle_lib, small_graph):
+    # eps = 0 is the plain search; eps below a query's margin changes
+    # nothing; on an exact tie a perturbation can pick either node, and only
+    # those two (every other distance is far away)
+    X, T, Q, G = small_graph
+    a = oracle_lib.search(X, G.offsets, G.indices, G.entry, Q[:30], 10, 32)
+    b = oracle_lib.search_perturbed(X, G.offsets, G.indices, G.entry, Q[:30], 10, 32, 0.0, 5)
+    assert (a[0] == b[0]).all() and (a[1] == b[1]).all() and (a[2] == b[2]).all() and (a[3] == b[3]).all()
+    gaps = a[4]
+    for q in np.nonzero(gaps > 1e-6)[0][:10]:
+        for seed in range(3):
+            c = oracle_lib.search_perturbed(X, G.offsets, G.indices, G.entry, Q[q:q + 1], 10, 32,
+                                            0.9 * gaps[q], seed)
+            # the margin covers the first k against the rest, not the order
+            # among the first k (swaps there are judged by distance)
+            assert set(c[0][0].tolist()) == set(a[0][q].tolist()) and c[2][0] == a[2][q] and c[3][0] == a[3][q]
+    Xt = np.array([[1, 0], [0, 1], [0, 1], [-1, 0]], np.float32)
+    off, idx = _complete(4)
+    got = set()
+    for seed in range(24):
+        ids, _, _, _ = oracle_lib.search_perturbed(Xt, off, idx, 0, np.array([[0, 1]], np.float32), 1, 1,
+                                                   1e-3, seed)
+        got.add(int(ids[0, 0]))
+    assert got == {1, 2}
 
 
 def test_search_exact_tie_has_zero_gap(oracle_lib):
