@@ -258,14 +258,19 @@ int rg_search(const rg_index *idx, const float *queries, int64_t nq, int32_t k, 
  * rg_knn -- exact k nearest base rows of each query (Def. 1): the
  * preprocessing step of construction and the ground truth of recall@k.
  *   queries device nq x d; base device n x d; ids/dists device nq x k.
- * The GPU computes FP32 scores with MFMA and keeps k + slack candidates per
- * query, then rescores them in canonical FP64 and certifies that no other
- * base row can be closer (the FP32 error bound is smaller than the margin);
- * rows that fail are recomputed with more candidates (error RG_EINTERNAL if
- * 256 do not suffice, e.g. more than 256 tied rows).  ids are in (delta, id) order and
- * dists hold the FP64 delta rounded to float.  Synchronous.
+ * Candidates: when every value of both matrices is below 2^15 in magnitude,
+ * the GPU first scores FP16-rounded rows with FP16 MFMA (FP32 accumulation)
+ * and keeps K = min(256, n, max(2k, k + 48)) per query; every candidate is
+ * rescored with the canonical FP64 distance and the row is certified when
+ * the K-th candidate's score plus the score error bound (FP16 rounding of
+ * both inputs and FP32 accumulation, see knn_exact) lies below the k-th
+ * canonical score, so no other base row can be among the k nearest.  Rows
+ * not certified are redone from FP32 MFMA scores (k + slack candidates,
+ * doubling to 256) and, failing that (more than 256 rows tied), by a full
+ * canonical scan on the host.  ids are in (delta, id) order and dists hold
+ * the FP64 delta rounded to float.  Synchronous.
  * Errors: RG_EINVAL (k < 1, k > n, k > 224, n >= 2^31), RG_ENOMEM,
- * RG_EDEVICE, RG_EINTERNAL (certification failed with 256 candidates).
+ * RG_EDEVICE.
  */
 int rg_knn(const float *queries, int64_t nq, const float *base, int64_t n, int32_t d,
            int32_t k, uint32_t *ids, float *dists, void *stream);
@@ -277,6 +282,25 @@ int rg_knn(const float *queries, int64_t nq, const float *base, int64_t n, int32
  */
 int rg_knn_candidates(const float *queries, int64_t nq, const float *base, int64_t n, int32_t d,
                       int32_t K, uint32_t *ids, float *scores, void *stream);
+
+/*
+ * rg_knn_candidates_f16 -- the FP16 candidate pass of rg_knn alone: the
+ * rows are rounded to FP16 (nearest even) and zero padded on the device,
+ * then for each query the K best base rows by the FP32 sum of the rounded
+ * products, ordered by (score descending, id ascending).  ids/scores device
+ * nq x K.  Values must be below 2^15 in magnitude.  Synchronous.
+ * Errors: RG_EINVAL (K < 1, K > 256, K > n, values out of range), RG_ENOMEM,
+ * RG_EDEVICE.
+ */
+int rg_knn_candidates_f16(const float *queries, int64_t nq, const float *base, int64_t n, int32_t d,
+                          int32_t K, uint32_t *ids, float *scores, void *stream);
+
+/*
+ * rg_knn_last_stats -- how the calling thread's last rg_knn (or the kNN of
+ * its last rg_build) certified its rows: from FP16 candidates, from FP32
+ * candidates, by the host scan.  Any output may be NULL.
+ */
+int rg_knn_last_stats(int64_t *rows_f16, int64_t *rows_f32, int64_t *rows_host);
 
 /*
  * rg_search_hashbits -- rg_search with the LDS visited table fixed at

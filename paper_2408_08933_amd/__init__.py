@@ -66,6 +66,8 @@ _SIGS = {
     "rg_search_hashbits": (i32, [P, P, i64, i32, i32, P, P, P, P, i32, P]),
     "rg_knn": (i32, [P, i64, P, i64, i32, i32, P, P, P]),
     "rg_knn_candidates": (i32, [P, i64, P, i64, i32, i32, P, P, P]),
+    "rg_knn_candidates_f16": (i32, [P, i64, P, i64, i32, i32, P, P, P]),
+    "rg_knn_last_stats": (i32, [ctypes.POINTER(i64)] * 3),
     "rg_index_build_stats": (i32, [P] + [ctypes.POINTER(ctypes.c_double)] * 4 + [ctypes.POINTER(i64)]),
     "rg_index_storage_ptrs": (i32, [P, PP, PP, PP, ctypes.POINTER(i32)]),
     "rg_save": (i32, [P, ctypes.c_char_p]),
@@ -316,6 +318,25 @@ def rg_knn_candidates(queries, base, K, stream=None):
     _check(lib().rg_knn_candidates(_ptr(queries), nq, _ptr(base), base.shape[0], base.shape[1], int(K), _ptr(ids),
                                    _ptr(sc), _stream(stream)))
     return ids, sc
+
+
+def rg_knn_candidates_f16(queries, base, K, stream=None):
+    import torch
+    queries, base = _dev_f32(queries, "queries"), _dev_f32(base, "base")
+    nq = queries.shape[0]
+    ids = torch.empty((nq, K), dtype=torch.int32, device=queries.device)
+    sc = torch.empty((nq, K), dtype=torch.float32, device=queries.device)
+    _check(lib().rg_knn_candidates_f16(_ptr(queries), nq, _ptr(base), base.shape[0], base.shape[1], int(K),
+                                       _ptr(ids), _ptr(sc), _stream(stream)))
+    return ids, sc
+
+
+def rg_knn_last_stats():
+    """Rows of this thread's last kNN certified from FP16 candidates, from
+    FP32 candidates and by the host scan."""
+    a, b, c = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
+    _check(lib().rg_knn_last_stats(ctypes.byref(a), ctypes.byref(b), ctypes.byref(c)))
+    return {"f16": a.value, "f32": b.value, "host": c.value}
 
 
 def rg_device_copy(dst, src, stream=None):

@@ -14,6 +14,8 @@
 namespace rg {
 
 static thread_local std::string g_err;
+// rows certified from FP16 candidates, from FP32 candidates, by the host scan
+static thread_local int64_t g_knn_rows[3];
 
 void set_error(const std::string &msg) { g_err = msg; }
 
@@ -200,60 +202,90 @@ uint64_t fnv1a(uint64_t h, const void *p, size_t n) {
 // ---------------------------------------------------------------------------
 // exact kNN
 // ---------------------------------------------------------------------------
+namespace {
+
+// Canonical FP64 kNN of one query row by a full scan of the base on the
+// host: the last resort for a row whose candidates cannot be certified
+// (ties wider than the largest candidate list).
+void knn_scan_row(const float *q, const float *X, int64_t n, int32_t d, int32_t k, int threads, uint32_t *ids,
+                  double *ds) {
+    std::vector<std::pair<double, uint32_t>> all((size_t)n);
+    par_rows(n, threads, [&](int64_t i) {
+        double s = 0.0;
+        for (int j = 0; j < d; ++j) s += (double)q[j] * (double)X[i * d + j];
+        all[i] = {-s, (uint32_t)i};
+    });
+    std::partial_sort(all.begin(), all.begin() + k, all.end());
+    for (int j = 0; j < k; ++j) {
+        ids[j] = all[j].second;
+        if (ds) ds[j] = all[j].first;
+    }
+}
+
+}  // namespace
+
+// Exact k nearest base rows of every query row, in canonical (delta, id)
+// order.  The GPU proposes K candidates per row (first from FP16 rows, at
+// the FP16 matrix rate, when every value fits FP16's range; rows it cannot
+// certify then from FP32 rows with K doubling up to 256); the candidates are
+// rescored with the canonical FP64 distance and a row is kept when its
+// certificate shows no other base row can be among its k nearest.  Rows no
+// list of 256 certifies are scanned in full on the host.
 int knn_exact(const float *Qdev, int64_t nq, const float *Xdev, int64_t n, int32_t d, int32_t k, int32_t slack,
               const float *Qhost, const float *Xhost, int threads, std::vector<uint32_t> *ids_out,
               std::vector<double> *d_out, hipStream_t st) {
     threads = hw_threads(threads);
     if (slack <= 0) slack = std::max(16, k / 4);
-    int32_t K = (int32_t)std::min<int64_t>(n, (int64_t)k + slack);
-    if (K > 256) K = std::max(k, 256);
     ids_out->assign((size_t)nq * k, kNone);
     if (d_out) d_out->assign((size_t)nq * k, INFINITY);
-    // FP32 error bound of any summation order of d rounded products, and the
-    // FP64 one of the canonical sum; scaled by |t| * max|x| (Cauchy-Schwarz).
-    const double u32 = std::ldexp(1.0, -24), u64 = std::ldexp(1.0, -53);
-    const double g32 = (d + 1) * u32 / (1.0 - (d + 1) * u32);
+    g_knn_rows[0] = g_knn_rows[1] = g_knn_rows[2] = 0;
+    const bool log = std::getenv("RG_LOG") != nullptr;
+    const double u32 = std::ldexp(1.0, -24), u64 = std::ldexp(1.0, -53), u16 = std::ldexp(1.0, -11);
     const double g64 = (d + 1) * u64 / (1.0 - (d + 1) * u64);
     std::vector<double> norm2((size_t)n);
+    std::vector<float> xabs((size_t)n), qabs((size_t)nq);  // largest |element| per row
     par_rows(n, threads, [&](int64_t i) {
         double s = 0.0;
-        for (int j = 0; j < d; ++j) s += (double)Xhost[i * d + j] * (double)Xhost[i * d + j];
+        float a = 0.f;
+        for (int j = 0; j < d; ++j) {
+            s += (double)Xhost[i * d + j] * (double)Xhost[i * d + j];
+            a = std::max(a, std::fabs(Xhost[i * d + j]));
+        }
         norm2[i] = s;
+        xabs[i] = a;
     });
-    double xmax = std::sqrt(*std::max_element(norm2.begin(), norm2.end())) * (1.0 + 1e-12);
+    par_rows(nq, threads, [&](int64_t i) {
+        float a = 0.f;
+        for (int j = 0; j < d; ++j) a = std::max(a, std::fabs(Qhost[i * d + j]));
+        qabs[i] = a;
+    });
+    const double xmax = std::sqrt(*std::max_element(norm2.begin(), norm2.end())) * (1.0 + 1e-12);
+    const float amax = std::max(*std::max_element(xabs.begin(), xabs.end()),
+                                nq ? *std::max_element(qabs.begin(), qabs.end()) : 0.f);
 
     std::vector<int64_t> rows((size_t)nq);
     for (int64_t i = 0; i < nq; ++i) rows[i] = i;
-    std::vector<float> qsub;
-    for (;;) {
+
+    // One pass: candidates of the rows listed (kind 16 or 32, K per row),
+    // certification, results of the certified rows; `rows` keeps the others.
+    auto pass = [&](const float *qd, const void *cand_q, const void *cand_x, int32_t dp, bool f16, int32_t K,
+                     double gsum, double eta, double abs0) -> int {
         const int64_t m = (int64_t)rows.size();
-        // queries of this round, contiguous on the device
-        const float *qd = Qdev;
-        DevBuf qbuf;
-        if (m != nq) {
-            qsub.resize((size_t)m * d);
-            for (int64_t i = 0; i < m; ++i) std::memcpy(&qsub[i * d], Qhost + rows[i] * d, sizeof(float) * d);
-            int rc = qbuf.alloc(sizeof(float) * qsub.size());
-            if (rc) return rc;
-            RG_HIP(hipMemcpyAsync(qbuf.p, qsub.data(), sizeof(float) * qsub.size(), hipMemcpyHostToDevice, st));
-            qd = qbuf.as<float>();
-        }
         DevBuf cid, csc;
         int rc = cid.alloc(sizeof(uint32_t) * (size_t)m * K);
         if (!rc) rc = csc.alloc(sizeof(float) * (size_t)m * K);
         if (rc) return rc;
-        rc = launch_knn_candidates(qd, m, d, Xdev, n, d, d, K, cid.as<uint32_t>(), csc.as<float>(), st);
+        rc = f16 ? launch_knn16_candidates(cand_q, m, cand_x, n, dp, K, cid.as<uint32_t>(), csc.as<float>(), st)
+                 : launch_knn_candidates(static_cast<const float *>(cand_q), m, d, static_cast<const float *>(cand_x),
+                                         n, d, d, K, cid.as<uint32_t>(), csc.as<float>(), st);
         if (rc) return rc;
-        if (std::getenv("RG_LOG")) std::fprintf(stderr, "[rg] knn candidates: %lld rows, K=%d\n", (long long)m, K);
-        // canonical FP64 rescoring, ordering and certification on the device;
-        // only each row's k results and its flag come back
         DevBuf oid, od, okb;
         rc = oid.alloc(sizeof(uint32_t) * (size_t)m * k);
         if (!rc && d_out) rc = od.alloc(sizeof(double) * (size_t)m * k);
         if (!rc) rc = okb.alloc((size_t)m);
         if (rc) return rc;
-        rc = launch_knn_certify(qd, m, d, Xdev, n, d, d, cid.as<uint32_t>(), csc.as<float>(), K, k, g32 + g64, xmax,
-                                oid.as<uint32_t>(), d_out ? od.as<double>() : nullptr, okb.as<uint8_t>(), st);
+        rc = launch_knn_certify(qd, m, d, Xdev, n, d, d, cid.as<uint32_t>(), csc.as<float>(), K, k, gsum, xmax, eta,
+                                abs0, oid.as<uint32_t>(), d_out ? od.as<double>() : nullptr, okb.as<uint8_t>(), st);
         if (rc) return rc;
         std::vector<uint32_t> hid((size_t)m * k);
         std::vector<double> hd(d_out ? (size_t)m * k : 0);
@@ -271,14 +303,77 @@ int knn_exact(const float *Qdev, int64_t nq, const float *Xdev, int64_t n, int32
         std::vector<int64_t> fail;
         for (int64_t i = 0; i < m; ++i)
             if (!ok[i]) fail.push_back(rows[i]);
-        if (fail.empty()) return RG_OK;
-        if (K >= 256 || K >= n) {
-            set_error("knn: " + std::to_string(fail.size()) + " rows could not be certified with 256 candidates");
-            return RG_EINTERNAL;
-        }
-        K = (int32_t)std::min<int64_t>(std::min<int64_t>(256, n), 2 * (int64_t)K);
+        g_knn_rows[f16 ? 0 : 1] += m - (int64_t)fail.size();
+        if (log)
+            std::fprintf(stderr, "[rg] knn %s candidates: %lld rows, K=%d, %lld not certified\n", f16 ? "FP16" : "FP32",
+                         (long long)m, K, (long long)fail.size());
         rows.swap(fail);
+        return RG_OK;
+    };
+    // the query rows still uncertified, gathered contiguously on the device
+    std::vector<float> qsub;
+    DevBuf qbuf;
+    auto gather_rows = [&](const float **qd) -> int {
+        if ((int64_t)rows.size() == nq) {
+            *qd = Qdev;
+            return RG_OK;
+        }
+        qsub.resize(rows.size() * (size_t)d);
+        for (size_t i = 0; i < rows.size(); ++i) std::memcpy(&qsub[i * d], Qhost + rows[i] * d, sizeof(float) * d);
+        if (qbuf.p) {
+            (void)hipFree(qbuf.p);
+            qbuf.p = nullptr;
+        }
+        int rc = qbuf.alloc(sizeof(float) * qsub.size());
+        if (rc) return rc;
+        RG_HIP(hipMemcpyAsync(qbuf.p, qsub.data(), sizeof(float) * qsub.size(), hipMemcpyHostToDevice, st));
+        *qd = qbuf.as<float>();
+        return RG_OK;
+    };
+
+    // FP16 pass.  Rounding each input to FP16 errs by at most u16 |v| + eta0
+    // (eta0 = 2^-25, half the subnormal spacing), the products of the
+    // rounded values are exact in FP32, and the FP32 accumulation of dp of
+    // them errs by at most gacc (2 units per add allows truncating adders).
+    // So a candidate score errs by at most
+    //   (2 u16 + u16^2 + gacc (1 + u16)^2) sum|t_i x_i|
+    //   + (1 + gacc) (1 + u16) eta0 (|t|_1 + |x|_1) + (1 + gacc) d eta0^2,
+    // with sum|t_i x_i| <= |t| xmax and |v|_1 <= sqrt(d) |v|.
+    if (amax < 32768.f) {
+        const int32_t dp = knn16_width(d);
+        const int32_t K = (int32_t)std::min<int64_t>(std::min<int64_t>(256, n), std::max(2 * k, k + 48));
+        const double eta0 = std::ldexp(1.0, -25);
+        const double gacc = 2.0 * dp * u32 / (1.0 - 2.0 * dp * u32);
+        const double gsum = 2 * u16 + u16 * u16 + gacc * (1 + u16) * (1 + u16) + g64;
+        const double eta = (1 + gacc) * (1 + u16) * eta0 * std::sqrt((double)d);
+        const double abs0 = (1 + gacc) * d * eta0 * eta0;
+        DevBuf q16, x16;
+        int rc = q16.alloc(2 * (size_t)knn16_rows(nq) * dp);
+        if (!rc) rc = x16.alloc(2 * (size_t)knn16_rows(n) * dp);
+        if (!rc) rc = launch_to_f16(Qdev, nq, d, d, q16.p, knn16_rows(nq), dp, st);
+        if (!rc) rc = launch_to_f16(Xdev, n, d, d, x16.p, knn16_rows(n), dp, st);
+        if (!rc) rc = pass(Qdev, q16.p, x16.p, dp, true, K, gsum, eta, abs0);
+        if (rc) return rc;
     }
+    // FP32 passes for what is left, K doubling
+    const double g32 = (d + 1) * u32 / (1.0 - (d + 1) * u32);
+    int32_t K = (int32_t)std::min<int64_t>(n, (int64_t)k + slack);
+    if (K > 256) K = std::max(k, 256);
+    while (!rows.empty()) {
+        const float *qd = nullptr;
+        int rc = gather_rows(&qd);
+        if (!rc) rc = pass(qd, qd, Xdev, d, false, K, g32 + g64, 0.0, 0.0);
+        if (rc) return rc;
+        if (rows.empty() || K >= 256 || K >= n) break;
+        K = (int32_t)std::min<int64_t>(std::min<int64_t>(256, n), 2 * (int64_t)K);
+    }
+    // the rest by a full canonical scan on the host
+    if (log && !rows.empty())
+        std::fprintf(stderr, "[rg] knn: %lld rows scanned on the host\n", (long long)rows.size());
+    for (int64_t q : rows)
+        knn_scan_row(Qhost + q * d, Xhost, n, d, k, threads, &(*ids_out)[q * k], d_out ? &(*d_out)[q * k] : nullptr);
+    g_knn_rows[2] = (int64_t)rows.size();
+    return RG_OK;
 }
 
 }  // namespace rg
@@ -296,6 +391,46 @@ int rg_knn_candidates(const float *queries, int64_t nq, const float *base, int64
         return RG_EINVAL;
     }
     return launch_knn_candidates(queries, nq, d, base, n, d, d, K, ids, scores, (hipStream_t)stream);
+}
+
+int rg_knn_candidates_f16(const float *queries, int64_t nq, const float *base, int64_t n, int32_t d, int32_t K,
+                          uint32_t *ids, float *scores, void *stream) {
+    if (!queries || !base || !ids || !scores || nq < 0 || n < 1 || n >= (1ll << 31) || d < 1 || K < 1 || K > n ||
+        K > 256) {
+        set_error("rg_knn_candidates_f16: invalid argument");
+        return RG_EINVAL;
+    }
+    if (nq == 0) return RG_OK;
+    hipStream_t st = (hipStream_t)stream;
+    std::vector<float> qh, xh;
+    int rc = copy_to_host(queries, nq * d, qh, st);
+    if (!rc) rc = copy_to_host(base, n * d, xh, st);
+    if (rc) return rc;
+    for (float v : qh)
+        if (!(std::fabs(v) < 32768.f)) {
+            set_error("rg_knn_candidates_f16: a query value is out of the FP16 range used (|v| < 2^15)");
+            return RG_EINVAL;
+        }
+    for (float v : xh)
+        if (!(std::fabs(v) < 32768.f)) {
+            set_error("rg_knn_candidates_f16: a base value is out of the FP16 range used (|v| < 2^15)");
+            return RG_EINVAL;
+        }
+    const int32_t dp = knn16_width(d);
+    DevBuf q16, x16;
+    rc = q16.alloc(2 * (size_t)knn16_rows(nq) * dp);
+    if (!rc) rc = x16.alloc(2 * (size_t)knn16_rows(n) * dp);
+    if (!rc) rc = launch_to_f16(queries, nq, d, d, q16.p, knn16_rows(nq), dp, st);
+    if (!rc) rc = launch_to_f16(base, n, d, d, x16.p, knn16_rows(n), dp, st);
+    if (!rc) rc = launch_knn16_candidates(q16.p, nq, x16.p, n, dp, K, ids, scores, st);
+    return rc;
+}
+
+int rg_knn_last_stats(int64_t *rows_f16, int64_t *rows_f32, int64_t *rows_host) {
+    if (rows_f16) *rows_f16 = g_knn_rows[0];
+    if (rows_f32) *rows_f32 = g_knn_rows[1];
+    if (rows_host) *rows_host = g_knn_rows[2];
+    return RG_OK;
 }
 
 int rg_knn(const float *queries, int64_t nq, const float *base, int64_t n, int32_t d, int32_t k, uint32_t *ids,
@@ -604,6 +739,15 @@ int rg_insert(rg_index *ix, const float *vectors, int64_t nv, int32_t L, void *s
         return RG_EINVAL;
     }
     if (nv == 0) return RG_OK;
+    if (ix->d_base && ix->d_adj_off) {
+        set_error("rg_insert: the index graph is held as CSR (out-degree > 128)");
+        return RG_EINVAL;
+    }
+    for (int64_t i = 0; i < nv * (int64_t)ix->d; ++i)
+        if (!std::isfinite(vectors[i])) {
+            set_error("rg_insert: a vector holds a value that is not finite");
+            return RG_EINVAL;
+        }
     if (L == 0) L = ix->L_build;
     const auto t0 = std::chrono::steady_clock::now();
     hipStream_t st = (hipStream_t)stream;
@@ -614,20 +758,25 @@ int rg_insert(rg_index *ix, const float *vectors, int64_t nv, int32_t L, void *s
     const int64_t n0 = ix->n;
     const int32_t d = ix->d;
     sg.base.insert(sg.base.end(), vectors, vectors + nv * d);
+    // on a failure past this point: the index keeps its n0 rows and graph
+    // (a grown device base holds them first), and its storage form, whose
+    // reduced copies are remade if they were released
+    auto undo = [&](int code) {
+        sg.base.resize((size_t)n0 * d);
+        if (storage != RG_STORE_FP32 && ix->d_base) {
+            const std::string err = g_err;
+            (void)rg_index_set_storage(ix, storage, stream);
+            g_err = err;
+        }
+        return code;
+    };
     std::vector<uint32_t> qid((size_t)nv * L);
     std::vector<int32_t> qn((size_t)nv);
     int rc = RG_OK;
     if (ix->d_base) {
         // canonical searches of the new rows on the device, graph as it stands
-        if (ix->d_adj_off) {
-            set_error("rg_insert: the index graph is held as CSR (out-degree > 128)");
-            return RG_EINVAL;
-        }
         rc = grow_device_base(ix, vectors, nv, st);
-        if (rc) {
-            sg.base.resize((size_t)n0 * d);
-            return rc;
-        }
+        if (rc) return undo(rc);
         const int64_t B = std::min<int64_t>(nv, 1 << 15);
         DevBuf di, dd, dn;
         rc = di.alloc(sizeof(uint32_t) * B * L);
@@ -655,10 +804,7 @@ int rg_insert(rg_index *ix, const float *vectors, int64_t nv, int32_t L, void *s
         rc = host_insert(sg, d, ix->M, ix->m_pj, L, ix->entry, n0, nv, qid.data(), qn.data(), ix->offsets,
                          ix->indices, 0);
     const auto t_merge = std::chrono::steady_clock::now();
-    if (rc) {
-        sg.base.resize((size_t)n0 * d);
-        return rc;
-    }
+    if (rc) return undo(rc);
     ix->n = n0 + nv;
     if (!ix->tomb.empty()) ix->tomb.resize((size_t)((ix->n + 31) / 32), 0u);
     if (ix->d_base) {

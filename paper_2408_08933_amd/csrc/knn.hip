@@ -39,8 +39,8 @@ constexpr int CAP = 512;        // per-row candidate buffer
 constexpr int CE = CAP / 64;    // pairs per lane when sorting a buffer
 
 struct KnnArgs {
-    const float *Q;
-    const float *X;
+    const void *Q;  // FP32 rows (k_knn) or FP16 rows padded to whole tiles (k_knn16)
+    const void *X;
     float *buf_sc;
     uint32_t *buf_id;
     float *out_sc;
@@ -124,12 +124,13 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
     const int nsl = (a.d + KC - 1) / KC;
     float4 va[4], vb[4];
     // interior tiles and full slices load without bounds checks
+    const float *Qf = static_cast<const float *>(a.Q), *Xf = static_cast<const float *>(a.X);
     const bool q_in = vq && q0 + BQ <= a.nq;
-    const float *qrow = a.Q + (q0 + lr) * (int64_t)a.ldq + lk;
+    const float *qrow = Qf + (q0 + lr) * (int64_t)a.ldq + lk;
     auto load_slice = [&](int64_t xt, int k0) {
         const int64_t x0 = xt * BX;
         if (q_in && vx && x0 + BX <= a.n && k0 + KC <= a.d) {
-            const float *xrow = a.X + (x0 + lr) * (int64_t)a.ldx + lk + k0;
+            const float *xrow = Xf + (x0 + lr) * (int64_t)a.ldx + lk + k0;
 #pragma unroll
             for (int p = 0; p < 4; ++p) {
                 va[p] = *reinterpret_cast<const float4 *>(qrow + (int64_t)p * 32 * a.ldq + k0);
@@ -139,8 +140,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
         }
 #pragma unroll
         for (int p = 0; p < 4; ++p) {
-            va[p] = ld4(a.Q, a.nq, a.ldq, a.d, q0 + p * 32 + lr, k0 + lk, vq);
-            vb[p] = ld4(a.X, a.n, a.ldx, a.d, x0 + p * 32 + lr, k0 + lk, vx);
+            va[p] = ld4(Qf, a.nq, a.ldq, a.d, q0 + p * 32 + lr, k0 + lk, vq);
+            vb[p] = ld4(Xf, a.n, a.ldx, a.d, x0 + p * 32 + lr, k0 + lk, vx);
         }
     };
     // A partial last slice is stored permuted: coordinate c at position
@@ -268,6 +269,177 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
     }
 }
 
+// ---------------------------------------------------------------------------
+// FP16 candidate pass (v_mfma_f32_16x16x32_f16, FP32 accumulation).
+//
+// The rows arrive rounded to FP16 (round to nearest even) and zero padded to
+// a multiple of 32 coordinates and to whole tiles, so every load is in
+// bounds and unchecked.  A workgroup owns 128 query rows and sweeps 128-row
+// tiles of the base; its four wavefronts each hold a 64 x 64 quarter of the
+// tile as 4 x 4 blocks of 16 x 16 (64 accumulator registers).  Operands are
+// staged through two LDS buffers 32 coordinates at a time, rows padded to 40
+// halves (80 bytes) so that the 16 lanes of a quarter-wave read distinct
+// banks.  In an MFMA k-step lane l supplies, for row (or column) l % 16, the
+// 8 coordinates 8 * (l / 16) .. + 7 of the slice, the same coordinates for
+// both operands.  The filter and the per-row candidate buffers are those of
+// k_knn above.  The scores are FP32 sums of exact products of the rounded
+// inputs; how far they may be from the exact ones is bounded in the
+// certification (knn_exact).
+// ---------------------------------------------------------------------------
+typedef _Float16 hx8 __attribute__((ext_vector_type(8)));
+
+constexpr int BQ16 = 128, BX16 = 128, KS16 = 32, AP16 = 40;  // AP16: LDS row pitch in halves
+
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k_knn16(KnnArgs a) {
+    __shared__ __align__(16) _Float16 As[2][BQ16 * AP16];
+    __shared__ __align__(16) _Float16 Bs[2][BX16 * AP16];
+    __shared__ __align__(16) float thr[BQ16];
+    __shared__ int cnt[BQ16];
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int wr = w >> 1, wc = w & 1;
+    const int64_t qt = a.q_tile0 + blockIdx.x;
+    const int sp = blockIdx.y;
+    const int64_t q0 = qt * BQ16;
+    const int64_t slot = (int64_t)blockIdx.x * a.splits + sp;
+    float *bsc = a.buf_sc + slot * BQ16 * CAP;
+    uint32_t *bid = a.buf_id + slot * BQ16 * CAP;
+    const _Float16 *Qh = static_cast<const _Float16 *>(a.Q), *Xh = static_cast<const _Float16 *>(a.X);
+
+    if (tid < BQ16) {
+        thr[tid] = -__builtin_inff();
+        cnt[tid] = 0;
+    }
+    const int64_t xt0 = (int64_t)sp * a.xtiles_per_split;
+    const int64_t xt1 = min(a.xtiles, xt0 + a.xtiles_per_split);
+    // staging: thread t moves the 16-byte chunk (t & 3) of rows (t >> 2) and
+    // (t >> 2) + 64 of both operands
+    const int lr = tid >> 2, lc = (tid & 3) * 8;
+    const int nks = a.d / KS16;  // d is the padded width here
+    const _Float16 *qsrc = Qh + (q0 + lr) * (int64_t)a.ldq + lc;
+    const int64_t qstep = 64 * (int64_t)a.ldq, xstep = 64 * (int64_t)a.ldx;
+    uint4 va0, va1, vb0, vb1;
+    _Float16 *adst = &As[0][lr * AP16 + lc], *bdst = &Bs[0][lr * AP16 + lc];
+    constexpr int ABUF = BQ16 * AP16, BBUF = BX16 * AP16, P64 = 64 * AP16;
+#define KNN16_LOAD(xt_, k0_)                                                                         \
+    do {                                                                                             \
+        const _Float16 *qs_ = qsrc + (k0_);                                                          \
+        const _Float16 *xs_ = Xh + ((xt_) * BX16 + lr) * (int64_t)a.ldx + lc + (k0_);                \
+        va0 = *reinterpret_cast<const uint4 *>(qs_);                                                 \
+        va1 = *reinterpret_cast<const uint4 *>(qs_ + qstep);                                         \
+        vb0 = *reinterpret_cast<const uint4 *>(xs_);                                                 \
+        vb1 = *reinterpret_cast<const uint4 *>(xs_ + xstep);                                         \
+    } while (0)
+#define KNN16_STORE(buf_)                                                                            \
+    do {                                                                                             \
+        _Float16 *ad_ = adst + (buf_) * ABUF, *bd_ = bdst + (buf_) * BBUF;                           \
+        *reinterpret_cast<uint4 *>(ad_) = va0;                                                       \
+        *reinterpret_cast<uint4 *>(ad_ + P64) = va1;                                                 \
+        *reinterpret_cast<uint4 *>(bd_) = vb0;                                                       \
+        *reinterpret_cast<uint4 *>(bd_ + P64) = vb1;                                                 \
+    } while (0)
+    int gst = 0;
+    if (xt0 < xt1) {
+        KNN16_LOAD(xt0, 0);
+        KNN16_STORE(0);
+    }
+    __syncthreads();
+    const int fr = lane & 15, fk = (lane >> 4) * 8;
+    const _Float16 *afrag = &As[0][(wr * 64 + fr) * AP16 + fk];
+    const _Float16 *bfrag = &Bs[0][(wc * 64 + fr) * AP16 + fk];
+    for (int64_t xt = xt0; xt < xt1; ++xt) {
+        const int64_t x0 = xt * BX16;
+        fx4 acc[4][4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+            for (int j = 0; j < 4; ++j) acc[i][j] = fx4{0.f, 0.f, 0.f, 0.f};
+        for (int ks = 0; ks < nks; ++ks, ++gst) {
+            const int buf = gst & 1;
+            const bool more = ks + 1 < nks || xt + 1 < xt1;
+            if (ks + 1 < nks)
+                KNN16_LOAD(xt, (ks + 1) * KS16);
+            else if (xt + 1 < xt1)
+                KNN16_LOAD(xt + 1, 0);
+            const _Float16 *ab = afrag + buf * ABUF, *bb = bfrag + buf * BBUF;
+            hx8 af[4], bf[4];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) af[i] = *reinterpret_cast<const hx8 *>(ab + i * 16 * AP16);
+#pragma unroll
+            for (int j = 0; j < 4; ++j) bf[j] = *reinterpret_cast<const hx8 *>(bb + j * 16 * AP16);
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+#pragma unroll
+                for (int j = 0; j < 4; ++j)
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_f16(af[i], bf[j], acc[i][j], 0, 0, 0);
+            if (more) KNN16_STORE(buf ^ 1);
+            __syncthreads();
+        }
+#undef KNN16_LOAD
+#undef KNN16_STORE
+        // filter: accumulator element r of block (i, j) is query row
+        // 16 i + 4 (lane / 16) + r of the wave's half, base column lane % 16
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int rb = wr * 64 + i * 16 + 4 * (lane >> 4);
+            const fx4 t4 = *reinterpret_cast<const fx4 *>(&thr[rb]);
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int row = rb + r;
+                const bool rok = q0 + row < a.nq;
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    const int64_t gx = x0 + wc * 64 + j * 16 + fr;
+                    const float sc = acc[i][j][r];
+                    if (rok && gx < a.n && sc >= t4[r]) {
+                        const int pos = atomicAdd(&cnt[row], 1);
+                        bsc[(int64_t)row * CAP + pos] = sc;
+                        bid[(int64_t)row * CAP + pos] = (uint32_t)gx;
+                    }
+                }
+            }
+        }
+        __syncthreads();
+        for (int row = w; row < BQ16; row += 4) {
+            const int c = cnt[row];
+            if (c > CAP - BX16) {
+                float t = thr[row];
+                const int nc = compact_row(bsc + (int64_t)row * CAP, bid + (int64_t)row * CAP, c, a.K, t);
+                if (lane == 0) {
+                    cnt[row] = nc;
+                    thr[row] = t;
+                }
+            }
+        }
+        __syncthreads();
+    }
+    for (int row = w; row < BQ16; row += 4) {
+        const int64_t gq = q0 + row;
+        if (gq >= a.nq) continue;
+        float t = thr[row];
+        float *rs = bsc + (int64_t)row * CAP;
+        uint32_t *ri = bid + (int64_t)row * CAP;
+        const int c = compact_row(rs, ri, cnt[row], a.K, t);
+        float *os = a.out_sc + ((int64_t)sp * a.nq + gq) * a.K;
+        uint32_t *oi = a.out_id + ((int64_t)sp * a.nq + gq) * a.K;
+        for (int i = lane; i < a.K; i += 64) {
+            os[i] = i < c ? rs[i] : -__builtin_inff();
+            oi[i] = i < c ? ri[i] : kNone;
+        }
+    }
+}
+
+// FP32 rows -> FP16 (round to nearest even), rows_pad x dp, zeros past
+// (rows, d).
+__global__ void k_to_f16(const float *src, int64_t rows, int32_t d, int64_t ld, _Float16 *dst, int64_t rows_pad,
+                         int32_t dp) {
+    const int64_t total = rows_pad * dp;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t r = i / dp;
+        const int c = (int)(i - r * dp);
+        dst[i] = (r < rows && c < d) ? (_Float16)src[r * ld + c] : (_Float16)0.f;
+    }
+}
+
 // Merge per-split top-K lists into one (one wavefront per query row).
 __global__ __launch_bounds__(64) void k_knn_merge(const float *sc, const uint32_t *id, int64_t nq, int K,
                                                   int splits, float *out_sc, uint32_t *out_id) {
@@ -326,7 +498,8 @@ struct CertArgs {
     uint8_t *ok;       // m
     int64_t m, n, ldq, ldx;
     int32_t d, K, k;
-    double gsum, xmax;  // FP32 + FP64 summation bound factor, max row norm
+    double gsum, xmax;  // relative error bound factor of the candidate scores (and the canonical sum), max row norm
+    double eta, abs0;   // absolute part of that bound: eta * (|t| + xmax) + abs0 (FP16 underflow)
 };
 
 __device__ __forceinline__ double canon_dot(const float *qs, const float *row, int d) {
@@ -367,7 +540,8 @@ __global__ __launch_bounds__(64) void k_knn_certify(CertArgs a) {
     if (!certified && valid >= a.k) {
         double tn = 0.0;
         for (int i = 0; i < a.d; ++i) tn = fma((double)qs[i], (double)qs[i], tn);
-        const double tau = a.gsum * sqrt(tn) * (1.0 + 1e-12) * a.xmax;
+        const double tnorm = sqrt(tn) * (1.0 + 1e-12);
+        const double tau = a.gsum * tnorm * a.xmax + a.eta * (tnorm + a.xmax) + a.abs0;
         const double sigma = (double)a.csc[r * a.K + a.K - 1];
         const int src = (a.k - 1) / CERT_E, se = (a.k - 1) % CERT_E;
         double kth = 0.0;
@@ -393,12 +567,20 @@ __global__ __launch_bounds__(64) void k_knn_certify(CertArgs a) {
 
 namespace {
 
+// One kernel of the candidate pass: the kernel, its query rows per
+// workgroup and base rows per tile, and the byte size of a row element.
+struct KnnKernel {
+    void (*fn)(KnnArgs);
+    int bq, bx;
+    size_t elem;
+};
+
 // Candidates of query rows [0, nq) of Q (one launch series, one split policy).
-int knn_range(const float *Q, int64_t nq, int32_t ldq, const float *X, int64_t n, int32_t ldx, int32_t d,
-              int32_t K, uint32_t *ids, float *scores, hipStream_t stream) {
+int knn_range(const KnnKernel &kk, const void *Q, int64_t nq, int32_t ldq, const void *X, int64_t n, int32_t ldx,
+              int32_t d, int32_t K, uint32_t *ids, float *scores, bool vec_q, bool vec_x, hipStream_t stream) {
     if (nq == 0) return RG_OK;
-    const int64_t qtiles = (nq + BQ - 1) / BQ;
-    const int64_t xtiles = (n + BX - 1) / BX;
+    const int64_t qtiles = (nq + kk.bq - 1) / kk.bq;
+    const int64_t xtiles = (n + kk.bx - 1) / kk.bx;
     // split the base when there are too few query tiles to fill the chip
     int splits = (int)std::min<int64_t>(16, std::max<int64_t>(1, 1024 / qtiles));
     splits = (int)std::min<int64_t>(splits, xtiles);
@@ -415,8 +597,8 @@ int knn_range(const float *Q, int64_t nq, int32_t ldq, const float *X, int64_t n
         if (tmp_sc) (void)hipFree(tmp_sc);
         if (tmp_id) (void)hipFree(tmp_id);
     };
-    if (hipMalloc(&buf_sc, sizeof(float) * slots * BQ * CAP) != hipSuccess ||
-        hipMalloc(&buf_id, sizeof(uint32_t) * slots * BQ * CAP) != hipSuccess) {
+    if (hipMalloc(&buf_sc, sizeof(float) * slots * kk.bq * CAP) != hipSuccess ||
+        hipMalloc(&buf_id, sizeof(uint32_t) * slots * kk.bq * CAP) != hipSuccess) {
         cleanup();
         set_error("knn: out of device memory for candidate buffers");
         return RG_ENOMEM;
@@ -445,13 +627,13 @@ int knn_range(const float *Q, int64_t nq, int32_t ldq, const float *X, int64_t n
     a.d = d;
     a.K = K;
     a.splits = splits;
-    a.vec_q = (ldq % 4 == 0) && ((uintptr_t)Q % 16 == 0);
-    a.vec_x = (ldx % 4 == 0) && ((uintptr_t)X % 16 == 0);
+    a.vec_q = vec_q;
+    a.vec_x = vec_x;
     const bool log = std::getenv("RG_LOG") != nullptr && qtiles > tiles_per_launch;
     for (int64_t t0 = 0; t0 < qtiles; t0 += tiles_per_launch) {
         a.q_tile0 = t0;
         const int64_t nt = std::min(tiles_per_launch, qtiles - t0);
-        hipLaunchKernelGGL(k_knn, dim3((unsigned)nt, (unsigned)splits), dim3(256), 0, stream, a);
+        hipLaunchKernelGGL(kk.fn, dim3((unsigned)nt, (unsigned)splits), dim3(256), 0, stream, a);
         if (hipGetLastError() != hipSuccess) {
             cleanup();
             set_error("knn: kernel launch failed");
@@ -481,6 +663,30 @@ int knn_range(const float *Q, int64_t nq, int32_t ldq, const float *X, int64_t n
     return RG_OK;
 }
 
+// Each workgroup sweeps the base for one query tile.  When the tiles leave
+// a thin last wave of workgroups (under half the device), its tiles run
+// with the base split across workgroups instead, so the chip is not mostly
+// idle for a whole sweep (same candidates).
+int knn_series(const KnnKernel &kk, const void *Q, int64_t nq, int32_t ldq, const void *X, int64_t n, int32_t ldx,
+               int32_t d, int32_t K, uint32_t *ids, float *scores, bool vec_q, bool vec_x, hipStream_t stream) {
+    int per_cu = 0, cus = 0, dev = 0;
+    RG_HIP(hipGetDevice(&dev));
+    RG_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+    RG_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kk.fn, 256, 0));
+    const int64_t resident = (int64_t)std::max(1, per_cu) * std::max(1, cus);
+    const int64_t qtiles = (nq + kk.bq - 1) / kk.bq;
+    const int64_t rem = qtiles % resident;
+    if (qtiles > resident && rem != 0 && rem < resident / 2) {
+        const int64_t nq_main = (qtiles - rem) * kk.bq;
+        const int rc = knn_range(kk, Q, nq_main, ldq, X, n, ldx, d, K, ids, scores, vec_q, vec_x, stream);
+        if (rc) return rc;
+        const void *Qr = static_cast<const char *>(Q) + (size_t)nq_main * ldq * kk.elem;
+        return knn_range(kk, Qr, nq - nq_main, ldq, X, n, ldx, d, K, ids + nq_main * K, scores + nq_main * K,
+                         vec_q, vec_x, stream);
+    }
+    return knn_range(kk, Q, nq, ldq, X, n, ldx, d, K, ids, scores, vec_q, vec_x, stream);
+}
+
 }  // namespace
 
 int launch_knn_candidates(const float *Q, int64_t nq, int32_t ldq, const float *X, int64_t n, int32_t ldx,
@@ -489,30 +695,40 @@ int launch_knn_candidates(const float *Q, int64_t nq, int32_t ldq, const float *
         set_error("knn: K must be in [1, 256]");
         return RG_EINVAL;
     }
-    // Each workgroup sweeps the base for one 128-row query tile.  When the
-    // tiles leave a thin last wave of workgroups (under half the device), its
-    // tiles run with the base split across workgroups instead, so the chip
-    // is not mostly idle for a whole sweep (same candidates).
-    int per_cu = 0, cus = 0, dev = 0;
-    RG_HIP(hipGetDevice(&dev));
-    RG_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
-    RG_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_knn, 256, 0));
-    const int64_t resident = (int64_t)std::max(1, per_cu) * std::max(1, cus);
-    const int64_t qtiles = (nq + BQ - 1) / BQ;
-    const int64_t rem = qtiles % resident;
-    if (qtiles > resident && rem != 0 && rem < resident / 2) {
-        const int64_t nq_main = (qtiles - rem) * BQ;
-        const int rc = knn_range(Q, nq_main, ldq, X, n, ldx, d, K, ids, scores, stream);
-        if (rc) return rc;
-        return knn_range(Q + nq_main * ldq, nq - nq_main, ldq, X, n, ldx, d, K, ids + nq_main * K,
-                         scores + nq_main * K, stream);
+    const KnnKernel kk{k_knn, BQ, BX, sizeof(float)};
+    const bool vq = (ldq % 4 == 0) && ((uintptr_t)Q % 16 == 0);
+    const bool vx = (ldx % 4 == 0) && ((uintptr_t)X % 16 == 0);
+    return knn_series(kk, Q, nq, ldq, X, n, ldx, d, K, ids, scores, vq, vx, stream);
+}
+
+int64_t knn16_rows(int64_t rows) { return (rows + BQ16 - 1) / BQ16 * BQ16; }
+
+int32_t knn16_width(int32_t d) { return (d + KS16 - 1) / KS16 * KS16; }
+
+int launch_to_f16(const float *src, int64_t rows, int32_t d, int64_t ld, void *dst, int64_t rows_pad, int32_t dp,
+                  hipStream_t stream) {
+    if (rows_pad == 0) return RG_OK;
+    const int64_t total = rows_pad * dp;
+    const unsigned blocks = (unsigned)std::min<int64_t>(65536, (total + 255) / 256);
+    hipLaunchKernelGGL(k_to_f16, dim3(blocks), dim3(256), 0, stream, src, rows, d, ld, static_cast<_Float16 *>(dst),
+                       rows_pad, dp);
+    RG_HIP(hipGetLastError());
+    return RG_OK;
+}
+
+int launch_knn16_candidates(const void *Q16, int64_t nq, const void *X16, int64_t n, int32_t dp, int32_t K,
+                            uint32_t *ids, float *scores, hipStream_t stream) {
+    if (K < 1 || K > CAP - BX16 || K > CAP / 2 || dp % KS16 != 0) {
+        set_error("knn16: K must be in [1, 256] and the width a multiple of 32");
+        return RG_EINVAL;
     }
-    return knn_range(Q, nq, ldq, X, n, ldx, d, K, ids, scores, stream);
+    const KnnKernel kk{k_knn16, BQ16, BX16, sizeof(_Float16)};
+    return knn_series(kk, Q16, nq, dp, X16, n, dp, dp, K, ids, scores, true, true, stream);
 }
 
 int launch_knn_certify(const float *Q, int64_t m, int64_t ldq, const float *X, int64_t n, int64_t ldx, int32_t d,
                        const uint32_t *cid, const float *csc, int32_t K, int32_t k, double gsum, double xmax,
-                       uint32_t *out_id, double *out_d, uint8_t *ok, hipStream_t stream) {
+                       double eta, double abs0, uint32_t *out_id, double *out_d, uint8_t *ok, hipStream_t stream) {
     if (K < k || K > 64 * CERT_E || k < 1 || d < 1 || d > 16384) {
         set_error("knn certify: bad candidate count or dimension");
         return RG_EINVAL;
@@ -535,6 +751,8 @@ int launch_knn_certify(const float *Q, int64_t m, int64_t ldq, const float *X, i
     a.k = k;
     a.gsum = gsum;
     a.xmax = xmax;
+    a.eta = eta;
+    a.abs0 = abs0;
     hipLaunchKernelGGL(k_knn_certify, dim3((unsigned)m), dim3(64), sizeof(float) * (size_t)d, stream, a);
     RG_HIP(hipGetLastError());
     return RG_OK;

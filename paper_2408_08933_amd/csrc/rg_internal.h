@@ -112,11 +112,20 @@ int launch_serve_admit(int32_t n, const int32_t *slots, const float *q, const in
 int launch_knn_candidates(const float *Q, int64_t nq, int32_t ldq, const float *X, int64_t n,
                           int32_t ldx, int32_t d, int32_t K, uint32_t *ids, float *scores,
                           hipStream_t stream);
-// Canonical FP64 rescoring, sort and certification of m rows of K FP32
+// The same from FP16 rows (round to nearest even): Q16 and X16 hold
+// knn16_rows(rows) rows of knn16_width(d) halves, zero padded.
+int64_t knn16_rows(int64_t rows);
+int32_t knn16_width(int32_t d);
+int launch_to_f16(const float *src, int64_t rows, int32_t d, int64_t ld, void *dst, int64_t rows_pad, int32_t dp,
+                  hipStream_t stream);
+int launch_knn16_candidates(const void *Q16, int64_t nq, const void *X16, int64_t n, int32_t dp, int32_t K,
+                            uint32_t *ids, float *scores, hipStream_t stream);
+// Canonical FP64 rescoring, sort and certification of m rows of K
 // candidates (see knn.hip); ok[i] = 1 where row i's k results are exact.
+// A candidate score errs by at most gsum |t| xmax + eta (|t| + xmax) + abs0.
 int launch_knn_certify(const float *Q, int64_t m, int64_t ldq, const float *X, int64_t n, int64_t ldx, int32_t d,
                        const uint32_t *cid, const float *csc, int32_t K, int32_t k, double gsum, double xmax,
-                       uint32_t *out_id, double *out_d, uint8_t *ok, hipStream_t stream);
+                       double eta, double abs0, uint32_t *out_id, double *out_d, uint8_t *ok, hipStream_t stream);
 
 // quant.hip
 int launch_pad_rows(const float *src, int64_t n, int32_t d, float *dst, int32_t pitch,

@@ -73,18 +73,6 @@ def test_knn_candidates_are_fp32_topk(dev, nq, n, d, K):
         assert got[q].min() >= kth_true[q] - 2 * tau[q, 0]
 
 
-@pytest.mark.parametrize("nq,k", [(1000, 10), (37, 100), (129, 1)])
-def test_knn_exact_matches_oracle(dev, oracle_lib, c1, nq, k):
-    X, Tr, Q, G = c1
-    Qs = np.concatenate([Q, Tr])[:nq]
-    say(f"rg_knn nq={nq} k={k}")
-    ids, ds = rg.rg_knn(T(Qs, dev), T(X, dev), k)
-    torch.cuda.synchronize()
-    oi, od = oracle_lib.knn(X, Qs, k)
-    assert np.array_equal(rg.as_u32(ids), oi)
-    assert np.array_equal(ds.cpu().numpy(), od.astype(np.float32))
-
-
 def test_knn_certification_retries_on_ties(dev, oracle_lib):
     # 40 identical rows nearest to every query: the first candidate list
     # (k + 16 = 26) ends inside the tie, so certification fails and the rows
@@ -106,15 +94,114 @@ def test_knn_certification_retries_on_ties(dev, oracle_lib):
     assert np.array_equal(ds.cpu().numpy(), od.astype(np.float32))
 
 
-def test_knn_uncertifiable_tie_is_an_error(dev):
-    # a tie of 300 rows cannot be resolved with at most 256 candidates
+def test_knn_tie_wider_than_any_candidate_list(dev, oracle_lib):
+    # a tie of 300 rows cannot be certified with at most 256 candidates; the
+    # rows are scanned in full on the host and the answer is still exact
     rng = np.random.default_rng(12)
     X = rng.standard_normal((2000, 16)).astype(np.float32) * 0.1
     X[:300] = 1.0
     Q = np.ones((4, 16), np.float32)
+    say("rg_knn with a 300-row tie, k=10")
+    ids, ds = rg.rg_knn(T(Q, dev), T(X, dev), 10)
+    torch.cuda.synchronize()
+    st = rg.rg_knn_last_stats()
+    oi, od = oracle_lib.knn(X, Q, 10)
+    assert np.array_equal(rg.as_u32(ids), oi) and (oi == np.arange(10)).all()
+    assert np.array_equal(ds.cpu().numpy(), od.astype(np.float32))
+    assert st == {"f16": 0, "f32": 0, "host": 4}
+
+
+def _fp16_scores(Q, X):
+    """Exact sums of the products of the FP16-rounded inputs (the FP16
+    pass's scores before FP32 accumulation), and the sums of their
+    magnitudes."""
+    q = torch.from_numpy(Q).half().double().numpy()
+    x = torch.from_numpy(X).half().double().numpy()
+    return q @ x.T, np.abs(q) @ np.abs(x).T
+
+
+# d = 16 and 200 are not multiples of 32 (zero padded); nq and n ragged
+@pytest.mark.parametrize("nq,n,d,K", [(300, 3000, 64, 48), (257, 1999, 200, 40), (5, 128, 16, 128),
+                                      (1000, 10000, 512, 200), (70, 1500, 95, 30)])
+def test_knn_candidates_f16_are_fp16_topk(dev, nq, n, d, K):
+    say(f"knn_candidates_f16 nq={nq} n={n} d={d} K={K}")
+    rng = np.random.default_rng(nq + n + d + 1)
+    X = rng.standard_normal((n, d)).astype(np.float32)
+    Q = rng.standard_normal((nq, d)).astype(np.float32)
+    ids, sc = rg.rg_knn_candidates_f16(T(Q, dev), T(X, dev), K)
+    torch.cuda.synchronize()
+    ids, sc = rg.as_u32(ids), sc.cpu().numpy().astype(np.float64)
+    S16, A16 = _fp16_scores(Q, X)
+    dp = (d + 31) // 32 * 32
+    gacc = 2 * dp * 2.0 ** -24 / (1 - 2 * dp * 2.0 ** -24)   # FP32 accumulation, any order, truncating adds
+    assert (ids < n).all()
+    assert all(len(set(r.tolist())) == K for r in ids)
+    got = np.take_along_axis(S16, ids.astype(np.int64), axis=1)
+    tau = gacc * np.take_along_axis(A16, ids.astype(np.int64), axis=1)
+    assert (np.abs(got - sc) <= tau).all()                   # each score is its pair's FP16-product sum
+    assert (np.diff(sc, axis=1) <= 0).all()                  # descending
+    for q in range(nq):
+        out = np.setdiff1d(np.arange(n), ids[q].astype(np.int64))
+        # nothing left out beats the K-th kept score beyond both roundings
+        assert (S16[q, out] <= sc[q, K - 1] + gacc * (A16[q, out] + A16[q].max())).all()
+
+
+@pytest.mark.parametrize("nq,k", [(1000, 10), (37, 100), (129, 1)])
+def test_knn_exact_through_fp16_candidates(dev, oracle_lib, c1, nq, k):
+    X, Tr, Q, G = c1
+    Qs = np.concatenate([Q, Tr])[:nq]
+    say(f"rg_knn (FP16 candidates) nq={nq} k={k}")
+    ids, ds = rg.rg_knn(T(Qs, dev), T(X, dev), k)
+    torch.cuda.synchronize()
+    st = rg.rg_knn_last_stats()
+    say(f"  certified rows: {st}")
+    oi, od = oracle_lib.knn(X, Qs, k)
+    assert np.array_equal(rg.as_u32(ids), oi)
+    assert np.array_equal(ds.cpu().numpy(), od.astype(np.float32))
+    assert st["f16"] + st["f32"] + st["host"] == nq and st["f16"] >= 0.99 * nq
+
+
+def test_knn_values_beyond_fp16_range_use_fp32(dev, oracle_lib):
+    rng = np.random.default_rng(3)
+    X = rng.standard_normal((3000, 32)).astype(np.float32)
+    X[7, 3] = 1e5
+    Q = rng.standard_normal((50, 32)).astype(np.float32)
+    ids, ds = rg.rg_knn(T(Q, dev), T(X, dev), 10)
+    torch.cuda.synchronize()
+    st = rg.rg_knn_last_stats()
+    oi, od = oracle_lib.knn(X, Q, 10)
+    assert np.array_equal(rg.as_u32(ids), oi) and st["f16"] == 0 and st["f32"] == 50
     with pytest.raises(rg.RGError):
-        rg.rg_knn(T(Q, dev), T(X, dev), 10)
-        torch.cuda.synchronize()
+        rg.rg_knn_candidates_f16(T(Q, dev), T(X, dev), 10)
+
+
+def test_knn_multi_launch_and_thin_last_wave(dev, oracle_lib):
+    # 200k query rows: more query tiles than one launch takes (1,024) and a
+    # last wave too thin to fill the device, which runs with the base split
+    # across workgroups; both candidate kernels, sampled rows checked
+    g = datagen.Generator(1, n=60_000, n_train=200_000, n_test=1)
+    X, Tr = g.base(), g.train()
+    say("rg_knn 200k x 60k x 64, k=32")
+    ids, ds = rg.rg_knn(T(Tr, dev), T(X, dev), 32)
+    torch.cuda.synchronize()
+    st = rg.rg_knn_last_stats()
+    say(f"  certified rows: {st}")
+    assert st["f16"] + st["f32"] + st["host"] == len(Tr)
+    pick = np.unique(np.concatenate([np.arange(0, len(Tr), 997), np.arange(len(Tr) - 300, len(Tr))]))
+    oi, od = oracle_lib.knn(X, Tr[pick], 32)
+    got = rg.as_u32(ids)[pick]
+    assert np.array_equal(got, oi)
+    assert np.array_equal(ds.cpu().numpy()[pick], od.astype(np.float32))
+    say("rg_knn_candidates (FP32) 200k x 60k x 64, K=40")
+    cid, csc = rg.rg_knn_candidates(T(Tr, dev), T(X, dev), 40)
+    torch.cuda.synchronize()
+    cid, csc = rg.as_u32(cid)[pick].astype(np.int64), csc.cpu().numpy()[pick].astype(np.float64)
+    S = Tr[pick].astype(np.float64) @ X.astype(np.float64).T
+    u = 2.0 ** -24
+    tau = 65 * u / (1 - 65 * u) * np.linalg.norm(Tr[pick], axis=1)[:, None] * np.linalg.norm(X, axis=1).max()
+    assert (np.abs(np.take_along_axis(S, cid, axis=1) - csc) <= tau).all()
+    kth = -np.sort(-S, axis=1)[:, 39]
+    assert (np.take_along_axis(S, cid, axis=1).min(axis=1) >= kth - 2 * tau[:, 0]).all()
 
 
 def test_knn_rejects_bad_k(dev):
@@ -248,6 +335,24 @@ def test_build_bit_exact_wide_lists(dev, oracle_lib):
     G = oracle_lib.Graph(X, Tr, 48, 128, 200)
     off, idx, entry = ix.graph()
     assert entry == G.entry and np.array_equal(off, G.offsets) and np.array_equal(idx, G.indices)
+
+
+def test_build_bit_exact_three_enhancement_batches(dev, oracle_lib):
+    # 70k rows: the device enhancement runs in batches of 32,768 nodes (three
+    # here, the last one ragged) and the kNN in FP16 candidates over
+    # 547 query tiles; the graph must equal the oracle's bit for bit
+    g = datagen.Generator(1, n=70_000, n_train=70_000, n_test=1)
+    X, Tr = g.base(), g.train()
+    say("oracle build 70k x 64, Nq=32, M=32, L=200")
+    G = oracle_lib.Graph(X, Tr, 32, 32, 200)
+    say("rg_build 70k x 64")
+    ix = rg.rg_build(T(X, dev), T(Tr, dev), 32, 32, L_build=200)
+    st = rg.rg_knn_last_stats()
+    say(f"  kNN rows certified: {st}")
+    off, idx, entry = ix.graph()
+    assert entry == G.entry
+    assert np.array_equal(off, G.offsets) and np.array_equal(idx, G.indices)
+    assert ix.build_stats()["repairs"] == G.repairs
 
 
 def test_build_stage_graphs_c1(oracle_lib, c1, c1_built):

@@ -58,11 +58,11 @@ def alone(dev, ix, q, k, L):
     return rg.as_u32(ids)[0], ds.cpu().numpy()[0]
 
 
-@pytest.mark.parametrize("storage", ["fp32", "fp8"])
+@pytest.mark.parametrize("storage", ["fp32", "bf16", "fp8"])
 def test_alone_equals_mix(setup, storage):
     dev, X, Q, ix = setup
-    if storage == "fp8":
-        rg.rg_index_set_storage(ix, rg.RG_STORE_FP8E4M3)
+    if storage != "fp32":
+        rg.rg_index_set_storage(ix, rg.RG_STORE_BF16 if storage == "bf16" else rg.RG_STORE_FP8E4M3)
     try:
         rng = np.random.default_rng(5)
         n = 240

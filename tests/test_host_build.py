@@ -216,3 +216,27 @@ def test_delete_marks_tombstones(oracle_lib):
     assert dead == [3, 40, 299]
     with pytest.raises(rg.RGError):
         ix.delete([300])
+
+
+def test_failed_insert_leaves_the_index_unchanged(oracle_lib):
+    # a rejected call (a non-finite value) must not touch rows, graph or the
+    # bipartite lists; a later valid insert behaves as on a fresh index
+    gen = datagen.Generator(1, n=400, n_train=400, n_test=10)
+    X, T = gen.base(), gen.train()
+    knn, _ = oracle_lib.knn(X, T, 8)
+    ix = rg.rg_build_from_knn(X, knn, 8, 8, L_build=50, keep_stages=True, train_host=T)
+    ref = rg.rg_build_from_knn(X, knn, 8, 8, L_build=50, keep_stages=True, train_host=T)
+    before = ix.graph(), ix.bipartite(), ix.info()["n"]
+    bad = X[:3] + 0.01
+    bad[1, 5] = np.nan
+    with pytest.raises(rg.RGError) as e:
+        ix.insert(bad)
+    assert e.value.code == rg.RG_EINVAL
+    after = ix.graph(), ix.bipartite(), ix.info()["n"]
+    assert after[2] == before[2]
+    assert all(np.array_equal(a, b) for a, b in zip(after[0][:2], before[0][:2])) and after[0][2] == before[0][2]
+    assert all(np.array_equal(a, b) for a, b in zip(after[1], before[1]))
+    good = X[:3] + 0.01
+    ix.insert(good)
+    ref.insert(good)
+    assert all(np.array_equal(a, b) for a, b in zip(ix.graph()[:2], ref.graph()[:2]))
