@@ -35,11 +35,17 @@ For both laws a query is s (.) point' + G u, with point' from the query
 mixture, u a fixed random unit vector (the "modality gap", norm G) and s a
 per-dimension scale (all ones unless the config says otherwise); rows are
 L2-normalised when the config is a cosine workload.
-Seeds: 240808933 + 1000 * config + stream, one stream per role.
+Seeds: 240808933 + 1000 * config + stream, one stream per role; the rows of
+a role are drawn in chunks of 65,536, chunk c from PCG64 seeded with
+(seed, c), so large sets are drawn on several threads with results that do
+not depend on the thread count.
 """
 from __future__ import annotations
 
+import concurrent.futures as cf
 import dataclasses
+import os
+
 import numpy as np
 
 SEED_BASE = 240808933
@@ -83,8 +89,12 @@ WORKLOADS = {
 }
 
 
+def seed_for(cfg: int, stream: int) -> int:
+    return SEED_BASE + 1000 * cfg + stream
+
+
 def rng_for(cfg: int, stream: int) -> np.random.Generator:
-    return np.random.Generator(np.random.PCG64(SEED_BASE + 1000 * cfg + stream))
+    return np.random.Generator(np.random.PCG64(seed_for(cfg, stream)))
 
 
 def _unit_rows(a: np.ndarray) -> np.ndarray:
@@ -97,35 +107,73 @@ def _centres(rng, k, d):
     return _unit_rows(rng.standard_normal((k, d), dtype=np.float32))
 
 
-def _mixture(rng, n, centres, sigma, chunk=1 << 18):
+CHUNK = 1 << 16  # rows per independently seeded chunk
+
+
+def _chunk_rng(seed: int, c: int) -> np.random.Generator:
+    """The generator of chunk c of a role: PCG64 seeded from (seed, c), so a
+    chunk's draws do not depend on the thread that makes them or on the
+    other chunks."""
+    return np.random.Generator(np.random.PCG64(np.random.SeedSequence(entropy=seed, spawn_key=(c,))))
+
+
+def _threads() -> int:
+    return max(1, min(16, os.cpu_count() or 1))
+
+
+def _chunked(n, d, seed, fill):
+    """An n x d float32 array whose chunk c (CHUNK rows) is fill(rng_c, rows)
+    with rng_c = _chunk_rng(seed, c); chunks run on a thread pool (numpy's
+    generators and BLAS release the interpreter lock)."""
+    out = np.empty((n, d), dtype=np.float32)
+
+    def work(c):
+        s0 = c * CHUNK
+        e = min(n, s0 + CHUNK)
+        out[s0:e] = fill(_chunk_rng(seed, c), e - s0)
+
+    nchunks = (n + CHUNK - 1) // CHUNK
+    if nchunks <= 1:
+        for c in range(nchunks):
+            work(c)
+    else:
+        with cf.ThreadPoolExecutor(_threads()) as ex:
+            list(ex.map(work, range(nchunks)))
+    return out
+
+
+def _mixture(seed, n, centres, sigma):
     k, d = centres.shape
-    out = np.empty((n, d), dtype=np.float32)
     scale = np.float32(sigma)
-    for s in range(0, n, chunk):
-        e = min(n, s + chunk)
-        z = rng.integers(0, k, size=e - s)
-        g = rng.standard_normal((e - s, d), dtype=np.float32)
-        out[s:e] = centres[z] + scale * g
-    return out
+
+    def fill(rng, m):
+        z = rng.integers(0, k, size=m)
+        g = rng.standard_normal((m, d), dtype=np.float32)
+        return centres[z] + scale * g
+
+    return _chunked(n, d, seed, fill)
 
 
-def _lowrank_mixture(rng, n, basis, centres, spread, noise, chunk=1 << 17):
+def _lowrank_mixture(seed, n, basis, centres, spread, noise):
     d, r = basis.shape
-    out = np.empty((n, d), dtype=np.float32)
     inv = np.float32(1.0 / np.sqrt(r))
-    for s in range(0, n, chunk):
-        e = min(n, s + chunk)
-        z = rng.integers(0, centres.shape[0], size=e - s)
-        h = centres[z] + np.float32(spread) * rng.standard_normal((e - s, r), dtype=np.float32)
+
+    def fill(rng, m):
+        z = rng.integers(0, centres.shape[0], size=m)
+        h = centres[z] + np.float32(spread) * rng.standard_normal((m, r), dtype=np.float32)
         x = h @ basis.T
-        x += np.float32(noise) * rng.standard_normal((e - s, d), dtype=np.float32)
-        out[s:e] = x * inv
-    return out
+        x += np.float32(noise) * rng.standard_normal((m, d), dtype=np.float32)
+        return x * inv
+
+    return _chunked(n, d, seed, fill)
 
 
-def _normalize_inplace(a: np.ndarray, chunk=1 << 18):
-    for s in range(0, a.shape[0], chunk):
-        a[s:s + chunk] = _unit_rows(a[s:s + chunk])
+def _normalize_inplace(a: np.ndarray):
+    def work(s0):
+        a[s0:s0 + CHUNK] = _unit_rows(a[s0:s0 + CHUNK])
+
+    with cf.ThreadPoolExecutor(_threads()) as ex:
+        list(ex.map(work, range(0, a.shape[0], CHUNK)))
 
 
 class Generator:
@@ -164,20 +212,19 @@ class Generator:
         else:
             self.scale = np.ones(d, dtype=np.float32)
 
-    def _points(self, rng, n, centres):
+    def _points(self, seed, n, centres):
         if self.basis is not None:
-            return _lowrank_mixture(rng, n, self.basis, centres, self.w.latent_spread, self.w.ambient_noise)
-        return _mixture(rng, n, centres, self.w.sigma)
+            return _lowrank_mixture(seed, n, self.basis, centres, self.w.latent_spread, self.w.ambient_noise)
+        return _mixture(seed, n, centres, self.w.sigma)
 
     def base(self) -> np.ndarray:
-        x = self._points(rng_for(self.w.cfg, S_BASE_POINTS), self.w.n, self.base_centres)
+        x = self._points(seed_for(self.w.cfg, S_BASE_POINTS), self.w.n, self.base_centres)
         if self.w.normalize:
             _normalize_inplace(x)
         return x
 
-    def _queries(self, stream, n, rng=None):
-        rng = rng_for(self.w.cfg, stream) if rng is None else rng
-        q = self._points(rng, n, self.query_centres)
+    def _queries(self, seed, n):
+        q = self._points(seed, n, self.query_centres)
         q *= self.scale
         q += self.gap
         if self.w.normalize:
@@ -185,14 +232,14 @@ class Generator:
         return q
 
     def train(self) -> np.ndarray:
-        return self._queries(S_TRAIN, self.w.n_train)
+        return self._queries(seed_for(self.w.cfg, S_TRAIN), self.w.n_train)
 
     def test(self) -> np.ndarray:
-        return self._queries(S_TEST, self.w.n_test)
+        return self._queries(seed_for(self.w.cfg, S_TEST), self.w.n_test)
 
     def in_distribution(self, n: int) -> np.ndarray:
         """Fresh draws from the base law (ID queries), for sanity ratios."""
-        x = self._points(rng_for(self.w.cfg, S_TEST + 100), n, self.base_centres)
+        x = self._points(seed_for(self.w.cfg, S_TEST + 100), n, self.base_centres)
         if self.w.normalize:
             _normalize_inplace(x)
         return x
@@ -203,7 +250,7 @@ class Generator:
         t = np.cumsum(rng.exponential(1.0 / rate, size=n))
         k = rng.choice(np.asarray(ks, dtype=np.int32), size=n)
         L = rng.choice(np.asarray(Ls, dtype=np.int32), size=n)
-        q = self._queries(S_REQ, n, rng=rng)
+        q = self._queries(seed_for(self.w.cfg, S_REQ + 10 * seed_offset + 5), n)
         return t, q, k, L
 
 

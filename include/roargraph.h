@@ -341,6 +341,16 @@ int rg_load(const char *path, void *stream, rg_index **out);
  * Asynchronous.  Errors: RG_EINVAL, RG_EDEVICE. */
 int rg_device_copy(void *dst, const void *src, int64_t bytes, void *stream);
 
+/* rg_measure_peaks -- measured peaks of the current device, beside which
+ * the benchmark quotes its roofline fractions (the datasheet peaks stand
+ * alongside).  hbm_read_gbs: a streaming read of a 4 GiB buffer with 16-byte
+ * vector loads (best of 5, GB/s).  f16_tflops / f32_tflops: independent FP16
+ * 16x16x32 and FP32 16x16x4 MFMA instructions on register operands, 8 per
+ * wave in flight, every SIMD busy (best of 3).  Any output may be NULL.
+ * Synchronous; allocates and frees its buffers.  Errors: RG_ENOMEM,
+ * RG_EDEVICE. */
+int rg_measure_peaks(double *hbm_read_gbs, double *f16_tflops, double *f32_tflops, void *stream);
+
 void rg_free(rg_index *idx);
 const char *rg_last_error(void);
 

@@ -68,6 +68,7 @@ _SIGS = {
     "rg_knn_candidates": (i32, [P, i64, P, i64, i32, i32, P, P, P]),
     "rg_knn_candidates_f16": (i32, [P, i64, P, i64, i32, i32, P, P, P]),
     "rg_knn_last_stats": (i32, [ctypes.POINTER(i64)] * 3),
+    "rg_measure_peaks": (i32, [ctypes.POINTER(ctypes.c_double)] * 3 + [P]),
     "rg_index_build_stats": (i32, [P] + [ctypes.POINTER(ctypes.c_double)] * 4 + [ctypes.POINTER(i64)]),
     "rg_index_storage_ptrs": (i32, [P, PP, PP, PP, ctypes.POINTER(i32)]),
     "rg_save": (i32, [P, ctypes.c_char_p]),
@@ -337,6 +338,14 @@ def rg_knn_last_stats():
     a, b, c = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
     _check(lib().rg_knn_last_stats(ctypes.byref(a), ctypes.byref(b), ctypes.byref(c)))
     return {"f16": a.value, "f32": b.value, "host": c.value}
+
+
+def rg_measure_peaks(stream=None):
+    """Measured HBM read bandwidth (GB/s) and FP16 / FP32 MFMA throughput
+    (TFLOP/s) of the current device."""
+    v = [ctypes.c_double() for _ in range(3)]
+    _check(lib().rg_measure_peaks(*[ctypes.byref(x) for x in v], _stream(stream)))
+    return {"hbm_read_GBps": v[0].value, "mfma_f16_TFLOPs": v[1].value, "mfma_f32_TFLOPs": v[2].value}
 
 
 def rg_device_copy(dst, src, stream=None):

@@ -275,7 +275,7 @@ int knn_exact(const float *Qdev, int64_t nq, const float *Xdev, int64_t n, int32
         int rc = cid.alloc(sizeof(uint32_t) * (size_t)m * K);
         if (!rc) rc = csc.alloc(sizeof(float) * (size_t)m * K);
         if (rc) return rc;
-        rc = f16 ? launch_knn16_candidates(cand_q, m, cand_x, n, dp, K, cid.as<uint32_t>(), csc.as<float>(), st)
+        rc = f16 ? launch_knn16_candidates(cand_q, m, cand_x, n, d, dp, K, cid.as<uint32_t>(), csc.as<float>(), st)
                  : launch_knn_candidates(static_cast<const float *>(cand_q), m, d, static_cast<const float *>(cand_x),
                                          n, d, d, K, cid.as<uint32_t>(), csc.as<float>(), st);
         if (rc) return rc;
@@ -422,7 +422,7 @@ int rg_knn_candidates_f16(const float *queries, int64_t nq, const float *base, i
     if (!rc) rc = x16.alloc(2 * (size_t)knn16_rows(n) * dp);
     if (!rc) rc = launch_to_f16(queries, nq, d, d, q16.p, knn16_rows(nq), dp, st);
     if (!rc) rc = launch_to_f16(base, n, d, d, x16.p, knn16_rows(n), dp, st);
-    if (!rc) rc = launch_knn16_candidates(q16.p, nq, x16.p, n, dp, K, ids, scores, st);
+    if (!rc) rc = launch_knn16_candidates(q16.p, nq, x16.p, n, d, dp, K, ids, scores, st);
     return rc;
 }
 
@@ -1128,6 +1128,48 @@ int rg_device_copy(void *dst, const void *src, int64_t bytes, void *stream) {
         return RG_EINVAL;
     }
     return launch_copy_probe(dst, src, bytes, (hipStream_t)stream);
+}
+
+int rg_measure_peaks(double *hbm_read_gbs, double *f16_tflops, double *f32_tflops, void *stream) {
+    hipStream_t st = (hipStream_t)stream;
+    int dev = 0, cus = 0;
+    RG_HIP(hipGetDevice(&dev));
+    RG_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+    const int blocks = 8 * std::max(1, cus);  // 8 waves per SIMD
+    const int64_t bytes = 4ll << 30;
+    DevBuf buf, sink;
+    int rc = buf.alloc((size_t)bytes);
+    if (!rc) rc = sink.alloc(sizeof(float) * 256 * (size_t)std::max(blocks, 65536));
+    if (rc) return rc;
+    RG_HIP(hipMemsetAsync(buf.p, 1, (size_t)bytes, st));
+    hipEvent_t e0, e1;
+    RG_HIP(hipEventCreate(&e0));
+    RG_HIP(hipEventCreate(&e1));
+    auto timed = [&](auto &&launch, int reps, float *best) -> int {
+        *best = 1e30f;
+        for (int r = 0; r < reps + 1; ++r) {  // the first run warms up
+            RG_HIP(hipEventRecord(e0, st));
+            int rc2 = launch();
+            if (rc2) return rc2;
+            RG_HIP(hipEventRecord(e1, st));
+            RG_HIP(hipEventSynchronize(e1));
+            float ms = 0.f;
+            RG_HIP(hipEventElapsedTime(&ms, e0, e1));
+            if (r > 0) *best = std::min(*best, ms);
+        }
+        return RG_OK;
+    };
+    float ms = 0.f;
+    double flop = 0.0;
+    rc = timed([&]() { return launch_read_stream(buf.p, bytes, sink.p, 65536, st); }, 5, &ms);
+    if (!rc && hbm_read_gbs) *hbm_read_gbs = (double)bytes / (ms * 1e-3) / 1e9;
+    if (!rc) rc = timed([&]() { return launch_mfma_probe(0, 4096, sink.p, blocks, st, &flop); }, 3, &ms);
+    if (!rc && f16_tflops) *f16_tflops = flop / (ms * 1e-3) / 1e12;
+    if (!rc) rc = timed([&]() { return launch_mfma_probe(1, 1024, sink.p, blocks, st, &flop); }, 3, &ms);
+    if (!rc && f32_tflops) *f32_tflops = flop / (ms * 1e-3) / 1e12;
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    return rc;
 }
 
 void rg_free(rg_index *ix) {

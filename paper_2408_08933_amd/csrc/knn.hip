@@ -276,11 +276,18 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
 // a multiple of 32 coordinates and to whole tiles, so every load is in
 // bounds and unchecked.  A workgroup owns 128 query rows and sweeps 128-row
 // tiles of the base; its four wavefronts each hold a 64 x 64 quarter of the
-// tile as 4 x 4 blocks of 16 x 16 (64 accumulator registers).  Operands are
-// staged through two LDS buffers 32 coordinates at a time, rows padded to 40
-// halves (80 bytes) so that the 16 lanes of a quarter-wave read distinct
+// tile as 4 x 4 blocks of 16 x 16 (64 accumulator registers).
+//
+// At the FP16 matrix rate one 32-coordinate stage of a tile is only ~256
+// cycles of MFMA work per wavefront, far less than a load's latency, so the
+// operands go straight from global memory into a ring of NST16 LDS stages
+// (global_load_lds, no registers involved): the loads of stage s + NST16 - 1
+// are issued while stage s is multiplied.  One instruction moves a 16-row x
+// 32-coordinate block (1 KB, 16 bytes per lane, consecutive in LDS); within
+// it row j's 16-byte chunk c sits at 64 j + 16 (c ^ ((j >> 2) & 3)), so the
+// 16 lanes of a quarter-wave that read one chunk of 16 rows hit distinct
 // banks.  In an MFMA k-step lane l supplies, for row (or column) l % 16, the
-// 8 coordinates 8 * (l / 16) .. + 7 of the slice, the same coordinates for
+// 8 coordinates 8 * (l / 16) .. + 7 of the stage, the same coordinates for
 // both operands.  The filter and the per-row candidate buffers are those of
 // k_knn above.  The scores are FP32 sums of exact products of the rounded
 // inputs; how far they may be from the exact ones is bounded in the
@@ -288,11 +295,59 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
 // ---------------------------------------------------------------------------
 typedef _Float16 hx8 __attribute__((ext_vector_type(8)));
 
-constexpr int BQ16 = 128, BX16 = 128, KS16 = 32, AP16 = 40;  // AP16: LDS row pitch in halves
+constexpr int BQ16 = 128, BX16 = 128, KS16 = 32, NST16 = 4;
+constexpr int STAGE16 = (BQ16 + BX16) * KS16;  // halves per stage: A blocks, then B blocks
+
+// s_waitcnt immediates: vmcnt [3:0] and [15:14], expcnt [6:4], lgkmcnt
+// [11:8]; a field at its maximum does not wait.
+constexpr int kWaitLgkm0 = 0xC07F;                       // LDS done, memory ops may be outstanding
+__device__ __forceinline__ void wait_vm(int n) {         // at most n (0, 4 or 8) vector-memory ops outstanding
+    if (n >= 8)
+        __builtin_amdgcn_s_waitcnt(0x0F78);
+    else if (n >= 4)
+        __builtin_amdgcn_s_waitcnt(0x0F74);
+    else
+        __builtin_amdgcn_s_waitcnt(0x0F70);
+}
+
+// The LDS reads that follow the ring's loads are written as one asm block
+// each, which waits for its own results: the compiler cannot tell which ring
+// slot a global_load_lds writes and would otherwise wait for every load in
+// flight before any LDS read, emptying the ring at each stage.  The stage
+// loads are waited for by wait_vm above, before the barrier.
+__device__ __forceinline__ void lds_frags(uint32_t a_addr, uint32_t b_addr, hx8 &a0, hx8 &a1, hx8 &a2, hx8 &a3,
+                                          hx8 &b0, hx8 &b1, hx8 &b2, hx8 &b3) {
+    asm volatile(
+        "ds_read_b128 %0, %8\n\t"
+        "ds_read_b128 %1, %8 offset:1024\n\t"
+        "ds_read_b128 %2, %8 offset:2048\n\t"
+        "ds_read_b128 %3, %8 offset:3072\n\t"
+        "ds_read_b128 %4, %9\n\t"
+        "ds_read_b128 %5, %9 offset:1024\n\t"
+        "ds_read_b128 %6, %9 offset:2048\n\t"
+        "ds_read_b128 %7, %9 offset:3072\n\t"
+        "s_waitcnt lgkmcnt(0)"
+        : "=&v"(a0), "=&v"(a1), "=&v"(a2), "=&v"(a3), "=&v"(b0), "=&v"(b1), "=&v"(b2), "=&v"(b3)
+        : "v"(a_addr), "v"(b_addr)
+        : "memory");
+}
+
+__device__ __forceinline__ fx4 lds_f4(uint32_t addr) {
+    fx4 v;
+    asm volatile("ds_read_b128 %0, %1\n\ts_waitcnt lgkmcnt(0)" : "=&v"(v) : "v"(addr) : "memory");
+    return v;
+}
+
+__device__ __forceinline__ int lds_i32(uint32_t addr) {
+    int v;
+    asm volatile("ds_read_b32 %0, %1\n\ts_waitcnt lgkmcnt(0)" : "=&v"(v) : "v"(addr) : "memory");
+    return v;
+}
+
+__device__ __forceinline__ uint32_t lds_addr(const void *p) { return (uint32_t)(uintptr_t)p; }
 
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k_knn16(KnnArgs a) {
-    __shared__ __align__(16) _Float16 As[2][BQ16 * AP16];
-    __shared__ __align__(16) _Float16 Bs[2][BX16 * AP16];
+    __shared__ __align__(1024) _Float16 ring[NST16 * STAGE16];
     __shared__ __align__(16) float thr[BQ16];
     __shared__ int cnt[BQ16];
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
@@ -309,43 +364,43 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
         thr[tid] = -__builtin_inff();
         cnt[tid] = 0;
     }
+    __syncthreads();
     const int64_t xt0 = (int64_t)sp * a.xtiles_per_split;
     const int64_t xt1 = min(a.xtiles, xt0 + a.xtiles_per_split);
-    // staging: thread t moves the 16-byte chunk (t & 3) of rows (t >> 2) and
-    // (t >> 2) + 64 of both operands
-    const int lr = tid >> 2, lc = (tid & 3) * 8;
     const int nks = a.d / KS16;  // d is the padded width here
-    const _Float16 *qsrc = Qh + (q0 + lr) * (int64_t)a.ldq + lc;
-    const int64_t qstep = 64 * (int64_t)a.ldq, xstep = 64 * (int64_t)a.ldx;
-    uint4 va0, va1, vb0, vb1;
-    _Float16 *adst = &As[0][lr * AP16 + lc], *bdst = &Bs[0][lr * AP16 + lc];
-    constexpr int ABUF = BQ16 * AP16, BBUF = BX16 * AP16, P64 = 64 * AP16;
-#define KNN16_LOAD(xt_, k0_)                                                                         \
-    do {                                                                                             \
-        const _Float16 *qs_ = qsrc + (k0_);                                                          \
-        const _Float16 *xs_ = Xh + ((xt_) * BX16 + lr) * (int64_t)a.ldx + lc + (k0_);                \
-        va0 = *reinterpret_cast<const uint4 *>(qs_);                                                 \
-        va1 = *reinterpret_cast<const uint4 *>(qs_ + qstep);                                         \
-        vb0 = *reinterpret_cast<const uint4 *>(xs_);                                                 \
-        vb1 = *reinterpret_cast<const uint4 *>(xs_ + xstep);                                         \
-    } while (0)
-#define KNN16_STORE(buf_)                                                                            \
-    do {                                                                                             \
-        _Float16 *ad_ = adst + (buf_) * ABUF, *bd_ = bdst + (buf_) * BBUF;                           \
-        *reinterpret_cast<uint4 *>(ad_) = va0;                                                       \
-        *reinterpret_cast<uint4 *>(ad_ + P64) = va1;                                                 \
-        *reinterpret_cast<uint4 *>(bd_) = vb0;                                                       \
-        *reinterpret_cast<uint4 *>(bd_ + P64) = vb1;                                                 \
-    } while (0)
-    int gst = 0;
-    if (xt0 < xt1) {
-        KNN16_LOAD(xt0, 0);
-        KNN16_STORE(0);
-    }
-    __syncthreads();
-    const int fr = lane & 15, fk = (lane >> 4) * 8;
-    const _Float16 *afrag = &As[0][(wr * 64 + fr) * AP16 + fk];
-    const _Float16 *bfrag = &Bs[0][(wc * 64 + fr) * AP16 + fk];
+    const int64_t nstage = (xt1 > xt0 ? xt1 - xt0 : 0) * nks;
+    // this lane's share of a block: row j of the block, the chunk that lands
+    // in its 16 bytes
+    const int bj = lane >> 2, bc = ((lane & 3) ^ ((bj >> 2) & 3)) * 8;
+    // wave w moves blocks 2w and 2w + 1 of both operands (rows 32 w .. 32 w + 31)
+    const _Float16 *qsrc = Qh + (q0 + 32 * w + bj) * (int64_t)a.ldq + bc;
+    const _Float16 *xsrc = Xh + (32 * w + bj) * (int64_t)a.ldx + bc;
+    const int64_t q16 = 16 * (int64_t)a.ldq, x16 = 16 * (int64_t)a.ldx;
+    // the next stage to load: coordinate offset ik of the tile at xs, ring slot islot
+    int ik = 0, islot = 0;
+    const _Float16 *xs = xsrc + xt0 * BX16 * (int64_t)a.ldx;
+    const int64_t xtile = BX16 * (int64_t)a.ldx;
+    auto issue = [&]() {
+        _Float16 *dst = ring + islot * STAGE16 + 2 * w * 512;
+        __builtin_amdgcn_global_load_lds(qsrc + ik, dst, 16, 0, 0);
+        __builtin_amdgcn_global_load_lds(qsrc + ik + q16, dst + 512, 16, 0, 0);
+        __builtin_amdgcn_global_load_lds(xs + ik, dst + BQ16 * KS16, 16, 0, 0);
+        __builtin_amdgcn_global_load_lds(xs + ik + x16, dst + BQ16 * KS16 + 512, 16, 0, 0);
+        islot = islot + 1 == NST16 ? 0 : islot + 1;
+        ik += KS16;
+        if (ik == a.d) {
+            ik = 0;
+            xs += xtile;
+        }
+    };
+    for (int64_t g = 0; g < NST16 - 1 && g < nstage; ++g) issue();
+    // fragment reads: block row fr of the wave's blocks, chunk fg (k-group)
+    const int fr = lane & 15, fg = lane >> 4;
+    const int foff = fr * 32 + ((fg ^ ((fr >> 2) & 3)) * 8);
+    const uint32_t ring_a = lds_addr(ring + wr * 4 * 512 + foff);
+    const uint32_t ring_b = lds_addr(ring + BQ16 * KS16 + wc * 4 * 512 + foff);
+    int64_t g = 0;
+    int cslot = 0;  // ring slot of stage g
     for (int64_t xt = xt0; xt < xt1; ++xt) {
         const int64_t x0 = xt * BX16;
         fx4 acc[4][4];
@@ -353,35 +408,36 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
         for (int i = 0; i < 4; ++i)
 #pragma unroll
             for (int j = 0; j < 4; ++j) acc[i][j] = fx4{0.f, 0.f, 0.f, 0.f};
-        for (int ks = 0; ks < nks; ++ks, ++gst) {
-            const int buf = gst & 1;
-            const bool more = ks + 1 < nks || xt + 1 < xt1;
-            if (ks + 1 < nks)
-                KNN16_LOAD(xt, (ks + 1) * KS16);
-            else if (xt + 1 < xt1)
-                KNN16_LOAD(xt + 1, 0);
-            const _Float16 *ab = afrag + buf * ABUF, *bb = bfrag + buf * BBUF;
+        for (int ks = 0; ks < nks; ++ks, ++g) {
+            // stage g has landed once at most the later stages' loads (4 per
+            // stage) are outstanding; the barrier then also tells every wave
+            // that all waves are done with slot (g - 1) % NST16
+            wait_vm(4 * (int)min<int64_t>(NST16 - 2, nstage - 1 - g));
+            __builtin_amdgcn_s_barrier();
+            if (g + NST16 - 1 < nstage) issue();
+            const uint32_t so = (uint32_t)cslot * STAGE16 * 2;
+            cslot = cslot + 1 == NST16 ? 0 : cslot + 1;
             hx8 af[4], bf[4];
-#pragma unroll
-            for (int i = 0; i < 4; ++i) af[i] = *reinterpret_cast<const hx8 *>(ab + i * 16 * AP16);
-#pragma unroll
-            for (int j = 0; j < 4; ++j) bf[j] = *reinterpret_cast<const hx8 *>(bb + j * 16 * AP16);
+            lds_frags(ring_a + so, ring_b + so, af[0], af[1], af[2], af[3], bf[0], bf[1], bf[2], bf[3]);
 #pragma unroll
             for (int i = 0; i < 4; ++i)
 #pragma unroll
                 for (int j = 0; j < 4; ++j)
                     acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_f16(af[i], bf[j], acc[i][j], 0, 0, 0);
-            if (more) KNN16_STORE(buf ^ 1);
-            __syncthreads();
         }
-#undef KNN16_LOAD
-#undef KNN16_STORE
         // filter: accumulator element r of block (i, j) is query row
         // 16 i + 4 (lane / 16) + r of the wave's half, base column lane % 16
+        bool stored = false;
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
             const int rb = wr * 64 + i * 16 + 4 * (lane >> 4);
-            const fx4 t4 = *reinterpret_cast<const fx4 *>(&thr[rb]);
+            const fx4 t4 = lds_f4(lds_addr(&thr[rb]));
+            bool hit = false;
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+#pragma unroll
+                for (int j = 0; j < 4; ++j) hit |= acc[i][j][r] >= t4[r];
+            if (!__builtin_amdgcn_ballot_w64(hit)) continue;
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
                 const int row = rb + r;
@@ -394,24 +450,38 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
                         const int pos = atomicAdd(&cnt[row], 1);
                         bsc[(int64_t)row * CAP + pos] = sc;
                         bid[(int64_t)row * CAP + pos] = (uint32_t)gx;
+                        stored = true;
                     }
                 }
             }
         }
-        __syncthreads();
-        for (int row = w; row < BQ16; row += 4) {
-            const int c = cnt[row];
-            if (c > CAP - BX16) {
-                float t = thr[row];
-                const int nc = compact_row(bsc + (int64_t)row * CAP, bid + (int64_t)row * CAP, c, a.K, t);
-                if (lane == 0) {
-                    cnt[row] = nc;
-                    thr[row] = t;
-                }
+        __builtin_amdgcn_s_waitcnt(kWaitLgkm0);
+        __builtin_amdgcn_s_barrier();
+        // rows w, w + 4, ..: lane l < 32 looks at row w + 4 l; compaction of a
+        // row whose buffer could overflow on the next tile (rare)
+        const int myc = lane < BQ16 / 4 ? lds_i32(lds_addr(&cnt[w + 4 * lane])) : 0;
+        uint64_t full = __builtin_amdgcn_ballot_w64(myc > CAP - BX16);
+        while (full) {
+            const int l = __builtin_ctzll(full);
+            full &= full - 1;
+            const int row = w + 4 * l;
+            float t = thr[row];
+            const int nc = compact_row(bsc + (int64_t)row * CAP, bid + (int64_t)row * CAP, cnt[row], a.K, t);
+            stored = true;
+            if (lane == 0) {
+                cnt[row] = nc;
+                thr[row] = t;
             }
         }
-        __syncthreads();
+        // the candidate stores count in the same counter as the stage
+        // loads; drain them so the waits above keep their meaning.  The
+        // kernel issues no other vector-memory operation (no register
+        // spills; the build checks that it uses no scratch)
+        if (__builtin_amdgcn_ballot_w64(stored)) __builtin_amdgcn_s_waitcnt(0x0F70);
+        __builtin_amdgcn_s_waitcnt(kWaitLgkm0);
+        __builtin_amdgcn_s_barrier();
     }
+    __syncthreads();
     for (int row = w; row < BQ16; row += 4) {
         const int64_t gq = q0 + row;
         if (gq >= a.nq) continue;
@@ -571,7 +641,7 @@ namespace {
 // workgroup and base rows per tile, and the byte size of a row element.
 struct KnnKernel {
     void (*fn)(KnnArgs);
-    int bq, bx;
+    int bq, bx, threads;
     size_t elem;
 };
 
@@ -633,7 +703,7 @@ int knn_range(const KnnKernel &kk, const void *Q, int64_t nq, int32_t ldq, const
     for (int64_t t0 = 0; t0 < qtiles; t0 += tiles_per_launch) {
         a.q_tile0 = t0;
         const int64_t nt = std::min(tiles_per_launch, qtiles - t0);
-        hipLaunchKernelGGL(kk.fn, dim3((unsigned)nt, (unsigned)splits), dim3(256), 0, stream, a);
+        hipLaunchKernelGGL(kk.fn, dim3((unsigned)nt, (unsigned)splits), dim3(kk.threads), 0, stream, a);
         if (hipGetLastError() != hipSuccess) {
             cleanup();
             set_error("knn: kernel launch failed");
@@ -672,7 +742,7 @@ int knn_series(const KnnKernel &kk, const void *Q, int64_t nq, int32_t ldq, cons
     int per_cu = 0, cus = 0, dev = 0;
     RG_HIP(hipGetDevice(&dev));
     RG_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
-    RG_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kk.fn, 256, 0));
+    RG_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kk.fn, kk.threads, 0));
     const int64_t resident = (int64_t)std::max(1, per_cu) * std::max(1, cus);
     const int64_t qtiles = (nq + kk.bq - 1) / kk.bq;
     const int64_t rem = qtiles % resident;
@@ -695,7 +765,7 @@ int launch_knn_candidates(const float *Q, int64_t nq, int32_t ldq, const float *
         set_error("knn: K must be in [1, 256]");
         return RG_EINVAL;
     }
-    const KnnKernel kk{k_knn, BQ, BX, sizeof(float)};
+    const KnnKernel kk{k_knn, BQ, BX, 256, sizeof(float)};
     const bool vq = (ldq % 4 == 0) && ((uintptr_t)Q % 16 == 0);
     const bool vx = (ldx % 4 == 0) && ((uintptr_t)X % 16 == 0);
     return knn_series(kk, Q, nq, ldq, X, n, ldx, d, K, ids, scores, vq, vx, stream);
@@ -716,13 +786,13 @@ int launch_to_f16(const float *src, int64_t rows, int32_t d, int64_t ld, void *d
     return RG_OK;
 }
 
-int launch_knn16_candidates(const void *Q16, int64_t nq, const void *X16, int64_t n, int32_t dp, int32_t K,
-                            uint32_t *ids, float *scores, hipStream_t stream) {
-    if (K < 1 || K > CAP - BX16 || K > CAP / 2 || dp % KS16 != 0) {
+int launch_knn16_candidates(const void *Q16, int64_t nq, const void *X16, int64_t n, int32_t d, int32_t dp,
+                            int32_t K, uint32_t *ids, float *scores, hipStream_t stream) {
+    if (K < 1 || K > CAP - BX16 || K > CAP / 2 || dp % KS16 != 0 || d < 1 || d > dp) {
         set_error("knn16: K must be in [1, 256] and the width a multiple of 32");
         return RG_EINVAL;
     }
-    const KnnKernel kk{k_knn16, BQ16, BX16, sizeof(_Float16)};
+    const KnnKernel kk{k_knn16, BQ16, BX16, 256, sizeof(_Float16)};
     return knn_series(kk, Q16, nq, dp, X16, n, dp, dp, K, ids, scores, true, true, stream);
 }
 

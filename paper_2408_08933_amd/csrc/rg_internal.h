@@ -112,14 +112,18 @@ int launch_serve_admit(int32_t n, const int32_t *slots, const float *q, const in
 int launch_knn_candidates(const float *Q, int64_t nq, int32_t ldq, const float *X, int64_t n,
                           int32_t ldx, int32_t d, int32_t K, uint32_t *ids, float *scores,
                           hipStream_t stream);
+// peaks.hip: probes of the device's read bandwidth and matrix throughput
+int launch_read_stream(const void *src, int64_t bytes, void *sink, int blocks, hipStream_t stream);
+int launch_mfma_probe(int kind, int iters, void *sink, int blocks, hipStream_t stream, double *flop);
+
 // The same from FP16 rows (round to nearest even): Q16 and X16 hold
 // knn16_rows(rows) rows of knn16_width(d) halves, zero padded.
 int64_t knn16_rows(int64_t rows);
 int32_t knn16_width(int32_t d);
 int launch_to_f16(const float *src, int64_t rows, int32_t d, int64_t ld, void *dst, int64_t rows_pad, int32_t dp,
                   hipStream_t stream);
-int launch_knn16_candidates(const void *Q16, int64_t nq, const void *X16, int64_t n, int32_t dp, int32_t K,
-                            uint32_t *ids, float *scores, hipStream_t stream);
+int launch_knn16_candidates(const void *Q16, int64_t nq, const void *X16, int64_t n, int32_t d, int32_t dp,
+                            int32_t K, uint32_t *ids, float *scores, hipStream_t stream);
 // Canonical FP64 rescoring, sort and certification of m rows of K
 // candidates (see knn.hip); ok[i] = 1 where row i's k results are exact.
 // A candidate score errs by at most gsum |t| xmax + eta (|t| + xmax) + abs0.
