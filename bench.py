@@ -251,22 +251,63 @@ def measured_traffic(L, k, nq, ms_launch):
     return b / (ms_launch * 1e-3) / 1e9, b
 
 
-def cpu_baseline(X, off, idx, entry, Qh, k, L, seconds):
+def cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def _oracle_search_rate(X, off, idx, entry, Qh, k, L, seconds, threads):
+    """Queries per second of the FP64 oracle search on `threads` OpenMP
+    threads, over the test queries cycled, for about `seconds` of work."""
     import oracle
-    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    oracle.set_threads(threads)
     n_done, t = 0, 0.0
-    batch = 64
+    batch = 8 * threads
     while t < seconds:
         s0 = n_done % len(Qh)
         q = Qh[s0:s0 + batch]
         t0 = time.perf_counter()
-        oracle.search(X, off, idx, entry, q, k, L)
+        oracle.search(X, off, idx, entry, q, k, L, with_margins=False)
         t += time.perf_counter() - t0
         n_done += len(q)
         batch = min(batch * 2, 2048)
-    return {"value": n_done / t, "unit": "queries/s", "cores": threads, "kind": "oracle",
+    return n_done / t, n_done, t
+
+
+def cpu_baseline(X, off, idx, entry, Qh, k, L, seconds):
+    """The oracle timed on this host: its search on the same graph and test
+    queries at the operating L, on all host threads and on one thread (the
+    paper's search protocol, Sec. 5.1), and its whole build of the tiny
+    workload split into the kNN preprocessing and the rest (Sec. 5.7)."""
+    import datagen
+    import oracle
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    qps, n_done, t = _oracle_search_rate(X, off, idx, entry, Qh, k, L, seconds, threads)
+    qps1, n1, t1 = _oracle_search_rate(X, off, idx, entry, Qh, k, L, seconds / 3, 1)
+    oracle.set_threads(threads)
+    g = datagen.Generator(1)
+    X1, T1 = g.base(), g.train()
+    t0 = time.perf_counter()
+    oracle.knn(X1, T1, 32)
+    t_knn = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    oracle.Graph(X1, T1, 32, 32, 500)
+    t_build = time.perf_counter() - t0
+    return {"value": qps, "unit": "queries/s", "cores": threads, "kind": "oracle",
             "sample": f"{n_done} searches over the {len(Qh)} test queries (cycled), same graph, L={L}, k={k}; "
-                      f"FP64 oracle search, OpenMP over queries ({threads} threads), {t:.1f} s"}
+                      f"FP64 oracle search, OpenMP over queries ({threads} threads), {t:.1f} s",
+            "cpu_model": cpu_model(),
+            "single_thread": {"value": qps1, "unit": "queries/s", "cores": 1,
+                              "sample": f"{n1} searches, one thread, {t1:.1f} s"},
+            "build_tiny": {"workload": "tiny-ood-d64 (10k x 64, 10k training queries, Nq=32, M=32, L_build=500)",
+                           "threads": threads, "knn_s": t_knn, "total_s": t_build,
+                           "rest_s": max(0.0, t_build - t_knn),
+                           "note": "the oracle build recomputes the kNN inside; rest = total - kNN"}}
 
 
 ABL_GRID = [10, 20, 40, 60, 100, 150, 200, 300, 400, 500]

@@ -84,7 +84,7 @@ enum { RG_STAGE_PROJECTED = 1, RG_STAGE_BIPARTITE = 2 };
  *   M      bound on every node's final out-degree (>= 3); projection and
  *          enhancement use m_pj + m_ce <= M - 1 and one slot per node is left
  *          for the reachability repair.
- * The Nq-NN lists come from the GPU kNN (rg_knn semantics: FP32 MFMA
+ * The Nq-NN lists come from the GPU kNN (rg_knn semantics: FP16 or FP32 MFMA
  * candidates, exact FP64 rerank with a certified margin); the graph steps run
  * on host threads with the canonical FP64 distance (sum of exact products in
  * increasing coordinate order).  The result is deterministic and independent
@@ -187,16 +187,25 @@ int rg_index_bipartite(const rg_index *idx, const int64_t **bridge_offsets, cons
  *   - the sub-bipartite graph N_out(q) u {q, v} is projected with v as pivot
  *     (Algorithm 2 for one pivot: candidates N_out(q) by (delta(v, .), id), at
  *     most L, AcquireNeighbors with fill to m_pj); the selection is v's row;
- *   - each selected p gains the edge p -> v while its row has fewer than M
- *     entries; if none does, v gets one in-edge by the build's repair rule
- *     (first queue node with a free slot, else the first in BFS order);
+ *   - each selected p takes v through Algorithm 2's reverse step on its whole
+ *     row in the index: row(p) <- AcquireNeighbors(p, row(p) u {v}, M, with
+ *     fill).  A row with room simply gains v; a full row keeps M entries by
+ *     the selection rule, which may drop v or one of its old neighbours.  If
+ *     no p keeps v, v gets one in-edge by the build's repair rule (the first
+ *     queue node with a free slot, else the first in BFS order);
  *   - v is appended to N_out(q).  With no joined node in the queue, v's
  *     candidates are its queue and no N_out changes.
- * Out-degrees stay <= M and every node stays reachable from the entry.  The
- * device copies (rows, adjacency, tombstones, the chosen storage form) are
- * remade.  Deterministic.  Not concurrent with other calls on the index.
+ * At the end of the call every node the entry no longer reaches (an old
+ * node can lose its last in-edge to a full row's selection) gets one
+ * in-edge, in ascending id, from the first node in BFS order with a free
+ * slot.  Out-degrees stay <= M and every node stays reachable from the
+ * entry.  The device copies (rows, adjacency, tombstones, the chosen storage
+ * form) are remade.  Deterministic.  Not concurrent with other calls on the
+ * index.  Every argument is checked before anything changes (non-finite
+ * values are rejected); a failure after that leaves the index with its
+ * previous rows, graph and storage form.
  * Errors: RG_EINVAL (no kept stages or training queries, L > 512, graph held
- * as CSR), RG_ENOMEM, RG_EDEVICE, RG_EINTERNAL.
+ * as CSR, a value that is not finite), RG_ENOMEM, RG_EDEVICE, RG_EINTERNAL.
  */
 int rg_insert(rg_index *idx, const float *vectors, int64_t nv, int32_t L, void *stream);
 
@@ -303,6 +312,27 @@ int rg_knn_candidates_f16(const float *queries, int64_t nq, const float *base, i
 int rg_knn_last_stats(int64_t *rows_f16, int64_t *rows_f32, int64_t *rows_host);
 
 /*
+ * rg_search_noalloc -- rg_search for callers that cannot allocate device
+ * memory: code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc.  It calls no hipMalloc, hipFree or allocating library
+ * routine.  It always runs the persistent search with its exact visited
+ * bitmaps, kept in a file-scope device array of 256 MiB that each device
+ * the library runs on holds until the process ends (the work counter, then
+ * one bitmap of ceil(n / 32) words, rounded up to 64, per resident
+ * workgroup); the grid shrinks to the bitmaps that fit.  Arguments, layout
+ * and results are those of rg_search (the same ids and distances; hops and
+ * evals are the exact counts).  The index's device must be the current
+ * device.  Every call on a device shares that device's array and leaves it
+ * dirty: calls that overlap on one device race and must be serialized by
+ * the caller (one stream, or events).  Asynchronous, like rg_search.
+ * Errors: RG_EINVAL (as rg_search; an index whose single bitmap exceeds
+ * the array, n > about 2^31 rows; a device other than the index's),
+ * RG_EDEVICE.
+ */
+int rg_search_noalloc(const rg_index *idx, const float *queries, int64_t nq, int32_t k, int32_t L,
+                      uint32_t *ids, float *dists, uint32_t *hops, uint32_t *evals, void *stream);
+
+/*
  * rg_search_hashbits -- rg_search with the LDS visited table fixed at
  * 2^hash_bits entries (8..15, and at least twice the ELL row width).  The
  * table only bounds work (a cleared table makes nodes be scored again), so
@@ -313,7 +343,7 @@ int rg_search_hashbits(const rg_index *idx, const float *queries, int64_t nq, in
                        void *stream);
 
 /* rg_index_build_stats -- wall seconds of the build's kNN preprocessing
- * (Sec. 5.6 reports it as the dominant share), projection, enhancement and
+ * (Sec. 5.7 reports it as the dominant share), projection, enhancement and
  * total, and the number of repair edges.  Any output may be NULL. */
 int rg_index_build_stats(const rg_index *idx, double *t_knn, double *t_project, double *t_enhance,
                          double *t_total, int64_t *repairs);

@@ -60,6 +60,7 @@ def _load():
         "or_recall": (f64, [P, i32, P, i32, i64, i32]),
         "or_build": (P, [P, i64, i32, P, i64, i32, i32, i32, i32, i32]),
         "or_repair": (i64, [i64, i32, u32, P, P, P, P, i64]),
+        "or_set_threads": (None, [i32]),
         "or_graph_n": (i64, [P]),
         "or_graph_entry": (u32, [P]),
         "or_graph_repairs": (i64, [P]),
@@ -141,7 +142,12 @@ def acquire(X, x, C, m, fill):
     return res[:n].copy()
 
 
-def search(X, offsets, indices, entry, Q, k, L, with_stats=True):
+def set_threads(n: int) -> None:
+    """OpenMP threads of the oracle's parallel loops (0: the default)."""
+    _load().or_set_threads(int(n))
+
+
+def search(X, offsets, indices, entry, Q, k, L, with_stats=True, with_margins=True):
     """Beam search; returns ids, FP64 distances, hops, evals and each query's
     decision margin: the smallest (delta_b - delta_a) / (S_a + S_b), with
     S = sum_i |q_i x_i|, over the pairs whose order decides the search."""
@@ -155,9 +161,9 @@ def search(X, offsets, indices, entry, Q, k, L, with_stats=True):
     ds = np.empty((nq, k), np.float64)
     hops = np.empty(nq, np.uint32)
     ev = np.empty(nq, np.uint32)
-    gaps = np.empty(nq, np.float64)
+    gaps = np.full(nq, np.nan)
     _load().or_search(_p(X), X.shape[0], X.shape[1], _p(off), _p(idx), int(entry), _p(Q), nq,
-                      int(k), int(L), _p(ids), _p(ds), _p(hops), _p(ev), _p(gaps))
+                      int(k), int(L), _p(ids), _p(ds), _p(hops), _p(ev), _p(gaps) if with_margins else None)
     return ids, ds, hops, ev, gaps
 
 

@@ -41,6 +41,18 @@
 
 #define OR_NONE 0xFFFFFFFFu
 
+/* OpenMP threads of the parallel loops (queries of a search batch, rows of */
+/* the kNN, enhancement searches); 0 keeps the runtime's default.           */
+void or_set_threads(int32_t n)
+{
+#ifdef _OPENMP
+    if (n > 0)
+        omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+}
+
 /* ------------------------------------------------------------------------ */
 /* Distance (Def. 1; inner product as in Sec. 5.1).                          */
 /* ------------------------------------------------------------------------ */
