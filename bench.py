@@ -1,16 +1,20 @@
 #!/usr/bin/env python3
 """Benchmark: QPS at recall@10 = 0.90 of the RoarGraph beam search on one MI355X.
 
-Workload (default): the text-to-image-like configuration -- d = 200 inner
-product (unnormalised), 1M base vectors from a 256-centre Gaussian mixture,
-1M training queries and 10k test queries from a shifted 256-centre mixture
-(gap norm 1.5, per-dimension query scale U[0.5, 1.5]); index built with
-Nq = 100, M = 64, L_build = 500.  Synthetic, seeded (datagen).
+Workload (default, --config 4): the serving configuration -- d = 200 inner
+product (unnormalised), 10M base vectors (8 GB FP32) from a 1024-centre
+mixture, the index built from 10M training queries (|T| = |X|) of a shifted
+1024-centre mixture (gap norm 1.5, per-dimension query scale U[0.5, 1.5]),
+10k test queries of the same law; Nq = 100, M = 64, L_build = 500.  Seeded,
+synthetic (datagen).
 
-One step = one rg_search call over all 10k test queries at the smallest L
-of the sweep whose mean recall@10 reaches 0.90 (ground truth from the exact
-rg_knn).  Inputs are resident in HBM before timing starts.  Prints ONE JSON
-line on stdout; progress goes to stderr.
+One step = one rg_search call over all 10k test queries, FP32 rows, at the
+smallest L of the sweep whose mean recall@10 reaches 0.90 (ground truth from
+the exact rg_knn); inputs are resident in HBM before timing starts.  The same
+is measured for BF16 and FP8 rows with the FP32 rerank, then each form
+serves a Poisson stream of mixed (k, L) requests at three rates (p50/p99
+overall and per class).  Prints ONE JSON line on stdout; progress (including
+the build's, by default) goes to stderr.
 """
 from __future__ import annotations
 
@@ -104,8 +108,16 @@ def time_search(rg, torch, ix, Q, k, L, steps, warmup):
 
 def algorithmic_bytes(rg, torch, ix, Q, k, L, d, bytes_per_row, avg_deg):
     """Per-query bytes the method must move: every distinct visited row, every
-    expanded node's adjacency row (ids + offsets), the query, the results."""
-    _, _, hops, ev = rg.rg_search(ix, Q, k, L, stats=True, hash_bits=15)
+    expanded node's adjacency row (ids + offsets), the query, the results.
+    The rows are counted by the persistent search's exact visited bitmap
+    (rg_search_noalloc), so rows an LDS table forgot and scored again are not
+    counted."""
+    nq = Q.shape[0]
+    ids = torch.empty((nq, k), dtype=torch.int32, device=Q.device)
+    ds = torch.empty((nq, k), dtype=torch.float32, device=Q.device)
+    hops = torch.empty(nq, dtype=torch.int32, device=Q.device)
+    ev = torch.empty(nq, dtype=torch.int32, device=Q.device)
+    rg.rg_search_noalloc_into(ix, Q, k, L, ids, ds, hops, ev)
     torch.cuda.synchronize()
     V = ev.cpu().numpy().astype(np.float64)
     H = hops.cpu().numpy().astype(np.float64)
@@ -142,18 +154,28 @@ def serve_run(rg, ix, Qh, gt, n_req, rate, seed=0, timeout=120.0):
     wall = srv.now() - t0
     st = srv.stats()
     srv.close()
-    lat = np.array([r["t_done"] - r["t_submit"] for r in done.values()])
+    tags = np.fromiter(done.keys(), dtype=np.int64)
+    lat = np.array([done[t]["t_done"] - done[t]["t_submit"] for t in tags])
     hit = tot = 0
     for tag, r in done.items():
         kk = int(ks[tag])
         hit += len(np.intersect1d(r["ids"][:kk], gt[tag % len(Qh), :kk]))
         tot += kk
+    # latency per (k, L) class of the mix
+    classes = {}
+    for kk in (1, 10, 100):
+        for LL in (32, 128, 512):
+            sel = (ks[tags] == kk) & (Ls[tags] == LL)
+            if sel.any():
+                classes[f"k{kk}_L{LL}"] = {"requests": int(sel.sum()),
+                                            "p50_ms": float(np.percentile(lat[sel], 50) * 1e3),
+                                            "p99_ms": float(np.percentile(lat[sel], 99) * 1e3)}
     return {"requests": len(done), "offered_qps": rate, "achieved_qps": len(done) / wall,
             "p50_ms": float(np.percentile(lat, 50) * 1e3), "p99_ms": float(np.percentile(lat, 99) * 1e3),
-            "recall": hit / max(tot, 1), "steps": st["steps"]}
+            "recall": hit / max(tot, 1), "steps": st["steps"], "per_class": classes}
 
 
-def serve_latency(rg, ix, Qh, gt, n_req=100000):
+def serve_latency(rg, ix, Qh, gt, n_req=200000):
     """Closed-loop capacity, then Poisson arrivals at 0.5, 0.8, 0.95 of it
     (after a short unmeasured run: a process's first serving run is slower)."""
     serve_run(rg, ix, Qh, gt, 5000, None, seed=3)
@@ -236,11 +258,12 @@ def search_sources_sha() -> str:
     return h.hexdigest()[:16]
 
 
-def measured_traffic(L, k, nq, ms_launch):
-    """HBM bytes per launch from the committed counter passes (FETCH_SIZE +
-    WRITE_SIZE, calibrated with a plain copy), as GB/s over this run's launch
-    time; None when the kernel sources or the operating point changed."""
-    path = os.path.join(ROOT, "profiles", "k_search_persistent_fp32_t2i-like-d200.traffic.txt")
+def measured_traffic(workload, L, k, nq, ms_launch):
+    """HBM bytes per launch of the FP32 search from the committed counter
+    passes (FETCH_SIZE + WRITE_SIZE, calibrated with a plain copy), as GB/s
+    over this run's launch time; None when the kernel sources or the
+    operating point differ from the profiled ones."""
+    path = os.path.join(ROOT, "profiles", f"search_fp32_{workload}.traffic.txt")
     if not os.path.exists(path):
         return None, None
     kv = dict(line.strip().split("=", 1) for line in open(path) if "=" in line)
@@ -396,128 +419,57 @@ def ablation(rg, torch, dev, n):
     return out
 
 
-# Storage forms measured per workload: the configuration's own form next to
-# plain FP32 (the 10M x 200 serving workload is plain FP32; the reduced forms
-# are added there for comparison).
-WORKLOAD_FORMS = {3: ("fp32", "bf16"), 4: ("fp32", "bf16", "fp8"), 5: ("fp32", "fp8")}
-
-
-def workload_run(rg, torch, dev, wid, train_frac, steps, serve_req):
-    """The method end to end on another workload shape (not the headline
-    line): build from |T| = train_frac |X| training queries, graph checks,
-    then per storage form QPS at recall@10 = 0.90 (and recall@100 for the
-    CLIP-like shape, which asks for k = 100), the recall of the reduced form
-    at the FP32 operating L, distance errors against FP64 and serving
-    latency at three Poisson rates."""
-    import datagen
-    w = datagen.WORKLOADS[wid]
-    nt = int(round(train_frac * w.n_train))
-    g = datagen.Generator(wid, n=w.n, n_train=nt, n_test=w.n_test)
-    log(f"workload {w.name}: n={w.n} d={w.d} train={nt} test={w.n_test} Nq={w.Nq} M={w.M}")
-    t = time.time()
-    Xh, Th, Qh = g.base(), g.train(), g.test()
-    log(f"data generated in {time.time() - t:.1f} s")
-    X = torch.from_numpy(Xh).to(dev)
-    Q = torch.from_numpy(Qh).to(dev)
-    Tr = torch.from_numpy(Th).to(dev)
-    del Th
-    t = time.time()
-    ix = rg.rg_build(X, Tr, w.Nq, w.M, L_build=500)
-    torch.cuda.synchronize()
-    bstats = ix.build_stats()
-    bstats["wall_s"] = time.time() - t
-    del Tr
-    torch.cuda.empty_cache()
-    log(f"build: {bstats}")
-    off, idx, entry = ix.graph()
-    bstats["checks"] = graph_checks(off, idx, entry, w.M)
-    log(f"graph checks: {bstats['checks']}")
-    avg_deg = float(np.diff(off).mean())
-    del off, idx
-    gt100 = rg.as_u32(rg.rg_knn(Q, X, 100)[0])
-    info = ix.info()
+def graph_stage(rg, torch, ix, Q, k, L, gt, steps, warmup, d, bytes_per_row, avg_deg, rerank_bytes):
+    """Timed searches of one storage form at one L: QPS, per-launch times and
+    the algorithmic bytes per launch (plus the FP32 rerank for reduced rows)."""
     nq = Q.shape[0]
-    out = {"workload": w.name, "n_base": w.n, "d": w.d, "n_train": nt, "n_test": int(nq), "Nq": w.Nq, "M": w.M,
-           "L_build": 500, "metric_space": "cosine" if w.normalize else "inner product", "build": bstats,
-           "forms": {}, "data": "synthetic"}
-    L32 = {}
-    for name in WORKLOAD_FORMS[wid]:
-        st = {"fp32": rg.RG_STORE_FP32, "bf16": rg.RG_STORE_BF16, "fp8": rg.RG_STORE_FP8E4M3}[name]
-        rg.rg_index_set_storage(ix, st)
-        f = {}
-        for k, grid in ((10, L_GRID), (100, [L for L in L_GRID if L >= 100])):
-            if k == 100 and wid != 3:
-                continue
-            log(f"{name} sweep, k={k}")
-            L, curve = sweep(rg, torch, ix, Q, gt100[:, :k], k, grid, 0.90)
-            if L is None:
-                L = grid[-1]
-            wall, lm = time_search(rg, torch, ix, Q, k, L, steps, 2)
-            bpr = {"fp32": 4.0 * w.d, "bf16": 2.0 * w.d, "fp8": w.d + 4.0}[name]
-            b, vm, hm = algorithmic_bytes(rg, torch, ix, Q, k, L, w.d, bpr, avg_deg)
-            if name != "fp32":
-                b += nq * max(L, k) * 4.0 * w.d   # the FP32 rerank of the final queue
-            f[f"k{k}"] = {"L": L, f"recall_at_{k}": dict(curve)[L], "qps": nq * steps / wall,
-                          "ms_per_launch": float(np.mean(lm)), "mean_visits": vm, "mean_hops": hm,
-                          "algorithmic_GBps": b / (np.mean(lm) * 1e-3) / 1e9,
-                          "curve": [[a, b] for a, b in curve]}
-            if name == "fp32":
-                L32[k] = L
-                # the LDS visited table in place of the HBM bitmap, at the same L
-                # (the bitmap costs n/8 bytes per query to clear)
-                f[f"k{k}"]["lds_table_ms_per_launch"] = {}
-                for hb in (10, 11):
-                    rg.rg_search(ix, Q, k, L, hash_bits=hb)
-                    torch.cuda.synchronize()
-                    t0 = time.perf_counter()
-                    for _ in range(steps):
-                        rg.rg_search(ix, Q, k, L, hash_bits=hb)
-                    torch.cuda.synchronize()
-                    f[f"k{k}"]["lds_table_ms_per_launch"][hb] = (time.perf_counter() - t0) / steps * 1e3
-            else:
-                ids, _ = rg.rg_search(ix, Q, k, L32[k])
-                torch.cuda.synchronize()
-                f[f"k{k}"]["recall_at_fp32_L"] = {"L": L32[k], "recall": recall_at(rg.as_u32(ids), gt100, k)}
-            log(f"  {name} k={k}: {f[f'k{k}']}")
-        ids, ds = rg.rg_search(ix, Q, 10, f["k10"]["L"])
-        torch.cuda.synchronize()
-        rows = None if st == rg.RG_STORE_FP32 else storage_rows(rg, ix, st, w.n, w.d, info["pitch"])
-        f["dist_err_vs_fp64"] = distance_errors(Xh, Qh, rg.as_u32(ids), ds.cpu().numpy(), rows=rows)
-        del rows
-        log(f"  {name} distance error: {f['dist_err_vs_fp64']}")
-        if wid in (4, 5) and serve_req:
-            log(f"serving {name}")
-            f["serving"] = serve_latency(rg, ix, Qh, gt100, n_req=serve_req)
-        out["forms"][name] = f
-    rg.rg_index_set_storage(ix, rg.RG_STORE_FP32)
-    base = out["forms"]["fp32"]["k10"]["qps"]
-    for name, f in out["forms"].items():
-        f["qps_vs_fp32_at_recall_0.90"] = f["k10"]["qps"] / base
-    return out
+    wall, lm = time_search(rg, torch, ix, Q, k, L, steps, warmup)
+    b, vm, hm = algorithmic_bytes(rg, torch, ix, Q, k, L, d, bytes_per_row, avg_deg)
+    b += rerank_bytes
+    ms = float(np.mean(lm))
+    return {"qps": nq * steps / wall, "wall_s": wall, "ms_per_launch": ms, "bytes_per_launch": b,
+            "algorithmic_GBps": b / (ms * 1e-3) / 1e9, "mean_visits": vm, "mean_hops": hm}
+
+
+def search_kernel_name(n, d, L, k, storage):
+    """The kernel rg_search runs for this index and call (the library's rule:
+    the persistent kernel with its exact bitmap for FP32 rows while n / 8
+    bytes stay under 5% of 40 L_eff rows of 4 d bytes, else the LDS-table
+    kernel; the LDS-table kernel for BF16 and FP8 rows)."""
+    if storage == "fp32" and n / 8.0 <= 0.05 * 40.0 * max(L, k) * 4.0 * d:
+        return "k_search_persistent (FP32 rows, exact HBM visited bitmap)"
+    return f"k_search ({storage.upper()} rows, LDS visited table)"
 
 
 def main():
+    t_start = time.time()
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--config", type=int, choices=(2, 3, 4, 5), default=4,
+                    help="workload: 2 = 1M x 200 text-to-image-like, 3 = 2M x 512 CLIP-like, "
+                         "4 = 10M x 200 serving (the default), 5 = 8M x 512 FP8 serving")
+    ap.add_argument("--train-frac", type=float, default=1.0, help="|T| / |X| (the configurations: 1)")
+    ap.add_argument("--n", type=int, default=None, help="override base/training size (not the headline)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--serve-requests", type=int, default=200000, help="requests per serving run")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-precision", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
-    ap.add_argument("--n", type=int, default=None, help="override base/training size (not the headline)")
+    ap.add_argument("--time-budget", type=float, default=540.0,
+                    help="seconds from start after which optional parts (serving, reduced forms, CPU baseline) "
+                         "are skipped and reported as such")
+    ap.add_argument("--save-index", default=None, help="write the index, test queries and L to this prefix")
     ap.add_argument("--copy-probe", action="store_true", help="run a 1 GiB plain copy kernel (traffic calibration)")
     ap.add_argument("--ablation", action="store_true",
                     help="instead of the benchmark: G_bi / G_pj / RoarGraph, |T| = 0.1/0.5/1 |X|, ID queries")
-    ap.add_argument("--workload", type=int, choices=(3, 4, 5), default=None,
-                    help="instead of the benchmark: the method end to end on the CLIP-like 2M x 512 (3), "
-                         "10M x 200 serving (4) or 8M x 512 FP8 serving (5) shape")
-    ap.add_argument("--train-frac", type=float, default=1.0, help="|T| / |X| for --workload")
-    ap.add_argument("--serve-requests", type=int, default=100000, help="requests per serving run (--workload)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on exactly one GPU; --gpus N > 1 is not supported", file=sys.stderr)
         sys.exit(2)
+    # build progress on stderr by default, so no phase of a long build is silent
+    os.environ.setdefault("RG_LOG", "1")
 
     import torch
 
@@ -526,17 +478,16 @@ def main():
 
     rg.lib()
     dev = torch.device("cuda:0")
-    w = datagen.WORKLOADS[2]
     if args.ablation:
+        w = datagen.WORKLOADS[2]
         print(json.dumps({"ablation": ablation(rg, torch, dev, args.n or w.n)}), flush=True)
         return
-    if args.workload:
-        r = workload_run(rg, torch, dev, args.workload, args.train_frac, 10, args.serve_requests)
-        print(json.dumps({"workload_run": r}), flush=True)
-        return
+    left = lambda: args.time_budget - (time.time() - t_start)  # noqa: E731
+    w = datagen.WORKLOADS[args.config]
     n = args.n or w.n
-    g = datagen.Generator(2, n=n, n_train=n, n_test=w.n_test)
-    log(f"workload {w.name}: n={n} d={w.d} train={n} test={w.n_test} Nq={w.Nq} M={w.M}")
+    nt = int(round(args.train_frac * (args.n or w.n_train)))
+    g = datagen.Generator(args.config, n=n, n_train=nt, n_test=w.n_test)
+    log(f"workload {w.name}: n={n} d={w.d} train={nt} test={w.n_test} Nq={w.Nq} M={w.M}")
     t = time.time()
     Xh, Th, Qh = g.base(), g.train(), g.test()
     log(f"data generated in {time.time() - t:.1f} s")
@@ -549,8 +500,10 @@ def main():
     torch.cuda.synchronize()
     bstats = ix.build_stats()
     bstats["wall_s"] = time.time() - t
+    bstats["knn_rows_certified"] = rg.rg_knn_last_stats()
     log(f"build: {bstats}")
     del Tr
+    torch.cuda.empty_cache()
     off, idx, entry = ix.graph()
     avg_deg = float(np.diff(off).mean())
     info = ix.info()
@@ -561,7 +514,8 @@ def main():
     gt100 = rg.as_u32(gt_ids)
     gt = gt100[:, :10]
     log(f"ground truth (exact kNN, k=100) in {time.time() - t:.1f} s")
-
+    peaks = rg.rg_measure_peaks()
+    log(f"measured peaks: {peaks}")
     if args.copy_probe:
         src = torch.empty(1 << 28, dtype=torch.float32, device=dev)
         dst = torch.empty_like(src)
@@ -573,93 +527,100 @@ def main():
         del src, dst
 
     k = 10
-    log("FP32 sweep")
-    L, curve = sweep(rg, torch, ix, Q, gt, k, L_GRID, 0.90)
-    if L is None:
-        L = L_GRID[-1]
-    rec = dict(curve)[L]
-    wall, launch_ms = time_search(rg, torch, ix, Q, k, L, args.steps, args.warmup)
     nq = Q.shape[0]
-    qps = nq * args.steps / wall
-    ms_launch = float(np.mean(launch_ms))
-    bytes_total, Vm, Hm = algorithmic_bytes(rg, torch, ix, Q, k, L, w.d, 4.0 * w.d, avg_deg)
-    achieved = bytes_total / (ms_launch * 1e-3) / 1e9
-    log(f"FP32 L={L} recall={rec:.4f} QPS={qps:.0f} launch={ms_launch:.3f} ms visits={Vm:.0f} hops={Hm:.0f} "
-        f"algorithmic {achieved:.0f} GB/s")
-
-    ids_fp32, ds_fp32 = rg.rg_search(ix, Q, k, L)
-    torch.cuda.synchronize()
-    err_fp32 = distance_errors(Xh, Qh, rg.as_u32(ids_fp32), ds_fp32.cpu().numpy())
-    log(f"FP32 distance error vs FP64: {err_fp32}")
-
+    forms = {}
     serving = {}
-    if not args.no_serve:
-        log("serving FP32: closed-loop capacity, then Poisson arrivals at 0.5/0.8/0.95 of it")
-        serving["fp32"] = serve_latency(rg, ix, Qh, gt100)
-        log(f"serving fp32: capacity {serving['fp32']['capacity_qps']:.0f} req/s")
-
-    precision = {}
-    if not args.no_precision:
-        for name, st, bpr in (("bf16", rg.RG_STORE_BF16, 2.0 * w.d), ("fp8", rg.RG_STORE_FP8E4M3, w.d + 4.0)):
-            rg.rg_index_set_storage(ix, st)
-            log(f"{name} sweep")
-            Lp, cp = sweep(rg, torch, ix, Q, gt, k, L_GRID, 0.90)
-            if Lp is None:
-                Lp = L_GRID[-1]
-            wp, lm = time_search(rg, torch, ix, Q, k, Lp, args.steps, args.warmup)
-            b, vm, hm = algorithmic_bytes(rg, torch, ix, Q, k, Lp, w.d, bpr, avg_deg)
-            b += nq * max(Lp, k) * 4.0 * w.d   # the FP32 rerank of the final queue
-            ids_p, ds_p = rg.rg_search(ix, Q, k, Lp)
+    skipped = []
+    for name, st, bpr in (("fp32", rg.RG_STORE_FP32, 4.0 * w.d), ("bf16", rg.RG_STORE_BF16, 2.0 * w.d),
+                          ("fp8", rg.RG_STORE_FP8E4M3, w.d + 4.0)):
+        if name != "fp32" and (args.no_precision or left() < 60):
+            skipped.append(f"{name} form")
+            continue
+        rg.rg_index_set_storage(ix, st)
+        log(f"{name} sweep")
+        L, curve = sweep(rg, torch, ix, Q, gt, k, L_GRID, 0.90)
+        if L is None:
+            L = L_GRID[-1]
+        rr = 0.0 if name == "fp32" else nq * max(L, k) * 4.0 * w.d   # the FP32 rerank of the final queue
+        f = graph_stage(rg, torch, ix, Q, k, L, gt, args.steps, args.warmup, w.d, bpr, avg_deg, rr)
+        f.update({"L": L, "recall_at_10": dict(curve)[L], "curve": [[a, b] for a, b in curve],
+                  "kernel": search_kernel_name(n, w.d, L, k, name)})
+        ids, ds = rg.rg_search(ix, Q, k, L)
+        torch.cuda.synchronize()
+        rows = None if name == "fp32" else storage_rows(rg, ix, st, n, w.d, info["pitch"])
+        f["dist_err_vs_fp64"] = distance_errors(Xh, Qh, rg.as_u32(ids), ds.cpu().numpy(), rows=rows)
+        del rows
+        if name != "fp32":
+            L32 = forms["fp32"]["L"]
+            ids, _ = rg.rg_search(ix, Q, k, L32)
             torch.cuda.synchronize()
-            err = distance_errors(Xh, Qh, rg.as_u32(ids_p), ds_p.cpu().numpy(),
-                                  rows=storage_rows(rg, ix, st, n, w.d, info["pitch"]))
-            precision[name] = {"L": Lp, "recall_at_10": dict(cp)[Lp], "qps": nq * args.steps / wp,
-                               "ms_per_launch": float(np.mean(lm)),
-                               "algorithmic_GBps": b / (np.mean(lm) * 1e-3) / 1e9,
-                               "qps_vs_fp32": nq * args.steps / wp / qps, "dist_err_vs_fp64": err}
-            log(f"{name}: {precision[name]}")
-            if not args.no_serve:
-                log(f"serving {name}")
-                serving[name] = serve_latency(rg, ix, Qh, gt100)
+            f["recall_at_fp32_L"] = {"L": L32, "recall": recall_at(rg.as_u32(ids), gt, k)}
+            f["qps_vs_fp32"] = f["qps"] / forms["fp32"]["qps"]
+        forms[name] = f
+        log(f"{name}: L={L} recall={f['recall_at_10']:.4f} QPS={f['qps']:.0f} launch={f['ms_per_launch']:.3f} ms "
+            f"visits={f['mean_visits']:.0f} hops={f['mean_hops']:.0f} algorithmic {f['algorithmic_GBps']:.0f} GB/s")
+        if args.save_index and name == "fp32":
+            rg.rg_save(ix, args.save_index + ".rgidx")
+            np.save(args.save_index + ".queries.npy", Qh)
+            with open(args.save_index + ".json", "w") as fh:
+                json.dump({"L": L, "k": k, "config": args.config}, fh)
+            log(f"index saved to {args.save_index}.rgidx")
+        if not args.no_serve:
+            if left() < 90:
+                skipped.append(f"{name} serving")
+            else:
+                log(f"serving {name}: closed-loop capacity, then Poisson arrivals at 0.5/0.8/0.95 of it")
+                serving[name] = serve_latency(rg, ix, Qh, gt100, n_req=args.serve_requests)
                 log(f"serving {name}: capacity {serving[name]['capacity_qps']:.0f} req/s")
-        rg.rg_index_set_storage(ix, rg.RG_STORE_FP32)
+    rg.rg_index_set_storage(ix, rg.RG_STORE_FP32)
 
     cpu = None
     if not args.no_cpu_baseline:
-        log("CPU oracle baseline")
-        cpu = cpu_baseline(Xh, off, idx, entry, Qh, k, L, args.cpu_seconds)
-        log(f"cpu: {cpu}")
+        if left() < 45:
+            skipped.append("cpu baseline")
+        else:
+            log("CPU oracle baseline")
+            cpu = cpu_baseline(Xh, off, idx, entry, Qh, k, forms["fp32"]["L"], min(args.cpu_seconds, left() / 3))
+            log(f"cpu: {cpu}")
 
-    traffic, traffic_bytes = measured_traffic(L, k, int(nq), ms_launch) if n == w.n else (None, None)
+    f32 = forms["fp32"]
+    L = f32["L"]
+    traffic, traffic_bytes = measured_traffic(w.name, L, k, int(nq), f32["ms_per_launch"]) \
+        if (n == w.n and nt == w.n_train) else (None, None)
+    achieved = f32["algorithmic_GBps"]
     out = {
         "metric": METRIC,
-        "value": qps,
+        "value": f32["qps"],
         "unit": "queries/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": wall / args.steps * 1e3,
+        "ms_per_step": f32["wall_s"] / args.steps * 1e3,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": w.name, "n_base": n, "d": w.d, "n_train": n, "n_test": int(nq), "Nq": w.Nq,
-                   "M": w.M, "L_build": 500, "k": k, "L": L, "recall_at_10": rec,
-                   "recall_curve": [[a, b] for a, b in curve], "metric_space": "inner product"},
+        "config": {"workload": w.name, "n_base": n, "d": w.d, "n_train": nt, "n_test": int(nq), "Nq": w.Nq,
+                   "M": w.M, "L_build": 500, "k": k, "L": L, "recall_at_10": f32["recall_at_10"],
+                   "recall_curve": f32["curve"], "metric_space": "cosine" if w.normalize else "inner product"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-                     "traffic_bytes_per_launch": traffic_bytes,
-                     "kernel": "k_search_persistent<8,7,0> (FP32 beam search, d=200)",
-                     "bytes_per_launch": bytes_total, "mean_visits": Vm, "mean_hops": Hm,
-                     "avg_degree": avg_deg, "ms_per_launch": ms_launch},
-        "dist_err_vs_fp64": err_fp32,
+                     "traffic_bytes_per_launch": traffic_bytes, "kernel": f32["kernel"],
+                     "bytes_per_launch": f32["bytes_per_launch"], "mean_visits": f32["mean_visits"],
+                     "mean_hops": f32["mean_hops"], "avg_degree": avg_deg, "ms_per_launch": f32["ms_per_launch"],
+                     "measured_peak_GBps": peaks["hbm_read_GBps"],
+                     "frac_of_measured_peak": achieved / peaks["hbm_read_GBps"]},
+        "dist_err_vs_fp64": f32["dist_err_vs_fp64"],
         "cpu_baseline": cpu,
         "paper_context": PAPER_CONTEXT,
-        "precision": precision,
+        "precision": {kk: v for kk, v in forms.items() if kk != "fp32"},
         "serving": serving or None,
         "build": bstats,
         "index": info,
+        "peaks_measured": peaks,
+        "skipped": skipped,
+        "bench_wall_s": time.time() - t_start,
     }
     print(json.dumps(out), flush=True)
 
