@@ -441,6 +441,30 @@ def search_kernel_name(n, d, L, k, storage):
     return f"k_search ({storage.upper()} rows, LDS visited table)"
 
 
+def profile_search(rg, torch, dev, args):
+    """Searches only, on a saved index: the launches a profiler attributes
+    to the search kernel at the benchmark's operating point."""
+    meta = json.load(open(args.profile_search + ".json"))
+    ix = rg.rg_load(args.profile_search + ".rgidx")
+    Q = torch.from_numpy(np.load(args.profile_search + ".queries.npy")).to(dev)
+    st = {"fp32": rg.RG_STORE_FP32, "bf16": rg.RG_STORE_BF16, "fp8": rg.RG_STORE_FP8E4M3}[args.storage]
+    rg.rg_index_set_storage(ix, st)
+    L = meta["L"] if args.storage == "fp32" else meta.get(f"L_{args.storage}", meta["L"])
+    k = meta["k"]
+    if args.copy_probe:
+        src = torch.empty(1 << 28, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        src.fill_(1.0)
+        torch.cuda.synchronize()
+        rg.rg_device_copy(dst, src)
+        torch.cuda.synchronize()
+        del src, dst
+    wall, lm = time_search(rg, torch, ix, Q, k, L, args.steps, args.warmup)
+    log(f"profile-search {args.storage}: L={L} k={k} launches={args.steps} mean {np.mean(lm):.3f} ms")
+    print(json.dumps({"profile_search": {"storage": args.storage, "L": L, "k": k, "nq": int(Q.shape[0]),
+                                         "ms_per_launch": float(np.mean(lm)), "launch_ms": lm}}), flush=True)
+
+
 def main():
     t_start = time.time()
     ap = argparse.ArgumentParser()
@@ -461,6 +485,10 @@ def main():
                     help="seconds from start after which optional parts (serving, reduced forms, CPU baseline) "
                          "are skipped and reported as such")
     ap.add_argument("--save-index", default=None, help="write the index, test queries and L to this prefix")
+    ap.add_argument("--profile-search", default=None,
+                    help="instead of the benchmark: load an index saved with --save-index and run --steps "
+                         "searches of its test queries at its operating L, FP32 rows (for profilers)")
+    ap.add_argument("--storage", choices=("fp32", "bf16", "fp8"), default="fp32", help="rows for --profile-search")
     ap.add_argument("--copy-probe", action="store_true", help="run a 1 GiB plain copy kernel (traffic calibration)")
     ap.add_argument("--ablation", action="store_true",
                     help="instead of the benchmark: G_bi / G_pj / RoarGraph, |T| = 0.1/0.5/1 |X|, ID queries")
@@ -481,6 +509,9 @@ def main():
     if args.ablation:
         w = datagen.WORKLOADS[2]
         print(json.dumps({"ablation": ablation(rg, torch, dev, args.n or w.n)}), flush=True)
+        return
+    if args.profile_search:
+        profile_search(rg, torch, dev, args)
         return
     left = lambda: args.time_budget - (time.time() - t_start)  # noqa: E731
     w = datagen.WORKLOADS[args.config]
@@ -559,12 +590,15 @@ def main():
         forms[name] = f
         log(f"{name}: L={L} recall={f['recall_at_10']:.4f} QPS={f['qps']:.0f} launch={f['ms_per_launch']:.3f} ms "
             f"visits={f['mean_visits']:.0f} hops={f['mean_hops']:.0f} algorithmic {f['algorithmic_GBps']:.0f} GB/s")
-        if args.save_index and name == "fp32":
-            rg.rg_save(ix, args.save_index + ".rgidx")
-            np.save(args.save_index + ".queries.npy", Qh)
+        if args.save_index:
+            if name == "fp32":
+                rg.rg_save(ix, args.save_index + ".rgidx")
+                np.save(args.save_index + ".queries.npy", Qh)
+                log(f"index saved to {args.save_index}.rgidx")
+            meta = {"k": k, "config": args.config, **{("L" if kk == "fp32" else f"L_{kk}"): v["L"]
+                                                      for kk, v in forms.items()}}
             with open(args.save_index + ".json", "w") as fh:
-                json.dump({"L": L, "k": k, "config": args.config}, fh)
-            log(f"index saved to {args.save_index}.rgidx")
+                json.dump(meta, fh)
         if not args.no_serve:
             if left() < 90:
                 skipped.append(f"{name} serving")
