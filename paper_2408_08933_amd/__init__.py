@@ -63,6 +63,7 @@ _SIGS = {
                             ctypes.POINTER(i32), ctypes.POINTER(i64)]),
     "rg_index_set_storage": (i32, [P, i32, P]),
     "rg_search": (i32, [P, P, i64, i32, i32, P, P, P, P, P]),
+    "rg_search_noalloc": (i32, [P, P, i64, i32, i32, P, P, P, P, P]),
     "rg_search_hashbits": (i32, [P, P, i64, i32, i32, P, P, P, P, i32, P]),
     "rg_knn": (i32, [P, i64, P, i64, i32, i32, P, P, P]),
     "rg_knn_candidates": (i32, [P, i64, P, i64, i32, i32, P, P, P]),
@@ -297,6 +298,13 @@ def rg_search_into(index: Index, queries, k, L, ids, ds, hops=None, ev=None, str
     _check(lib().rg_search(index.h, _ptr(queries), queries.shape[0], int(k), int(L), _ptr(ids), _ptr(ds),
                            _ptr(hops) if hops is not None else None, _ptr(ev) if ev is not None else None,
                            _stream(stream)))
+
+
+def rg_search_noalloc_into(index: Index, queries, k, L, ids, ds, hops=None, ev=None, stream=None):
+    """The allocation-free search into preallocated device tensors."""
+    _check(lib().rg_search_noalloc(index.h, _ptr(queries), queries.shape[0], int(k), int(L), _ptr(ids), _ptr(ds),
+                                   _ptr(hops) if hops is not None else None,
+                                   _ptr(ev) if ev is not None else None, _stream(stream)))
 
 
 def rg_knn(queries, base, k, stream=None):

@@ -993,6 +993,44 @@ int rg_search(const rg_index *ix, const float *queries, int64_t nq, int32_t k, i
     return rc;
 }
 
+int rg_search_noalloc(const rg_index *ix, const float *queries, int64_t nq, int32_t k, int32_t L, uint32_t *ids,
+                      float *dists, uint32_t *hops, uint32_t *evals, void *stream) {
+    if (!ix || nq < 0 || (nq > 0 && (!queries || !ids || !dists)) || k < 1 || L < 1 || k > kMaxL || L > kMaxL ||
+        nq >= (1ll << 31)) {
+        set_error("rg_search_noalloc: invalid argument (need 1 <= k, L <= 512)");
+        return RG_EINVAL;
+    }
+    if (!ix->d_base) {
+        set_error("rg_search_noalloc: index has no device data (built by rg_build_from_knn)");
+        return RG_EINVAL;
+    }
+    SearchArgs a = search_args(ix, queries, nq, k, L, ids, dists, hops, evals);
+    a.bm_words = ((ix->n + 31) / 32 + 63) / 64 * 64;
+    const int64_t fit = ((int64_t)kNoAllocScratchBytes - 256) / (a.bm_words * 4);
+    if (fit < 1) {
+        set_error("rg_search_noalloc: one visited bitmap of " + std::to_string(a.bm_words * 4) +
+                  " bytes does not fit the " + std::to_string(kNoAllocScratchBytes) + "-byte scratch");
+        return RG_EINVAL;
+    }
+    if (nq == 0) return RG_OK;
+    hipStream_t st = (hipStream_t)stream;
+    uint32_t *ptr = nullptr;
+    int rc = noalloc_scratch(ix->device, &ptr);
+    if (rc) return rc;
+    int per_cu = 0, cus = 0;
+    rc = search_occupancy(a, &per_cu);
+    if (rc) return rc;
+    RG_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, ix->device));
+    int64_t grid = (int64_t)std::max(1, per_cu) * std::max(1, cus);
+    grid = std::min<int64_t>(std::min<int64_t>(grid, nq), fit);
+    a.grid = (int32_t)grid;
+    a.work = ptr;
+    a.bitmap = ptr + 64;
+    rc = launch_zero_words(a.work, 64, st);
+    if (!rc) rc = launch_search_persistent(a, st);
+    return rc;
+}
+
 // Same as rg_search with an explicit visited-table size (2^hash_bits
 // entries, 8..15); used to check that the table size never changes results.
 int rg_search_hashbits(const rg_index *ix, const float *queries, int64_t nq, int32_t k, int32_t L, uint32_t *ids,

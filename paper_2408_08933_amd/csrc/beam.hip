@@ -30,6 +30,7 @@
 #include "wave_ops.h"
 
 #include <climits>
+#include <mutex>
 
 namespace rg {
 namespace {
@@ -758,6 +759,58 @@ int serve_step_occupancy(const SlotArgs &a, int *blocks_per_cu) {
     case RG_STORE_FP8E4M3: return dispatch_dim<StepOcc, RG_STORE_FP8E4M3>(a.s.d, b, nullptr);
     default: set_error("serve: unknown storage"); return RG_EINVAL;
     }
+}
+
+// ---------------------------------------------------------------------------
+// Device scratch of the allocation-free search (rg_search_noalloc): the
+// persistent search's work counter (first 256 bytes) and one visited bitmap
+// per resident workgroup.  Each device holds its own copy of this array from
+// the library's first use on it until the process ends.  In host code the
+// array's name is not a device address: the address comes from
+// hipGetSymbolAddress, taken once per device with that device current.
+// ---------------------------------------------------------------------------
+namespace {
+
+__device__ __align__(256) uint32_t scratch[kNoAllocScratchBytes / 4];
+
+__global__ void k_zero_words(uint32_t *p, int n) {
+    if ((int)threadIdx.x < n) p[threadIdx.x] = 0u;
+}
+
+}  // namespace
+
+int noalloc_scratch(int device, uint32_t **out) {
+    static std::mutex mu;
+    static uint32_t *ptr[kMaxDevices] = {};
+    if (device < 0 || device >= kMaxDevices) {
+        set_error("search_noalloc: device index out of range");
+        return RG_EINVAL;
+    }
+    std::lock_guard<std::mutex> lock(mu);
+    if (!ptr[device]) {
+        int cur = -1;
+        RG_HIP(hipGetDevice(&cur));
+        if (cur != device) {
+            set_error("search_noalloc: the index's device must be the current device");
+            return RG_EINVAL;
+        }
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p) {
+            set_error(std::string("search_noalloc: hipGetSymbolAddress: ") + hipGetErrorString(e));
+            return RG_EDEVICE;
+        }
+        ptr[device] = static_cast<uint32_t *>(p);
+    }
+    *out = ptr[device];
+    return RG_OK;
+}
+
+// a fill kernel rather than a memset, so callers may capture the search in a graph
+int launch_zero_words(uint32_t *p, int n, hipStream_t stream) {
+    hipLaunchKernelGGL(k_zero_words, dim3(1), dim3(64), 0, stream, p, n);
+    RG_HIP(hipGetLastError());
+    return RG_OK;
 }
 
 }  // namespace rg

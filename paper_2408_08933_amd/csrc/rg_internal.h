@@ -60,6 +60,12 @@ struct SearchArgs {
 
 // beam.hip
 int launch_search(const SearchArgs &a, hipStream_t stream);
+// Scratch of the allocation-free search: a file-scope device array of this
+// size per device; noalloc_scratch gives this device's address of it.
+constexpr size_t kNoAllocScratchBytes = 256ull << 20;
+constexpr int kMaxDevices = 64;
+int noalloc_scratch(int device, uint32_t **out);
+int launch_zero_words(uint32_t *p, int n, hipStream_t stream);
 int launch_search_persistent(const SearchArgs &a, hipStream_t stream);
 int search_occupancy(const SearchArgs &a, int *blocks_per_cu);
 size_t search_lds_bytes(int Leff, int pitch, int hash_bits, int cand);
