@@ -461,7 +461,20 @@ def profile_search(rg, torch, dev, args):
         del src, dst
     wall, lm = time_search(rg, torch, ix, Q, k, L, args.steps, args.warmup)
     log(f"profile-search {args.storage}: L={L} k={k} launches={args.steps} mean {np.mean(lm):.3f} ms")
-    print(json.dumps({"profile_search": {"storage": args.storage, "L": L, "k": k, "nq": int(Q.shape[0]),
+    # the same searches once more with their counters, against the saved
+    # ground truth: recall and mean expansions must equal the benchmark's
+    nq = Q.shape[0]
+    ids = torch.empty((nq, k), dtype=torch.int32, device=dev)
+    ds = torch.empty((nq, k), dtype=torch.float32, device=dev)
+    hops = torch.empty(nq, dtype=torch.int32, device=dev)
+    ev = torch.empty(nq, dtype=torch.int32, device=dev)
+    rg.rg_search_into(ix, Q, k, L, ids, ds, hops, ev)
+    torch.cuda.synchronize()
+    gt = np.load(args.profile_search + ".gt.npy")
+    print(json.dumps({"profile_search": {"storage": args.storage, "L": L, "k": k, "nq": int(nq),
+                                         "recall_at_10": recall_at(rg.as_u32(ids), gt, k),
+                                         "mean_hops": float(hops.double().mean()),
+                                         "mean_rows_scored": float(ev.double().mean()),
                                          "ms_per_launch": float(np.mean(lm)), "launch_ms": lm}}), flush=True)
 
 
@@ -594,6 +607,7 @@ def main():
             if name == "fp32":
                 rg.rg_save(ix, args.save_index + ".rgidx")
                 np.save(args.save_index + ".queries.npy", Qh)
+                np.save(args.save_index + ".gt.npy", gt)
                 log(f"index saved to {args.save_index}.rgidx")
             meta = {"k": k, "config": args.config, **{("L" if kk == "fp32" else f"L_{kk}"): v["L"]
                                                       for kk, v in forms.items()}}
