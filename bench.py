@@ -607,7 +607,7 @@ def main():
             if name == "fp32":
                 rg.rg_save(ix, args.save_index + ".rgidx")
                 np.save(args.save_index + ".queries.npy", Qh)
-                np.save(args.save_index + ".gt.npy", gt)
+                np.save(args.save_index + ".gt.npy", gt100)
                 log(f"index saved to {args.save_index}.rgidx")
             meta = {"k": k, "config": args.config, **{("L" if kk == "fp32" else f"L_{kk}"): v["L"]
                                                       for kk, v in forms.items()}}
