@@ -87,6 +87,23 @@ def test_medoid(oracle_lib):
     assert oracle_lib.medoid(np.array([[5, 5]], np.float32)) == 0
 
 
+# medoid with the projected-graph mask (R9): the mean is over ALL rows, the
+# choice among the masked rows only, lower id on ties
+def test_medoid_mask(oracle_lib):
+    # mean of all rows 5.6: row 2 (7); the mean of the masked rows (2.67)
+    # would give row 1
+    X = np.array([[0], [1], [7], [10], [10]], np.float32)
+    assert oracle_lib.medoid(X, mask=np.array([1, 1, 1, 0, 0], bool)) == 2
+    # mean 4.5: unmasked, rows 1 and 2 tie (lower id 1); masked to rows 0
+    # and 3, which tie at 4.5 from the mean -> row 0
+    X = np.array([[0], [4], [5], [9]], np.float32)
+    assert oracle_lib.medoid(X) == 1
+    assert oracle_lib.medoid(X, mask=np.array([1, 0, 0, 1], bool)) == 0
+    assert oracle_lib.medoid(X, mask=np.array([0, 0, 0, 1], bool)) == 3
+    # an empty mask selects from all rows
+    assert oracle_lib.medoid(X, mask=np.zeros(4, bool)) == 1
+
+
 # --------------------------------------------------------------------------
 # AcquireNeighbors (Algorithm 3) on hand geometry
 # --------------------------------------------------------------------------
