@@ -471,8 +471,13 @@ def profile_search(rg, torch, dev, args):
     rg.rg_search_into(ix, Q, k, L, ids, ds, hops, ev)
     torch.cuda.synchronize()
     gt = np.load(args.profile_search + ".gt.npy")
+    rec = recall_at(rg.as_u32(ids), gt, k)
+    want = meta.get("recall", {}).get(args.storage)
+    if want is not None and abs(rec - want) > 1e-4:
+        log(f"profile-search: recall {rec:.5f} on the saved index, the benchmark measured {want:.5f}")
+        sys.exit(3)
     print(json.dumps({"profile_search": {"storage": args.storage, "L": L, "k": k, "nq": int(nq),
-                                         "recall_at_10": recall_at(rg.as_u32(ids), gt, k),
+                                         "recall_at_10": rec,
                                          "mean_hops": float(hops.double().mean()),
                                          "mean_rows_scored": float(ev.double().mean()),
                                          "ms_per_launch": float(np.mean(lm)), "launch_ms": lm}}), flush=True)
@@ -610,7 +615,8 @@ def main():
                 np.save(args.save_index + ".gt.npy", gt100)
                 log(f"index saved to {args.save_index}.rgidx")
             meta = {"k": k, "config": args.config, **{("L" if kk == "fp32" else f"L_{kk}"): v["L"]
-                                                      for kk, v in forms.items()}}
+                                                      for kk, v in forms.items()},
+                    "recall": {kk: v["recall_at_10"] for kk, v in forms.items()}}
             with open(args.save_index + ".json", "w") as fh:
                 json.dump(meta, fh)
         if not args.no_serve:

@@ -666,6 +666,14 @@ struct PersistentLaunch {
     static int run(const SearchArgs &a, hipStream_t s) { return launch_persistent<ST, CLS>(a, s); }
 };
 template <int ST, int CLS>
+struct TableOcc {
+    static int run(const SearchArgs &a, hipStream_t) {
+        const size_t lds = search_lds_bytes(a.Leff, a.qpad, a.hash_bits, a.cand);
+        RG_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(a.occ_out, k_search<ST, CLS>, 64, lds));
+        return RG_OK;
+    }
+};
+template <int ST, int CLS>
 struct OccLaunch {
     static int run(const SearchArgs &a, hipStream_t) {
         return occupancy_of<ST, CLS>(a.Leff, a.qpad, a.cand, a.occ_out);
@@ -726,6 +734,17 @@ int search_occupancy(const SearchArgs &a, int *blocks_per_cu) {
     case RG_STORE_FP32: return dispatch_dim<OccLaunch, RG_STORE_FP32>(a.d, b, nullptr);
     case RG_STORE_BF16: return dispatch_dim<OccLaunch, RG_STORE_BF16>(a.d, b, nullptr);
     case RG_STORE_FP8E4M3: return dispatch_dim<OccLaunch, RG_STORE_FP8E4M3>(a.d, b, nullptr);
+    default: set_error("search: unknown storage"); return RG_EINVAL;
+    }
+}
+
+int table_search_occupancy(const SearchArgs &a, int *blocks_per_cu) {
+    SearchArgs b = a;
+    b.occ_out = blocks_per_cu;
+    switch (a.storage) {
+    case RG_STORE_FP32: return dispatch_dim<TableOcc, RG_STORE_FP32>(a.d, b, nullptr);
+    case RG_STORE_BF16: return dispatch_dim<TableOcc, RG_STORE_BF16>(a.d, b, nullptr);
+    case RG_STORE_FP8E4M3: return dispatch_dim<TableOcc, RG_STORE_FP8E4M3>(a.d, b, nullptr);
     default: set_error("search: unknown storage"); return RG_EINVAL;
     }
 }

@@ -68,6 +68,8 @@ int noalloc_scratch(int device, uint32_t **out);
 int launch_zero_words(uint32_t *p, int n, hipStream_t stream);
 int launch_search_persistent(const SearchArgs &a, hipStream_t stream);
 int search_occupancy(const SearchArgs &a, int *blocks_per_cu);
+// workgroups of the LDS-table search (k_search) one CU holds with a.hash_bits
+int table_search_occupancy(const SearchArgs &a, int *blocks_per_cu);
 size_t search_lds_bytes(int Leff, int pitch, int hash_bits, int cand);
 int cand_capacity(int ell, bool csr);  // candidate-batch capacity for a graph layout
 // E4M3 row layout: d codes, zeros to a multiple of 4, the FP32 scale, zeros
