@@ -350,10 +350,10 @@ int rg_index_build_stats(const rg_index *idx, double *t_knn, double *t_project, 
 
 /* rg_index_storage_ptrs -- device pointers of the reduced-precision copies
  * (NULL until made by rg_index_set_storage): bf16 rows (pitch elements of
- * 2 bytes); e4m3 rows of pitch8 bytes, each holding the d codes, zeros up to
- * a multiple of 4 bytes, the row's FP32 scale and zeros up to a multiple of
- * 16 (the search reads the scale with the codes); and the scales again as an
- * array of n floats.  The index keeps ownership. */
+ * 2 bytes); e4m3 rows of pitch8 bytes (a multiple of 128), each holding the
+ * d codes, zeros up to a multiple of 4 bytes, the row's FP32 scale and zeros
+ * to the pitch (the search reads the scale with the codes); and the scales
+ * again as an array of n floats.  The index keeps ownership. */
 int rg_index_storage_ptrs(const rg_index *idx, const void **bf16, const void **fp8,
                           const float **scales, int32_t *pitch8);
 
@@ -401,7 +401,7 @@ typedef struct {
     int32_t max_L;            /* largest L_eff accepted (<= 512); 0 => 512 */
     int32_t hash_bits;        /* visited table of 2^hash_bits ids per slot (8..13, and at least
                                  twice the candidate batch); it bounds work, not results;
-                                 0 => 11 for FP32 storage, 9 for BF16 / FP8 */
+                                 0 => 9 */
 } rg_server_limits;
 
 typedef struct {

@@ -205,10 +205,13 @@ void rg_server::loop() {
 
 extern "C" {
 
-// default visited-table size per slot: 2^11 ids for FP32 rows, 2^9 for BF16
-// and FP8 (measured on the mixed-L serving load; a small table costs
-// rescoring, which the reduced rows make cheap)
-int serve_hash_bits(int32_t storage) { return storage == RG_STORE_FP32 ? 11 : 9; }
+// default visited-table size per slot: 2^9 ids for every storage form.  The
+// step kernel's LDS holds a queue of 512 entries and the table, so a small
+// table lets more workgroups share a CU; it costs a little rescoring.
+// Measured on the 10M x 200 index with the mixed-L load and 4,096 slots:
+// FP32 closed-loop capacity 297k (2^11, 11 workgroups per CU), 311k (2^10),
+// 348k req/s (2^9, 19 per CU); E4M3 rows 351k at 2^9, 344k at 2^8.
+static int serve_hash_bits(int32_t) { return 9; }
 
 int rg_server_create(const rg_index *ix, const rg_server_limits *lim, rg_server **out) {
     if (!ix || !out || !ix->d_base) {

@@ -495,7 +495,7 @@ def test_quantized_rows_match_oracle(dev, oracle_lib, c1):
     # each E4M3 row carries its scale after the codes (4-byte aligned); the
     # rest of the row is zero
     s_off = (d + 3) // 4 * 4
-    assert p8 == (s_off + 4 + 15) // 16 * 16
+    assert p8 == ((s_off + 4 + 15) // 16 * 16 + 127) // 128 * 128
     assert np.array_equal(c[:, s_off:s_off + 4].copy().view(np.float32)[:, 0], os_)
     assert not c[:, d:s_off].any() and not c[:, s_off + 4:].any()
 
