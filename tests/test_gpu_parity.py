@@ -467,6 +467,36 @@ def test_save_load_roundtrip(dev, c1, c1_built):
         assert e.value.code == rg.RG_ECORRUPT
 
 
+def test_save_load_several_chunks(dev):
+    # rg_save copies the padded device rows back 16,384 at a time: 40,000
+    # rows of d = 72 (pitch 80) take three copies, the last one ragged.  The
+    # loaded index must answer every query exactly as the saved one.
+    n, d = 40_000, 72
+    rng = np.random.default_rng(17)
+    X = rng.standard_normal((n, d)).astype(np.float32)
+    Q = rng.standard_normal((64, d)).astype(np.float32)
+    off, idx = datagen.random_graph_fast(n, 16, seed=5)
+    ix = rg.rg_index_from_csr(T(X, dev), off, idx, 0)
+    with tempfile.TemporaryDirectory() as td:
+        p = os.path.join(td, "r.rgidx")
+        rg.rg_save(ix, p)
+        ix2 = rg.rg_load(p)
+    a, b = ix.graph(), ix2.graph()
+    assert all(np.array_equal(x, y) for x, y in zip(a[:2], b[:2])) and a[2] == b[2]
+    r1 = rg.rg_search(ix, T(Q, dev), 10, 200)
+    r2 = rg.rg_search(ix2, T(Q, dev), 10, 200)
+    torch.cuda.synchronize()
+    assert torch.equal(r1[0], r2[0]) and torch.equal(r1[1], r2[1])
+    # the distances the loaded index returns are those of the original rows
+    # (rows from every copy chunk come back)
+    ids = rg.as_u32(r2[0])
+    assert ids.max() >= 2 * 16384
+    got = r2[1].cpu().numpy().astype(np.float64)
+    for q in range(len(Q)):
+        want = -(X[ids[q]].astype(np.float64) @ Q[q].astype(np.float64))
+        assert np.allclose(got[q], want, rtol=0, atol=1e-4)
+
+
 # ---------------------------------------------------------------------------
 # reduced-precision storage
 # ---------------------------------------------------------------------------
