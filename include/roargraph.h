@@ -444,7 +444,9 @@ int rg_server_stats(const rg_server *s, uint64_t *submitted, uint64_t *admitted,
 double rg_server_now(const rg_server *s);
 
 /* rg_server_slots -- slots actually allocated: min(max_slots,
- * hbm_pool_bytes / bytes of one slot's state). */
+ * hbm_pool_bytes / bytes of one slot's state).  A slot's state is its
+ * query, k and L, a queue of 512 (key, id) pairs, 8 state words, the
+ * visited table and one result record for each of the two steps in flight. */
 int32_t rg_server_slots(const rg_server *s);
 
 /* rg_server_destroy -- finish in-flight work, stop the thread, free all. */

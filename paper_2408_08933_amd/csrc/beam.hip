@@ -535,10 +535,14 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void k_
 // One scheduler step of the serving loop: advance each listed slot by up to
 // hops_budget expansions, keeping its whole state in device memory.  Five
 // resident wavefronts per SIMD, as for k_search: the step is latency-bound.
+// Slot state word 0: 0 = admitted, not started; > 0 = queue length of a
+// search in progress; -1 = finished (its record written; the slot is
+// skipped until the host admits a new request into it).
 template <int ST, int CLS>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(5))) void k_serve_step(SlotArgs sa) {
     extern __shared__ __align__(16) unsigned char smem[];
     const int slot = sa.active[blockIdx.x];
+    if (sa.slot_state[(size_t)slot * 8] < 0) return;
     SearchArgs a = sa.s;
     a.k = sa.slot_k[slot];
     a.Leff = max(sa.slot_L[slot], a.k);
@@ -582,7 +586,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(5))) void k_
             r->qn = qn;
             r->hops = hops;
             r->evals = evals;
-            st[0] = 0;
+            st[0] = -1;
         }
     } else {
         for (int i = lane; i < qn; i += 64) {

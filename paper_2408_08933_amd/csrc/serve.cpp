@@ -10,11 +10,19 @@
 // arrive while a step runs are admitted at the next step, so new work joins
 // work already on the device instead of waiting for a batch to drain.
 //
+// Two steps are in flight: the thread launches step s + 1 before it waits
+// for step s and collects its results, so the device runs the next step
+// while the host copies and hands out the last one's results and stages
+// new admissions.  A slot that finished in step s is still listed in step
+// s + 1 (the host has not seen it finish yet); it is marked finished in
+// device memory and that step skips it.  Each step has its own staging,
+// active-list, count and record buffers (two sets, used alternately).
+//
 // The step kernel runs the same per-query arithmetic as rg_search (same
 // distance function, same merge), and a slot's state is saved and restored
 // exactly, so a request returns the same ids and distances alone or in any
 // mix.  The device never waits on host memory: every kernel runs to
-// completion and the host polls a done flag after each step.
+// completion and the host waits on an event after each step.
 #include <chrono>
 #include <condition_variable>
 #include <cstring>
@@ -37,7 +45,6 @@ struct Pending {
 
 struct SlotInfo {
     bool busy = false;
-    bool fresh = false;
     uint64_t tag = 0;
     int32_t k = 0, L = 0;
     double t_submit = 0, t_admit = 0;
@@ -45,25 +52,33 @@ struct SlotInfo {
 
 constexpr size_t kMaxPending = 1u << 20;
 
+// Buffers of one in-flight step.
+struct StepBuf {
+    int32_t *d_adm_slot = nullptr, *d_adm_k = nullptr, *d_adm_L = nullptr, *d_active = nullptr;
+    float *d_adm_q = nullptr;
+    uint32_t *d_count = nullptr;
+    ServeRecord *d_rec = nullptr;
+    int32_t *h_adm_slot = nullptr, *h_adm_k = nullptr, *h_adm_L = nullptr, *h_active = nullptr;
+    float *h_adm_q = nullptr;
+    uint32_t *h_count = nullptr;
+    ServeRecord *h_rec = nullptr;
+    hipEvent_t done = nullptr;  // the step kernel and its count copy have finished
+    bool launched = false;
+};
+
 }  // namespace
 
 struct rg_server {
     const rg_index *ix = nullptr;
     rg_server_limits lim{};
     int32_t slots = 0, hash_bits = 12;
-    hipStream_t stream = nullptr;
+    hipStream_t stream = nullptr;       // admissions and step kernels
+    hipStream_t copy_stream = nullptr;  // result records back to the host
     // device slot arrays
     float *d_q = nullptr, *d_qd = nullptr;
-    int32_t *d_k = nullptr, *d_L = nullptr, *d_state = nullptr, *d_active = nullptr;
-    uint32_t *d_qi = nullptr, *d_hash = nullptr, *d_count = nullptr;
-    ServeRecord *d_rec = nullptr;
-    // admission staging (device) and pinned host mirrors
-    int32_t *d_adm_slot = nullptr, *d_adm_k = nullptr, *d_adm_L = nullptr;
-    float *d_adm_q = nullptr;
-    int32_t *h_adm_slot = nullptr, *h_adm_k = nullptr, *h_adm_L = nullptr, *h_active = nullptr;
-    float *h_adm_q = nullptr;
-    uint32_t *h_count = nullptr;
-    ServeRecord *h_rec = nullptr;
+    int32_t *d_k = nullptr, *d_L = nullptr, *d_state = nullptr;
+    uint32_t *d_qi = nullptr, *d_hash = nullptr;
+    StepBuf buf[2];
     // host side
     std::mutex mu;
     std::condition_variable cv;
@@ -78,30 +93,128 @@ struct rg_server {
 
     double now() const { return std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count(); }
     void loop();
+    bool launch(StepBuf &b, int32_t n_adm_now, int32_t n_active);
+    bool collect(StepBuf &b);
     void release();
 };
 
 void rg_server::release() {
-    void *ps[] = {d_q, d_qd, d_k, d_L, d_state, d_active, d_qi, d_hash, d_count, d_rec,
-                  d_adm_slot, d_adm_k, d_adm_L, d_adm_q};
+    void *ps[] = {d_q, d_qd, d_k, d_L, d_state, d_qi, d_hash};
     for (void *p : ps)
         if (p) (void)hipFree(p);
-    void *hs[] = {h_adm_slot, h_adm_k, h_adm_L, h_active, h_adm_q, h_count, h_rec};
-    for (void *p : hs)
-        if (p) (void)hipHostFree(p);
+    for (StepBuf &b : buf) {
+        void *dp[] = {b.d_adm_slot, b.d_adm_k, b.d_adm_L, b.d_active, b.d_adm_q, b.d_count, b.d_rec};
+        for (void *p : dp)
+            if (p) (void)hipFree(p);
+        void *hp[] = {b.h_adm_slot, b.h_adm_k, b.h_adm_L, b.h_active, b.h_adm_q, b.h_count, b.h_rec};
+        for (void *p : hp)
+            if (p) (void)hipHostFree(p);
+        if (b.done) (void)hipEventDestroy(b.done);
+    }
     if (stream) (void)hipStreamDestroy(stream);
+    if (copy_stream) (void)hipStreamDestroy(copy_stream);
+}
+
+// Enqueue one step on the server's stream: scatter the admitted requests into
+// their slots, advance the listed slots, copy the finished count back.
+bool rg_server::launch(StepBuf &b, int32_t n_adm_now, int32_t n_active) {
+    const int d = ix->d;
+    hipStream_t st = stream;
+    SlotArgs sa{};
+    sa.s.base = ix->d_base;
+    sa.s.base_bf16 = ix->d_bf16;
+    sa.s.base_fp8 = ix->d_fp8;
+    sa.s.adj = ix->d_adj;
+    sa.s.adj_off = ix->d_adj_off;
+    sa.s.tomb = ix->d_tomb;
+    sa.s.d = d;
+    sa.s.pitch = ix->pitch;
+    sa.s.pitch8 = ix->pitch8;
+    sa.s.qpad = query_pad(d, ix->pitch, ix->storage);
+    sa.s.ell = ix->ell;
+    sa.s.cand = cand_capacity(ix->ell, ix->d_adj_off != nullptr);
+    sa.s.hash_bits = hash_bits;
+    sa.s.entry = ix->entry;
+    sa.s.storage = ix->storage;
+    sa.active = b.d_active;
+    sa.n_active = n_active;
+    sa.slot_q = d_q;
+    sa.slot_k = d_k;
+    sa.slot_L = d_L;
+    sa.slot_qd = d_qd;
+    sa.slot_qi = d_qi;
+    sa.slot_state = d_state;
+    sa.slot_hash = d_hash;
+    sa.hops_budget = lim.hops_per_step;
+    sa.out_count = b.d_count;
+    sa.out_rec = b.d_rec;
+    bool ok = true;
+    if (n_adm_now > 0) {
+        ok = hipMemcpyAsync(b.d_adm_slot, b.h_adm_slot, 4 * n_adm_now, hipMemcpyHostToDevice, st) == hipSuccess &&
+             hipMemcpyAsync(b.d_adm_k, b.h_adm_k, 4 * n_adm_now, hipMemcpyHostToDevice, st) == hipSuccess &&
+             hipMemcpyAsync(b.d_adm_L, b.h_adm_L, 4 * n_adm_now, hipMemcpyHostToDevice, st) == hipSuccess &&
+             hipMemcpyAsync(b.d_adm_q, b.h_adm_q, sizeof(float) * d * n_adm_now, hipMemcpyHostToDevice, st) ==
+                 hipSuccess &&
+             launch_serve_admit(n_adm_now, b.d_adm_slot, b.d_adm_q, b.d_adm_k, b.d_adm_L, d, d_q, d_k, d_L, d_state,
+                                st) == RG_OK;
+    }
+    ok = ok &&
+         hipMemcpyAsync(b.d_active, b.h_active, sizeof(int32_t) * n_active, hipMemcpyHostToDevice, st) ==
+             hipSuccess &&
+         hipMemsetAsync(b.d_count, 0, 4, st) == hipSuccess && launch_serve_step(sa, st) == RG_OK &&
+         hipMemcpyAsync(b.h_count, b.d_count, 4, hipMemcpyDeviceToHost, st) == hipSuccess &&
+         hipEventRecord(b.done, st) == hipSuccess;
+    b.launched = ok;
+    return ok;
+}
+
+// Wait for the step in b, copy its finished records back (on the copy
+// stream, so the step launched after it keeps running) and hand them out.
+bool rg_server::collect(StepBuf &b) {
+    b.launched = false;
+    if (hipEventSynchronize(b.done) != hipSuccess) return false;
+    const uint32_t nf = *b.h_count;
+    if (nf > 0 &&
+        (hipMemcpyAsync(b.h_rec, b.d_rec, sizeof(ServeRecord) * nf, hipMemcpyDeviceToHost, copy_stream) !=
+             hipSuccess ||
+         hipStreamSynchronize(copy_stream) != hipSuccess))
+        return false;
+    const double t_done = now();
+    std::lock_guard<std::mutex> lk(mu);
+    ++n_steps;
+    for (uint32_t i = 0; i < nf; ++i) {
+        const ServeRecord &rec = b.h_rec[i];
+        SlotInfo &si = info[rec.slot];
+        rg_result r{};
+        r.tag = si.tag;
+        r.k = si.k;
+        r.status = RG_OK;
+        r.hops = rec.hops;
+        r.evals = rec.evals;
+        std::memcpy(r.ids, rec.ids, sizeof(uint32_t) * si.k);
+        std::memcpy(r.dists, rec.d, sizeof(float) * si.k);
+        r.t_submit = si.t_submit;
+        r.t_admit = si.t_admit;
+        r.t_done = t_done;
+        finished.push_back(r);
+        si.busy = false;
+        ++n_done;
+    }
+    return true;
 }
 
 void rg_server::loop() {
     (void)hipSetDevice(ix->device);
     const int d = ix->d;
+    int cur = 0;
     for (;;) {
+        StepBuf &b = buf[cur], &prev = buf[cur ^ 1];
         int32_t n_adm_now = 0, n_active = 0;
         {
             std::unique_lock<std::mutex> lk(mu);
             bool any_busy = false;
             for (auto &s : info) any_busy |= s.busy;
-            if (!any_busy && pending.empty()) {
+            if (!any_busy && pending.empty() && !prev.launched) {
                 if (stop) break;
                 cv.wait_for(lk, std::chrono::milliseconds(1));
                 continue;
@@ -111,96 +224,36 @@ void rg_server::loop() {
             for (int32_t s = 0; s < slots && !pending.empty() && !stop; ++s) {
                 if (info[s].busy) continue;
                 Pending &p = pending.front();
-                info[s] = SlotInfo{true, true, p.tag, p.k, p.L, p.t_submit, t_adm};
-                h_adm_slot[n_adm_now] = s;
-                h_adm_k[n_adm_now] = p.k;
-                h_adm_L[n_adm_now] = p.L;
-                std::memcpy(h_adm_q + (size_t)n_adm_now * d, p.q.data(), sizeof(float) * d);
+                info[s] = SlotInfo{true, p.tag, p.k, p.L, p.t_submit, t_adm};
+                b.h_adm_slot[n_adm_now] = s;
+                b.h_adm_k[n_adm_now] = p.k;
+                b.h_adm_L[n_adm_now] = p.L;
+                std::memcpy(b.h_adm_q + (size_t)n_adm_now * d, p.q.data(), sizeof(float) * d);
                 ++n_adm_now;
                 pending.pop_front();
                 ++n_adm;
             }
+            // every busy slot, including those that finish in the step in
+            // flight (that step marks them, and this one skips them)
             for (int32_t s = 0; s < slots; ++s)
-                if (info[s].busy) h_active[n_active++] = s;
+                if (info[s].busy) b.h_active[n_active++] = s;
         }
-        if (n_active == 0) continue;
-        SlotArgs sa{};
-        sa.s.base = ix->d_base;
-        sa.s.base_bf16 = ix->d_bf16;
-        sa.s.base_fp8 = ix->d_fp8;
-        sa.s.adj = ix->d_adj;
-        sa.s.adj_off = ix->d_adj_off;
-        sa.s.tomb = ix->d_tomb;
-        sa.s.d = d;
-        sa.s.pitch = ix->pitch;
-        sa.s.pitch8 = ix->pitch8;
-        sa.s.qpad = query_pad(d, ix->pitch, ix->storage);
-        sa.s.ell = ix->ell;
-        sa.s.cand = cand_capacity(ix->ell, ix->d_adj_off != nullptr);
-        sa.s.hash_bits = hash_bits;
-        sa.s.entry = ix->entry;
-        sa.s.storage = ix->storage;
-        sa.active = d_active;
-        sa.n_active = n_active;
-        sa.slot_q = d_q;
-        sa.slot_k = d_k;
-        sa.slot_L = d_L;
-        sa.slot_qd = d_qd;
-        sa.slot_qi = d_qi;
-        sa.slot_state = d_state;
-        sa.slot_hash = d_hash;
-        sa.hops_budget = lim.hops_per_step;
-        sa.out_count = d_count;
-        sa.out_rec = d_rec;
-        bool ok = true;
-        if (n_adm_now > 0) {
-            ok = hipMemcpyAsync(d_adm_slot, h_adm_slot, 4 * n_adm_now, hipMemcpyHostToDevice, stream) == hipSuccess &&
-                 hipMemcpyAsync(d_adm_k, h_adm_k, 4 * n_adm_now, hipMemcpyHostToDevice, stream) == hipSuccess &&
-                 hipMemcpyAsync(d_adm_L, h_adm_L, 4 * n_adm_now, hipMemcpyHostToDevice, stream) == hipSuccess &&
-                 hipMemcpyAsync(d_adm_q, h_adm_q, sizeof(float) * d * n_adm_now, hipMemcpyHostToDevice, stream) ==
-                     hipSuccess &&
-                 launch_serve_admit(n_adm_now, d_adm_slot, d_adm_q, d_adm_k, d_adm_L, d, d_q, d_k, d_L, d_state,
-                                    stream) == RG_OK;
-        }
-        ok = ok &&
-             hipMemcpyAsync(d_active, h_active, sizeof(int32_t) * n_active, hipMemcpyHostToDevice, stream) ==
-                 hipSuccess &&
-             hipMemsetAsync(d_count, 0, 4, stream) == hipSuccess && launch_serve_step(sa, stream) == RG_OK &&
-             hipMemcpyAsync(h_count, d_count, 4, hipMemcpyDeviceToHost, stream) == hipSuccess &&
-             hipStreamSynchronize(stream) == hipSuccess;
-        const uint32_t nf = ok ? *h_count : 0;
-        if (ok && nf > 0)
-            ok = hipMemcpyAsync(h_rec, d_rec, sizeof(ServeRecord) * nf, hipMemcpyDeviceToHost, stream) == hipSuccess &&
-                 hipStreamSynchronize(stream) == hipSuccess;
+        bool ok = n_active == 0 || launch(b, n_adm_now, n_active);
+        if (ok && prev.launched) ok = collect(prev);
         if (!ok) {
+            // drain what is in flight, then drop every request
+            (void)hipStreamSynchronize(stream);
+            (void)hipStreamSynchronize(copy_stream);
             std::lock_guard<std::mutex> lk(mu);
             err = RG_EDEVICE;
             for (auto &s : info) s.busy = false;
             pending.clear();
+            for (StepBuf &x : buf) x.launched = false;
             continue;
         }
-        ++n_steps;
-        const double t_done = now();
-        std::lock_guard<std::mutex> lk(mu);
-        for (uint32_t i = 0; i < nf; ++i) {
-            const ServeRecord &rec = h_rec[i];
-            SlotInfo &si = info[rec.slot];
-            rg_result r{};
-            r.tag = si.tag;
-            r.k = si.k;
-            r.status = RG_OK;
-            r.hops = rec.hops;
-            r.evals = rec.evals;
-            std::memcpy(r.ids, rec.ids, sizeof(uint32_t) * si.k);
-            std::memcpy(r.dists, rec.d, sizeof(float) * si.k);
-            r.t_submit = si.t_submit;
-            r.t_admit = si.t_admit;
-            r.t_done = t_done;
-            finished.push_back(r);
-            si.busy = false;
-            ++n_done;
-        }
+        cur ^= 1;
     }
+    (void)hipStreamSynchronize(stream);
 }
 
 extern "C" {
@@ -257,9 +310,10 @@ int rg_server_create(const rg_index *ix, const rg_server_limits *lim, rg_server 
     s->lim = l;
     s->hash_bits = l.hash_bits;
     // device bytes one slot keeps between steps: query, k/L, queue (keys + ids),
-    // state words, visited table, its result record
+    // state words, visited table, a result record in each of the two steps'
+    // buffers
     const int64_t per_slot = (int64_t)ix->d * 4 + 8 + (int64_t)kMaxL * 8 + 32 + ((int64_t)4 << s->hash_bits) +
-                             (int64_t)sizeof(ServeRecord);
+                             2 * (int64_t)sizeof(ServeRecord);
     int64_t slots = l.max_slots;
     if (l.hbm_pool_bytes > 0) slots = std::min<int64_t>(slots, l.hbm_pool_bytes / per_slot);
     if (slots < 1) {
@@ -270,7 +324,7 @@ int rg_server_create(const rg_index *ix, const rg_server_limits *lim, rg_server 
     s->slots = (int32_t)slots;
     s->info.resize((size_t)slots);
     (void)hipSetDevice(ix->device);
-    bool ok = hipStreamCreate(&s->stream) == hipSuccess;
+    bool ok = hipStreamCreate(&s->stream) == hipSuccess && hipStreamCreate(&s->copy_stream) == hipSuccess;
     auto al = [&](void **p, size_t b) { ok = ok && hipMalloc(p, b) == hipSuccess; };
     auto ah = [&](void **p, size_t b) { ok = ok && hipHostMalloc(p, b, hipHostMallocDefault) == hipSuccess; };
     al((void **)&s->d_q, sizeof(float) * slots * ix->d);
@@ -280,20 +334,23 @@ int rg_server_create(const rg_index *ix, const rg_server_limits *lim, rg_server 
     al((void **)&s->d_qi, sizeof(uint32_t) * slots * kMaxL);
     al((void **)&s->d_state, 32 * slots);
     al((void **)&s->d_hash, (size_t)slots << (s->hash_bits + 2));
-    al((void **)&s->d_active, 4 * slots);
-    al((void **)&s->d_count, 4);
-    al((void **)&s->d_rec, sizeof(ServeRecord) * slots);
-    al((void **)&s->d_adm_slot, 4 * slots);
-    al((void **)&s->d_adm_k, 4 * slots);
-    al((void **)&s->d_adm_L, 4 * slots);
-    al((void **)&s->d_adm_q, sizeof(float) * slots * ix->d);
-    ah((void **)&s->h_adm_slot, 4 * slots);
-    ah((void **)&s->h_adm_k, 4 * slots);
-    ah((void **)&s->h_adm_L, 4 * slots);
-    ah((void **)&s->h_active, 4 * slots);
-    ah((void **)&s->h_adm_q, sizeof(float) * slots * ix->d);
-    ah((void **)&s->h_count, 4);
-    ah((void **)&s->h_rec, sizeof(ServeRecord) * slots);
+    for (StepBuf &b : s->buf) {
+        al((void **)&b.d_active, 4 * slots);
+        al((void **)&b.d_count, 4);
+        al((void **)&b.d_rec, sizeof(ServeRecord) * slots);
+        al((void **)&b.d_adm_slot, 4 * slots);
+        al((void **)&b.d_adm_k, 4 * slots);
+        al((void **)&b.d_adm_L, 4 * slots);
+        al((void **)&b.d_adm_q, sizeof(float) * slots * ix->d);
+        ah((void **)&b.h_adm_slot, 4 * slots);
+        ah((void **)&b.h_adm_k, 4 * slots);
+        ah((void **)&b.h_adm_L, 4 * slots);
+        ah((void **)&b.h_active, 4 * slots);
+        ah((void **)&b.h_adm_q, sizeof(float) * slots * ix->d);
+        ah((void **)&b.h_count, 4);
+        ah((void **)&b.h_rec, sizeof(ServeRecord) * slots);
+        ok = ok && hipEventCreateWithFlags(&b.done, hipEventDisableTiming) == hipSuccess;
+    }
     if (!ok) {
         s->release();
         delete s;

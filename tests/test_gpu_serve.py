@@ -89,9 +89,10 @@ def test_alone_equals_mix(setup, storage):
 
 def test_memory_bounded_admission(setup):
     dev, X, Q, ix = setup
-    # with a 2^12-entry visited table one slot keeps ~24.9 KB at d=64 (query,
-    # queue, table, outputs): a 75 KB pool admits three requests at a time
-    srv = rg.Server(ix, max_slots=1000, hbm_pool_bytes=75_000, hash_bits=12)
+    # with a 2^12-entry visited table one slot keeps ~29.0 KB at d=64 (query,
+    # queue, table, a result record per in-flight step): a 90 KB pool admits
+    # three requests at a time
+    srv = rg.Server(ix, max_slots=1000, hbm_pool_bytes=90_000, hash_bits=12)
     assert srv.slots() == 3
     n = 40
     res = run_mix(srv, Q, np.full(n, 10), np.full(n, 64))
