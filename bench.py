@@ -134,9 +134,11 @@ def serve_run(rg, ix, Qh, gt, n_req, rate, seed=0, timeout=120.0):
     ks = rng.choice([1, 10, 100], n_req).astype(np.int32)
     Ls = rng.choice([32, 128, 512], n_req).astype(np.int32)
     arrive = np.cumsum(rng.exponential(1.0 / rate, n_req)) if rate else np.zeros(n_req)
-    # 4096 slots: the automatic count (twice the resident step workgroups,
-    # up to 9,728) serves more requests closed-loop but queues at high load
-    srv = rg.Server(ix, max_slots=4096, hops_per_step=32)
+    # 6,144 slots of 24 expansions per step, measured on the 10M x 200 index
+    # with FP32 rows: 4,096 slots ran out at 0.8 load (p99 of L = 32
+    # requests 7.5 ms against 2.6 ms) and 32 expansions per step added
+    # about half a millisecond to the median
+    srv = rg.Server(ix, max_slots=6144, hops_per_step=24)
     done = {}
     i = 0
     t0 = srv.now()
