@@ -443,6 +443,26 @@ def search_kernel_name(n, d, L, k, storage):
     return f"k_search ({storage.upper()} rows, LDS visited table)"
 
 
+def profile_knn(rg, torch, dev, args):
+    """The build's kNN candidate pass alone (one launch per step) on seeded
+    Gaussian rows of the serving shape's width, for counter passes."""
+    nq, n, d, K = 131072, 4_000_000, 200, 200
+    g = torch.Generator(device=dev)
+    g.manual_seed(1)
+    Q = torch.randn((nq, d), device=dev, generator=g) * 0.1
+    X = torch.randn((n, d), device=dev, generator=g) * 0.1
+    torch.cuda.synchronize()
+    times = []
+    for _ in range(args.steps):
+        t = time.perf_counter()
+        rg.rg_knn_candidates_f16(Q, X, K)
+        torch.cuda.synchronize()
+        times.append(time.perf_counter() - t)
+    flop = 2.0 * nq * n * d
+    print(json.dumps({"profile_knn": {"nq": nq, "n": n, "d": d, "K": K, "s_per_call": times,
+                                      "tflops_best": flop / min(times) / 1e12}}), flush=True)
+
+
 def profile_search(rg, torch, dev, args):
     """Searches only, on a saved index: the launches a profiler attributes
     to the search kernel at the benchmark's operating point."""
@@ -509,6 +529,9 @@ def main():
                     help="instead of the benchmark: load an index saved with --save-index and run --steps "
                          "searches of its test queries at its operating L, FP32 rows (for profilers)")
     ap.add_argument("--storage", choices=("fp32", "bf16", "fp8"), default="fp32", help="rows for --profile-search")
+    ap.add_argument("--profile-knn", action="store_true",
+                    help="instead of the benchmark: the FP16 kNN candidate pass alone, 131,072 queries against "
+                         "4M base rows of d = 200, K = 200, --steps times (for profilers)")
     ap.add_argument("--copy-probe", action="store_true", help="run a 1 GiB plain copy kernel (traffic calibration)")
     ap.add_argument("--ablation", action="store_true",
                     help="instead of the benchmark: G_bi / G_pj / RoarGraph, |T| = 0.1/0.5/1 |X|, ID queries")
@@ -532,6 +555,9 @@ def main():
         return
     if args.profile_search:
         profile_search(rg, torch, dev, args)
+        return
+    if args.profile_knn:
+        profile_knn(rg, torch, dev, args)
         return
     left = lambda: args.time_budget - (time.time() - t_start)  # noqa: E731
     w = datagen.WORKLOADS[args.config]
