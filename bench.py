@@ -42,6 +42,7 @@ PAPER_CONTEXT = {
     "knn_share_of_build_time": "87-93% (full training set, CPU)",
 }
 L_GRID = [10, 20, 30, 40, 50, 75, 100, 150, 200, 300, 400, 500]
+SERVE_SLOTS, SERVE_HOPS = 6144, 24  # server slots and expansions per scheduler step
 HBM_PEAK_GBS = 8000.0
 
 
@@ -138,7 +139,7 @@ def serve_run(rg, ix, Qh, gt, n_req, rate, seed=0, timeout=120.0):
     # with FP32 rows: 4,096 slots ran out at 0.8 load (p99 of L = 32
     # requests 7.5 ms against 2.6 ms) and 32 expansions per step added
     # about half a millisecond to the median
-    srv = rg.Server(ix, max_slots=6144, hops_per_step=24)
+    srv = rg.Server(ix, max_slots=SERVE_SLOTS, hops_per_step=SERVE_HOPS)
     done = {}
     i = 0
     t0 = srv.now()
@@ -183,8 +184,8 @@ def serve_latency(rg, ix, Qh, gt, n_req=200000):
     serve_run(rg, ix, Qh, gt, 5000, None, seed=3)
     cap = serve_run(rg, ix, Qh, gt, n_req, None, seed=1)
     lam = cap["achieved_qps"]
-    out = {"k_mix": [1, 10, 100], "L_mix": [32, 128, 512], "capacity_qps": lam, "capacity_recall": cap["recall"],
-           "rates": []}
+    out = {"k_mix": [1, 10, 100], "L_mix": [32, 128, 512], "slots": SERVE_SLOTS, "hops_per_step": SERVE_HOPS,
+           "steps_in_flight": 2, "capacity_qps": lam, "capacity_recall": cap["recall"], "rates": []}
     for f in (0.5, 0.8, 0.95):
         r = serve_run(rg, ix, Qh, gt, n_req, f * lam, seed=2)
         r["load"] = f
