@@ -119,6 +119,23 @@ def test_automatic_slot_count(setup):
         rg.Server(ix, max_slots=-1)
 
 
+def test_close_with_work_in_flight(setup):
+    # closing a server while requests are queued and steps are in flight
+    # finishes the admitted work, drops the queued requests and returns
+    dev, X, Q, ix = setup
+    srv = rg.Server(ix, max_slots=64, hops_per_step=4)
+    n = 2000
+    rng = np.random.default_rng(9)
+    ks = rng.choice([1, 10, 100], n).astype(np.int32)
+    Ls = rng.choice([32, 128, 512], n).astype(np.int32)
+    qs = np.stack([Q[i % len(Q)] for i in range(n)]).astype(np.float32)
+    assert srv.submit_batch(qs, ks, Ls, np.arange(n)) == n
+    time.sleep(0.01)
+    t = time.time()
+    srv.close()
+    assert time.time() - t < 30.0
+
+
 def test_pool_too_small_is_rejected(setup):
     dev, X, Q, ix = setup
     with pytest.raises(rg.RGError):
