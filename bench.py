@@ -41,7 +41,7 @@ PAPER_CONTEXT = {
     "roargraph_vs_projected_Text-to-Image": 1.49,
     "knn_share_of_build_time": "87-93% (full training set, CPU)",
 }
-L_GRID = [10, 20, 30, 40, 50, 75, 100, 150, 200, 300, 400, 500]
+L_GRID = [10, 20, 30, 40, 50, 75, 100, 150, 200, 300, 400, 500, 750, 1000]
 SERVE_SLOTS, SERVE_HOPS = 6144, 24  # server slots and expansions per scheduler step
 HBM_PEAK_GBS = 8000.0
 

@@ -240,8 +240,10 @@ int rg_index_set_storage(rg_index *idx, int32_t storage, void *stream);
 /*
  * rg_search -- batched beam search (Sec. 4.3), one query per wavefront.
  *   queries device, nq x d float32.
- *   k       results per query (1..512); L queue length (1..512); the queue
- *           actually kept is L_eff = max(L, k).
+ *   k       results per query (1..1024); L queue length (1..1024); the
+ *           queue actually kept is L_eff = max(L, k).  Queues of up to 512
+ *           entries and longer ones run in separate kernels (the longer
+ *           holding twice the queue entries per lane), with the same rules.
  *   ids     device, nq x k uint32; dists device, nq x k float32 holding
  *           -<q, x_id> in FP32, ascending; when fewer than k nodes are
  *           reachable the tail is 0xFFFFFFFF / +inf.

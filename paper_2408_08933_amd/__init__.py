@@ -293,8 +293,26 @@ def rg_search(index: Index, queries, k, L, stats=False, hash_bits=None, stream=N
     return (ids, ds, hops, ev) if stats else (ids, ds)
 
 
+def _out_buffers(queries, k, ids, ds, hops, ev):
+    """The output tensors must hold what the search writes: nq x k ids
+    (int32) and distances (float32), nq hops and evals (int32)."""
+    import torch
+    queries = _dev_f32(queries, "queries")
+    nq = queries.shape[0]
+    for t, name, dt, n in ((ids, "ids", torch.int32, nq * max(int(k), 0)),
+                           (ds, "dists", torch.float32, nq * max(int(k), 0)),
+                           (hops, "hops", torch.int32, nq), (ev, "evals", torch.int32, nq)):
+        if t is None and name in ("hops", "evals"):
+            continue
+        if not (isinstance(t, torch.Tensor) and t.is_cuda and t.dtype == dt and t.is_contiguous()
+                and t.numel() >= n):
+            raise ValueError(f"{name} must be a contiguous {dt} CUDA tensor of at least {n} elements")
+    return queries
+
+
 def rg_search_into(index: Index, queries, k, L, ids, ds, hops=None, ev=None, stream=None):
     """rg_search writing into preallocated device tensors (no allocation)."""
+    queries = _out_buffers(queries, k, ids, ds, hops, ev)
     _check(lib().rg_search(index.h, _ptr(queries), queries.shape[0], int(k), int(L), _ptr(ids), _ptr(ds),
                            _ptr(hops) if hops is not None else None, _ptr(ev) if ev is not None else None,
                            _stream(stream)))
@@ -302,6 +320,7 @@ def rg_search_into(index: Index, queries, k, L, ids, ds, hops=None, ev=None, str
 
 def rg_search_noalloc_into(index: Index, queries, k, L, ids, ds, hops=None, ev=None, stream=None):
     """The allocation-free search into preallocated device tensors."""
+    queries = _out_buffers(queries, k, ids, ds, hops, ev)
     _check(lib().rg_search_noalloc(index.h, _ptr(queries), queries.shape[0], int(k), int(L), _ptr(ids), _ptr(ds),
                                    _ptr(hops) if hops is not None else None,
                                    _ptr(ev) if ev is not None else None, _stream(stream)))

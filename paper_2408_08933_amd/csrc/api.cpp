@@ -945,9 +945,9 @@ int rg_index_storage_ptrs(const rg_index *ix, const void **bf16, const void **fp
 
 int rg_search(const rg_index *ix, const float *queries, int64_t nq, int32_t k, int32_t L, uint32_t *ids,
               float *dists, uint32_t *hops, uint32_t *evals, void *stream) {
-    if (!ix || nq < 0 || (nq > 0 && (!queries || !ids || !dists)) || k < 1 || L < 1 || k > kMaxL || L > kMaxL ||
-        nq >= (1ll << 31)) {
-        set_error("rg_search: invalid argument (need 1 <= k, L <= 512)");
+    if (!ix || nq < 0 || (nq > 0 && (!queries || !ids || !dists)) || k < 1 || L < 1 || k > kMaxSearchL ||
+        L > kMaxSearchL || nq >= (1ll << 31)) {
+        set_error("rg_search: invalid argument (need 1 <= k, L <= 1024)");
         return RG_EINVAL;
     }
     if (!ix->d_base) {
@@ -1007,9 +1007,9 @@ int rg_search(const rg_index *ix, const float *queries, int64_t nq, int32_t k, i
 
 int rg_search_noalloc(const rg_index *ix, const float *queries, int64_t nq, int32_t k, int32_t L, uint32_t *ids,
                       float *dists, uint32_t *hops, uint32_t *evals, void *stream) {
-    if (!ix || nq < 0 || (nq > 0 && (!queries || !ids || !dists)) || k < 1 || L < 1 || k > kMaxL || L > kMaxL ||
-        nq >= (1ll << 31)) {
-        set_error("rg_search_noalloc: invalid argument (need 1 <= k, L <= 512)");
+    if (!ix || nq < 0 || (nq > 0 && (!queries || !ids || !dists)) || k < 1 || L < 1 || k > kMaxSearchL ||
+        L > kMaxSearchL || nq >= (1ll << 31)) {
+        set_error("rg_search_noalloc: invalid argument (need 1 <= k, L <= 1024)");
         return RG_EINVAL;
     }
     if (!ix->d_base) {
@@ -1051,7 +1051,8 @@ int rg_search_hashbits(const rg_index *ix, const float *queries, int64_t nq, int
         set_error("rg_search_hashbits: hash_bits must be in [8, 15]");
         return RG_EINVAL;
     }
-    if (!ix || nq < 0 || (nq > 0 && (!queries || !ids || !dists)) || k < 1 || L < 1 || k > kMaxL || L > kMaxL) {
+    if (!ix || nq < 0 || (nq > 0 && (!queries || !ids || !dists)) || k < 1 || L < 1 || k > kMaxSearchL ||
+        L > kMaxSearchL) {
         set_error("rg_search_hashbits: invalid argument");
         return RG_EINVAL;
     }

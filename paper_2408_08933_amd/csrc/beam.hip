@@ -311,8 +311,9 @@ struct VisitBitmap {
     __device__ __forceinline__ void added(int) {}
 };
 
-// Expansions until done or `budget` expansions were made.
-template <int ST, int CLS, class VIS>
+// Expansions until done or `budget` expansions were made; the queue holds
+// up to 64 * QR entries.
+template <int ST, int CLS, int QR, class VIS>
 __device__ __forceinline__ void run_search(const SearchArgs &a, const Lds &s, VIS &vis,
                                            int &qn, int &ptr, uint32_t &hops, uint32_t &evals, int budget,
                                            bool &done) {
@@ -373,9 +374,9 @@ __device__ __forceinline__ void run_search(const SearchArgs &a, const Lds &s, VI
             __syncthreads();
             const QueueLds<float> ql{s.qd, s.qi, s.cd, s.ci, s.sd, s.si, s.slb};
             if (nnew <= 64)
-                merge_batch<1, float>(ql, nnew, Leff, qn, ptr);
+                merge_batch<1, float, QR>(ql, nnew, Leff, qn, ptr);
             else
-                merge_batch<2, float>(ql, nnew, Leff, qn, ptr);
+                merge_batch<2, float, QR>(ql, nnew, Leff, qn, ptr);
             __syncthreads();
         }
     }
@@ -407,13 +408,14 @@ __device__ __forceinline__ void init_state(const SearchArgs &a, const Lds &s, VI
     __syncthreads();
 }
 
-// Rescore the final queue against FP32 rows and sort it (reduced-precision storage).
-template <int CLS>
+// Rescore the final queue (at most 64 * QR entries) against FP32 rows and
+// sort it (reduced-precision storage).
+template <int CLS, int QR>
 __device__ __forceinline__ void rerank_queue(const SearchArgs &a, const Lds &s, int qn) {
     constexpr int G = shape_g(RG_STORE_FP32, CLS), NCH = shape_nch(RG_STORE_FP32, CLS);
     score_batch<RG_STORE_FP32, G, NCH, 2>(a, s.qs, (a.d + 3) >> 2, s.qi, ~kExpanded, s.qd, qn);
     __syncthreads();
-    constexpr int E = kMaxL / 64;
+    constexpr int E = QR;
     const int lane = lane_id();
     float k[E];
     uint32_t id[E];
@@ -486,9 +488,12 @@ __device__ __forceinline__ void write_result(const SearchArgs &a, const Lds &s, 
 // on memory latency more than on bandwidth; six or more spill.  FP32 rows
 // (more chunks in flight per row) take four, which keeps them out of
 // scratch: 4.6% faster on a 10M-row graph.
-template <int ST, int CLS>
-__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(ST == RG_STORE_FP32 ? 4 : 5))) void k_search(
-    SearchArgs a) {
+// QR = queue capacity / 64: kMaxL / 64, or kMaxSearchL / 64 for L_eff above
+// kMaxL, where twice the queue entries per lane in the merge and the rerank
+// take four resident wavefronts per SIMD for every storage form.
+template <int ST, int CLS, int QR>
+__global__ __launch_bounds__(64)
+__attribute__((amdgpu_waves_per_eu(ST == RG_STORE_FP32 || QR > kMaxL / 64 ? 4 : 5))) void k_search(SearchArgs a) {
     extern __shared__ __align__(16) unsigned char smem[];
     const int64_t q = blockIdx.x;
     const Lds s = carve(smem, a.Leff, a.qpad, a.cand);
@@ -498,8 +503,8 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(ST == RG_STO
     uint32_t hops, evals;
     bool done;
     init_state<ST, CLS>(a, s, vis, qn, ptr, hops, evals);
-    run_search<ST, CLS>(a, s, vis, qn, ptr, hops, evals, INT_MAX, done);
-    if constexpr (ST != RG_STORE_FP32) rerank_queue<CLS>(a, s, qn);
+    run_search<ST, CLS, QR>(a, s, vis, qn, ptr, hops, evals, INT_MAX, done);
+    if constexpr (ST != RG_STORE_FP32) rerank_queue<CLS, QR>(a, s, qn);
     write_result(a, s, q, qn, hops, evals);
 }
 
@@ -509,7 +514,8 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(ST == RG_STO
 // the candidate batch and many more queries are in flight per CU.
 // Four resident wavefronts per SIMD (<= 128 VGPRs) measured fastest for all
 // storage forms, ahead of fewer waves with more registers.
-template <int ST, int CLS>
+// QR as for k_search.
+template <int ST, int CLS, int QR>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void k_search_persistent(SearchArgs a) {
     extern __shared__ __align__(16) unsigned char smem[];
     const Lds s = carve(smem, a.Leff, a.qpad, a.cand);
@@ -525,8 +531,8 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void k_
         uint32_t hops, evals;
         bool done;
         init_state<ST, CLS>(a, s, vis, qn, ptr, hops, evals);
-        run_search<ST, CLS>(a, s, vis, qn, ptr, hops, evals, INT_MAX, done);
-        if constexpr (ST != RG_STORE_FP32) rerank_queue<CLS>(a, s, qn);
+        run_search<ST, CLS, QR>(a, s, vis, qn, ptr, hops, evals, INT_MAX, done);
+        if constexpr (ST != RG_STORE_FP32) rerank_queue<CLS, QR>(a, s, qn);
         write_result(a, s, q, qn, hops, evals);
         __syncthreads();
     }
@@ -573,9 +579,9 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(5))) void k_
         __syncthreads();
     }
     bool done;
-    run_search<ST, CLS>(a, s, vis, qn, ptr, hops, evals, sa.hops_budget, done);
+    run_search<ST, CLS, kMaxL / 64>(a, s, vis, qn, ptr, hops, evals, sa.hops_budget, done);
     if (done) {
-        if constexpr (ST != RG_STORE_FP32) rerank_queue<CLS>(a, s, qn);
+        if constexpr (ST != RG_STORE_FP32) rerank_queue<CLS, kMaxL / 64>(a, s, qn);
         int pos = 0;
         if (lane == 0) pos = (int)atomicAdd(sa.out_count, 1u);
         pos = __shfl(pos, 0);
@@ -617,10 +623,23 @@ __global__ __launch_bounds__(64) void k_serve_admit(int32_t n, const int32_t *sl
     }
 }
 
+// The kernels for a queue of L_eff entries: kMaxL or fewer, or up to kMaxSearchL.
+template <int ST, int CLS>
+void (*table_kernel(int Leff))(SearchArgs) {
+    return Leff > kMaxL ? k_search<ST, CLS, kMaxSearchL / 64> : k_search<ST, CLS, kMaxL / 64>;
+}
+template <int ST, int CLS>
+void (*persistent_kernel(int Leff))(SearchArgs) {
+    return Leff > kMaxL ? k_search_persistent<ST, CLS, kMaxSearchL / 64> : k_search_persistent<ST, CLS, kMaxL / 64>;
+}
+
 template <int ST, int CLS>
 int launch_one(const SearchArgs &a, hipStream_t stream) {
     const size_t lds = search_lds_bytes(a.Leff, a.qpad, a.hash_bits, a.cand);
-    hipLaunchKernelGGL((k_search<ST, CLS>), dim3((unsigned)a.nq), dim3(64), lds, stream, a);
+    if (a.Leff > kMaxL)
+        hipLaunchKernelGGL((k_search<ST, CLS, kMaxSearchL / 64>), dim3((unsigned)a.nq), dim3(64), lds, stream, a);
+    else
+        hipLaunchKernelGGL((k_search<ST, CLS, kMaxL / 64>), dim3((unsigned)a.nq), dim3(64), lds, stream, a);
     RG_HIP(hipGetLastError());
     return RG_OK;
 }
@@ -628,7 +647,12 @@ int launch_one(const SearchArgs &a, hipStream_t stream) {
 template <int ST, int CLS>
 int launch_persistent(const SearchArgs &a, hipStream_t stream) {
     const size_t lds = search_lds_bytes(a.Leff, a.qpad, 0, a.cand);
-    hipLaunchKernelGGL((k_search_persistent<ST, CLS>), dim3((unsigned)a.grid), dim3(64), lds, stream, a);
+    if (a.Leff > kMaxL)
+        hipLaunchKernelGGL((k_search_persistent<ST, CLS, kMaxSearchL / 64>), dim3((unsigned)a.grid), dim3(64), lds,
+                           stream, a);
+    else
+        hipLaunchKernelGGL((k_search_persistent<ST, CLS, kMaxL / 64>), dim3((unsigned)a.grid), dim3(64), lds, stream,
+                           a);
     RG_HIP(hipGetLastError());
     return RG_OK;
 }
@@ -636,7 +660,7 @@ int launch_persistent(const SearchArgs &a, hipStream_t stream) {
 template <int ST, int CLS>
 int occupancy_of(int Leff, int pitch, int cand, int *blocks_per_cu) {
     const size_t lds = search_lds_bytes(Leff, pitch, 0, cand);
-    RG_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k_search_persistent<ST, CLS>, 64, lds));
+    RG_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, persistent_kernel<ST, CLS>(Leff), 64, lds));
     return RG_OK;
 }
 
@@ -673,7 +697,7 @@ template <int ST, int CLS>
 struct TableOcc {
     static int run(const SearchArgs &a, hipStream_t) {
         const size_t lds = search_lds_bytes(a.Leff, a.qpad, a.hash_bits, a.cand);
-        RG_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(a.occ_out, k_search<ST, CLS>, 64, lds));
+        RG_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(a.occ_out, table_kernel<ST, CLS>(a.Leff), 64, lds));
         return RG_OK;
     }
 };

@@ -57,7 +57,8 @@ __device__ __forceinline__ int count_le(const int32_t *slb, int S, int i) {
 // survivors ahead of each one instead of sorting the whole batch.
 constexpr int kRankByCount = 32;
 
-template <int E, typename K>
+// QR = queue capacity / 64: each lane holds QR of the entries that move.
+template <int E, typename K, int QR = kMaxL / 64>
 __device__ __forceinline__ void merge_batch(const QueueLds<K> &s, int cnt, int Leff, int &qn, int &ptr) {
     const int lane = lane_id();
     const bool full = qn == Leff;
@@ -155,7 +156,7 @@ __device__ __forceinline__ void merge_batch(const QueueLds<K> &s, int cnt, int L
     }
     const int lbmin = s.slb[0];
     // entries of the queue that move, and their new places
-    constexpr int R = kMaxL / 64;
+    constexpr int R = QR;
     K md[R];
     uint32_t mi[R];
     int mp[R];

@@ -14,7 +14,8 @@ namespace rg {
 
 constexpr uint32_t kNone = 0xFFFFFFFFu;
 constexpr uint32_t kExpanded = 0x80000000u;  // queue-entry flag (ids < 2^31)
-constexpr int kMaxL = 512;                    // largest queue the search kernel holds
+constexpr int kMaxL = 512;                    // largest queue of the serving and construction searches
+constexpr int kMaxSearchL = 1024;            // largest queue of rg_search (L_eff above kMaxL: long-queue kernels)
 constexpr int kMaxEll = 128;                  // widest ELL row; wider graphs are searched as CSR
 
 void set_error(const std::string &msg);

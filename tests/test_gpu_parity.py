@@ -302,9 +302,50 @@ def test_search_special_graphs(dev, oracle_lib):
 
 def test_search_rejects_bad_args(dev, c1_index):
     q = torch.zeros((2, 64), device=dev)
-    for k, L in ((0, 10), (10, 0), (513, 10), (10, 513)):
+    for k, L in ((0, 10), (10, 0), (1025, 10), (10, 1025)):
         with pytest.raises(rg.RGError):
             rg.rg_search(c1_index, q, k, L)
+
+
+# Queues longer than 512 entries run in the long-queue kernels (twice the
+# queue entries per lane in the merge and the rerank).  Both visited sets
+# (the persistent kernel's exact bitmap, the LDS table) against the oracle,
+# for every storage form, at L just above 512, at the 1024 maximum, and
+# with k above 512; the two kernels return the same results.
+@pytest.mark.parametrize("storage", ["fp32", "bf16", "fp8"])
+def test_long_queue_parity(dev, oracle_lib, c1, storage):
+    X, Tr, Q, G = c1
+    Qs = Q[:150]
+    ix = rg.rg_index_from_csr(T(X, dev), G.offsets, G.indices, G.entry)
+    Xq = None
+    if storage != "fp32":
+        rg.rg_index_set_storage(ix, rg.RG_STORE_BF16 if storage == "bf16" else rg.RG_STORE_FP8E4M3)
+        Xq = oracle_lib.bf16(X) if storage == "bf16" else oracle_lib.quant_fp8(X)[2]
+    nq = Qs.shape[0]
+    for k, L in ((10, 513), (10, 1024), (700, 600), (1024, 1)):
+        say(f"long queue {storage} k={k} L={L}")
+        # exact bitmap: the persistent kernel
+        ids = torch.empty((nq, k), dtype=torch.int32, device=dev)
+        ds = torch.empty((nq, k), dtype=torch.float32, device=dev)
+        hops = torch.empty(nq, dtype=torch.int32, device=dev)
+        ev = torch.empty(nq, dtype=torch.int32, device=dev)
+        rg.rg_search_noalloc_into(ix, T(Qs, dev), k, L, ids, ds, hops, ev)
+        # LDS table of 2^10 entries: the table kernel, which forgets and rescores
+        tids, tds = rg.rg_search(ix, T(Qs, dev), k, L, hash_bits=10)
+        torch.cuda.synchronize()
+        assert torch.equal(ids, tids) and torch.equal(ds, tds), f"{storage} k={k} L={L}: kernels differ"
+        if Xq is None:
+            oi, od, oh, oe, gaps = oracle_lib.search(X, G.offsets, G.indices, G.entry, Qs, k, L)
+            r = compare(rg.as_u32(ids), ds.cpu().numpy(), oi, od, gaps, Qs, X, label=f"fp32 k={k} L={L}",
+                        gpu_evals=ev.cpu().numpy(), or_evals=oe, exact_visits=True,
+                        explain=oracle_explainer(oracle_lib, X, G.offsets, G.indices, G.entry, Qs, k, L))
+            sure = gaps > r["gamma"]
+            assert np.array_equal(hops.cpu().numpy()[sure], oh[sure].astype(np.int64))
+        else:
+            oi, od, _, _, gaps = oracle_lib.search_rerank(Xq, X, G.offsets, G.indices, G.entry, Qs, k, L)
+            compare(rg.as_u32(ids), ds.cpu().numpy(), oi, od, gaps, Qs, X, label=f"{storage} k={k} L={L}",
+                    storage=storage,
+                    explain=oracle_explainer(oracle_lib, X, G.offsets, G.indices, G.entry, Qs, k, L, Xq=Xq))
 
 
 # ---------------------------------------------------------------------------

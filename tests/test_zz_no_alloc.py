@@ -65,8 +65,13 @@ def test_noalloc_equals_search_two_calls(setup, storage):
 
 def test_noalloc_rejects_bad_arguments(setup):
     dev, ix, Q = setup
-    ids = torch.empty((4, 10), dtype=torch.int32, device=dev)
-    ds = torch.empty((4, 10), dtype=torch.float32, device=dev)
-    for k, L in ((0, 10), (10, 0), (513, 10)):
+    for k, L in ((0, 10), (10, 0), (1025, 10), (10, 1025)):
+        ids = torch.empty((4, max(k, 1)), dtype=torch.int32, device=dev)
+        ds = torch.empty((4, max(k, 1)), dtype=torch.float32, device=dev)
         with pytest.raises(rg.RGError):
             rg.rg_search_noalloc_into(ix, Q[:4], k, L, ids, ds)
+    # output buffers smaller than nq x k are refused before any launch
+    ids = torch.empty((4, 10), dtype=torch.int32, device=dev)
+    ds = torch.empty((4, 10), dtype=torch.float32, device=dev)
+    with pytest.raises(ValueError):
+        rg.rg_search_noalloc_into(ix, Q[:4], 11, 10, ids, ds)
