@@ -1,6 +1,7 @@
 """Host logic of bench.py (CPU): the roofline's measured traffic is used
 only for the kernel sources and the operating point the counters were
-taken on, and recall@k is the plain set definition."""
+taken on, recall@k is the plain set definition, and the operating point is
+the smallest swept L whose recall reaches the target."""
 import importlib.util
 import os
 import shutil
@@ -55,3 +56,33 @@ def test_recall_definition():
     # row 0: {1,2,3} vs {3,2,9} -> 2 of 3; row 1: {4,5,6} vs {7,8,9} -> 0
     assert abs(b.recall_at(ids, gt, 3) - 2 / 6) < 1e-12
     assert abs(b.recall_at(ids, gt, 1) - 0.0) < 1e-12
+
+
+def test_sweep_takes_the_smallest_L_that_reaches_the_target(monkeypatch):
+    b = _bench()
+
+    class FakeLib:
+        @staticmethod
+        def rg_search(ix, Q, k, L):
+            return L, None       # the "ids" carry L to the recall stand-in below
+
+        @staticmethod
+        def as_u32(x):
+            return x
+
+    class FakeTorch:
+        class cuda:
+            @staticmethod
+            def synchronize():
+                pass
+
+    # recall rises with L and first reaches 0.90 at L = 805, between the
+    # grid's 750 and 1000
+    monkeypatch.setattr(b, "recall_at", lambda L, gt, k: 0.90 if L >= 805 else 0.90 * L / 805)
+    L, curve = b.sweep(FakeLib, FakeTorch, None, None, None, 10, b.L_GRID, 0.90)
+    got = dict(curve)
+    assert L == 805 and got[805] >= 0.90 and got[804] < 0.90
+    assert b.L_GRID[-1] <= 1024      # the longest queue rg_search takes
+    # never reached: no operating point
+    monkeypatch.setattr(b, "recall_at", lambda L, gt, k: 0.5)
+    assert b.sweep(FakeLib, FakeTorch, None, None, None, 10, b.L_GRID, 0.90)[0] is None
