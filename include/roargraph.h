@@ -257,9 +257,10 @@ int rg_index_set_storage(rg_index *idx, int32_t storage, void *stream);
  * exact visited bitmap per resident query in device memory while n/8 bytes
  * stay below 5% of a query's expected row bytes (40 L_eff rows of 4d
  * bytes) or the graph is held as CSR (rows over 128 ids);
- * otherwise, and for BF16 / FP8, a visited table in LDS of 2^10 entries
- * (2^9 when the smaller table lets more workgroups share a CU) that forgets
- * and rescores (the results are the same; evals counts the rescoring).
+ * otherwise, and for BF16 / FP8, a visited table in LDS that forgets and
+ * rescores (the results are the same; evals counts the rescoring): the
+ * largest of 2^10, 2^9 and 2^8 entries that lets the most workgroups share
+ * a CU (2^8 only while it holds twice a row batch).
  * Asynchronous on stream.
  * Errors: RG_EINVAL, RG_EDEVICE.
  */

@@ -132,18 +132,29 @@ int upload_adj(rg_index *ix, hipStream_t st) {
     return RG_OK;
 }
 
-// Visited table of the LDS-table search: 2^10 ids, or 2^9 when the smaller
-// table lets more workgroups share a CU.  Measured on 10M x 200 at
-// L = 417: E4M3 rows 14.1 -> 11.6 ms and BF16 18.3 -> 17.8 ms per 10k
-// queries (16 -> 20 workgroups per CU) for 0.8% more rows scored; FP32
-// rows are held to 16 workgroups per CU by registers and keep 2^10.
+// Visited table of the LDS-table search: the largest of 2^10, 2^9 and 2^8
+// ids that lets the most workgroups share a CU (2^8 only while it holds
+// twice a row batch, as rg_search_hashbits requires).  The table only
+// bounds work; a smaller one forgets and rescores a little more.  Measured
+// per 10k queries: on 10M x 200 at L = 417, E4M3 rows 14.1 -> 11.6 ms and
+// BF16 18.3 -> 17.8 ms with 2^9 (16 -> 20 workgroups per CU) for 0.8% more
+// rows scored; on 8M x 512 at L = 803, E4M3 80.5 -> 66.5 ms and BF16 70.2
+// -> 65.7 ms with 2^8 (13 -> 15) for 0.7% more.  FP32 rows on 10M x 200 are
+// held to 16 workgroups per CU by registers and keep 2^10.
 int table_bits(SearchArgs a) {
-    int o9 = 0, o10 = 0;
-    a.hash_bits = 9;
-    if (table_search_occupancy(a, &o9)) return 10;
-    a.hash_bits = 10;
-    if (table_search_occupancy(a, &o10)) return 10;
-    return o10 >= o9 ? 10 : 9;
+    const int width = a.adj_off ? kMaxEll : a.ell;  // ids inserted per batch
+    int best = 10, occ = -1;
+    for (int hb = 10; hb >= 8; --hb) {
+        if ((1 << hb) < 2 * width + 2) break;
+        int o = 0;
+        a.hash_bits = hb;
+        if (table_search_occupancy(a, &o)) return best;
+        if (o > occ) {
+            occ = o;
+            best = hb;
+        }
+    }
+    return best;
 }
 
 // Search parameters common to every search entry point.

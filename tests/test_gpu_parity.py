@@ -330,10 +330,20 @@ def test_long_queue_parity(dev, oracle_lib, c1, storage):
         hops = torch.empty(nq, dtype=torch.int32, device=dev)
         ev = torch.empty(nq, dtype=torch.int32, device=dev)
         rg.rg_search_noalloc_into(ix, T(Qs, dev), k, L, ids, ds, hops, ev)
-        # LDS table of 2^10 entries: the table kernel, which forgets and rescores
-        tids, tds = rg.rg_search(ix, T(Qs, dev), k, L, hash_bits=10)
+        # LDS tables of 2^8..2^10 entries: the table kernel, which forgets and
+        # rescores; rg_search's own choice (for FP32 on this small graph, the
+        # bitmap) returns the same results
+        evs = {}
+        for hb in (8, 9, 10):
+            tids, tds, _, tev = rg.rg_search(ix, T(Qs, dev), k, L, stats=True, hash_bits=hb)
+            torch.cuda.synchronize()
+            assert torch.equal(ids, tids) and torch.equal(ds, tds), f"{storage} k={k} L={L} 2^{hb}: kernels differ"
+            evs[hb] = tev
+        dids, dds, _, d_ev = rg.rg_search(ix, T(Qs, dev), k, L, stats=True)
         torch.cuda.synchronize()
-        assert torch.equal(ids, tids) and torch.equal(ds, tds), f"{storage} k={k} L={L}: kernels differ"
+        assert torch.equal(ids, dids) and torch.equal(ds, dds), f"{storage} k={k} L={L}: default differs"
+        if storage != "fp32":   # the LDS table, at one of the three sizes
+            assert any(torch.equal(d_ev, e) for e in evs.values())
         if Xq is None:
             oi, od, oh, oe, gaps = oracle_lib.search(X, G.offsets, G.indices, G.entry, Qs, k, L)
             r = compare(rg.as_u32(ids), ds.cpu().numpy(), oi, od, gaps, Qs, X, label=f"fp32 k={k} L={L}",
