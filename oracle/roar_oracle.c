@@ -25,9 +25,9 @@
  *     reachability repair.
  *
  * Parity pins live in tests/test_oracle.py.  Projection and enhancement
- * beyond the hand-worked five-point build and the invariants checked there
- * are "parity unpinned" against the paper itself: its worked examples are
- * figures whose coordinates are not given.
+ * beyond the hand-worked five- and six-point builds and the invariants
+ * checked there are "parity unpinned" against the paper itself: its worked
+ * examples are figures whose coordinates are not given.
  */
 #define _POSIX_C_SOURCE 200809L
 #include <pthread.h>

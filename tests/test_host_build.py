@@ -47,6 +47,21 @@ def test_hand_worked_five_points(oracle_lib):
     assert entry == g["entry"]
 
 
+def test_hand_worked_six_points(oracle_lib):
+    import json, math
+    g0 = json.load(open(os.path.join(ROOT, "tests", "golden", "enhancement_6pt.json")))
+    u = lambda a: [math.cos(math.radians(a)), math.sin(math.radians(a))]
+    for g in (g0, dict(g0, **g0["variant_p5_235"])):
+        X = np.array([u(a) for a in g["base_angles_deg"]], np.float32)
+        T = np.array([u(a) for a in g["train_angles_deg"]], np.float32)
+        knn, _ = oracle_lib.knn(X, T, g["Nq"])
+        ix = rg.rg_build_from_knn(X, knn, g["Nq"], g["M"], L_build=g["L"], keep_stages=True)
+        off, idx, entry = ix.graph()
+        assert [idx[off[i]:off[i + 1]].tolist() for i in range(len(X))] == g["final_rows"]
+        assert entry == g["entry"]
+        assert ix.build_stats()["repairs"] == g["repairs"]
+
+
 @pytest.mark.parametrize("cfg,n,Nq,M,L", [(1, 1200, 16, 16, 100), (1, 3000, 32, 32, 200), (2, 1500, 24, 20, 120)])
 def test_library_graph_bit_exact_with_oracle(oracle_lib, cfg, n, Nq, M, L):
     gen = datagen.Generator(cfg, n=n, n_train=n, n_test=10, d=48 if cfg == 2 else None)

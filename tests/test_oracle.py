@@ -158,6 +158,24 @@ def test_build_hand_worked_five_points(oracle_lib):
     assert list(G.pivot) == [0, 3]
 
 
+def test_enhancement_hand_worked_six_points(oracle_lib):
+    # two enhancement edges per node and a queue of 3: truncated searches,
+    # occlusion without fill, reverse updates that re-prune copied rows
+    # (the variant moves P5 so that its own selection drops a candidate)
+    g0 = json.load(open(os.path.join(GOLDEN, "enhancement_6pt.json")))
+    for g in (g0, dict(g0, **g0["variant_p5_235"])):
+        X = np.array([unit2(a) for a in g["base_angles_deg"]], np.float32)
+        T = np.array([unit2(a) for a in g["train_angles_deg"]], np.float32)
+        G = oracle_lib.Graph(X, T, g["Nq"], g["M"], g["L"])
+        assert G.pivot.tolist() == g0["pivot"]
+        assert [sorted(r.tolist()) for r in G.rows("pj")] == g["pj_rows"]
+        assert G.entry == g["entry"]
+        assert [G.cx[x, :G.cx_n[x]].tolist() for x in range(len(X))] == g["enhancement_candidates"]
+        assert [sorted(r.tolist()) for r in G.rows("ce")] == g["ce_rows"]
+        assert [r.tolist() for r in G.rows("final")] == g["final_rows"]
+        assert G.repairs == g["repairs"]
+
+
 def test_projection_cutoff_hand_worked(oracle_lib):
     # overlapping bridge lists beyond L: distinct count before each list,
     # rank by distance to the pivot, truncate to L (Algorithm 2)
