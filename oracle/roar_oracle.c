@@ -25,7 +25,7 @@
  *     reachability repair.
  *
  * Parity pins live in tests/test_oracle.py.  Projection and enhancement
- * beyond the hand-worked five- and six-point builds and the invariants
+ * beyond the hand-worked builds in tests/golden and the invariants
  * checked there are "parity unpinned" against the paper itself: its worked
  * examples are figures whose coordinates are not given.
  */

@@ -62,6 +62,21 @@ def test_hand_worked_six_points(oracle_lib):
         assert ix.build_stats()["repairs"] == g["repairs"]
 
 
+def test_hand_worked_reverse_update(oracle_lib):
+    import json, math
+    g = json.load(open(os.path.join(ROOT, "tests", "golden", "enhancement_reverse.json")))
+    u = lambda a: [math.cos(math.radians(a)), math.sin(math.radians(a))]
+    b = g["base"]
+    X = np.array([[r * c for c in u(a)] for a, r in zip(b["angles_deg"], b["norms"])], np.float32)
+    T = np.array([u(a) for a in g["train_angles_deg"]], np.float32)
+    knn, _ = oracle_lib.knn(X, T, g["Nq"])
+    ix = rg.rg_build_from_knn(X, knn, g["Nq"], g["M"], L_build=g["L"])
+    off, idx, entry = ix.graph()
+    assert [idx[off[i]:off[i + 1]].tolist() for i in range(len(X))] == g["final_rows"]
+    assert entry == g["entry"]
+    assert ix.build_stats()["repairs"] == g["repairs"]
+
+
 @pytest.mark.parametrize("cfg,n,Nq,M,L", [(1, 1200, 16, 16, 100), (1, 3000, 32, 32, 200), (2, 1500, 24, 20, 120)])
 def test_library_graph_bit_exact_with_oracle(oracle_lib, cfg, n, Nq, M, L):
     gen = datagen.Generator(cfg, n=n, n_train=n, n_test=10, d=48 if cfg == 2 else None)

@@ -176,6 +176,23 @@ def test_enhancement_hand_worked_six_points(oracle_lib):
         assert G.repairs == g["repairs"]
 
 
+def test_enhancement_reverse_update_hand_worked(oracle_lib):
+    # a half-norm node no search reaches, processed last: its reverse update
+    # into a row with room drops it (AcquireNeighbors without fill)
+    g = json.load(open(os.path.join(GOLDEN, "enhancement_reverse.json")))
+    b = g["base"]
+    X = np.array([[r * c for c in unit2(a)] for a, r in zip(b["angles_deg"], b["norms"])], np.float32)
+    T = np.array([unit2(a) for a in g["train_angles_deg"]], np.float32)
+    G = oracle_lib.Graph(X, T, g["Nq"], g["M"], g["L"])
+    assert G.pivot.tolist() == g["pivot"]
+    assert [sorted(r.tolist()) for r in G.rows("pj")] == g["pj_rows"]
+    assert G.entry == g["entry"]
+    assert [G.cx[x, :G.cx_n[x]].tolist() for x in range(len(X))] == g["enhancement_candidates"]
+    assert [sorted(r.tolist()) for r in G.rows("ce")] == g["ce_rows"]
+    assert [r.tolist() for r in G.rows("final")] == g["final_rows"]
+    assert G.repairs == g["repairs"]
+
+
 def test_projection_cutoff_hand_worked(oracle_lib):
     # overlapping bridge lists beyond L: distinct count before each list,
     # rank by distance to the pivot, truncate to L (Algorithm 2)
